@@ -1,0 +1,434 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms, exact invariants, brute-force sums on tiny inputs
+or synthetic ground truth.  ``test_planted_mistakes`` plants plausible errors
+in the oracle (on the CPU) and checks that at least one pin catches each.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ssoct_oracle as O
+from paper_2003_08960_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Printed values (text after Eq. 3, caption of Fig. 2)
+# --------------------------------------------------------------------------
+
+def check_printed_axial():
+    g = _golden()
+    e = g["twice_axial_pitch_um"]
+    lam1, lam2 = e["lam1_nm"] * 1e-9, e["lam2_nm"] * 1e-9
+    assert abs(O.twice_axial_pitch(lam1, lam2) * 1e6 - e["value"]) <= e["printed_digits"]
+    e = g["coherence_length_um"]
+    assert abs(O.coherence_length(lam1, lam2) * 1e6 - e["value"]) <= e["printed_digits"]
+    e = g["axial_range_mm"]
+    nz = g["n_z"]["value"]
+    for dl, printed in e["cases"]:
+        l1 = (e["centre_nm"] + dl / 2) * 1e-9
+        l2 = (e["centre_nm"] - dl / 2) * 1e-9
+        assert abs(O.axial_range(l1, l2, nz) * 1e3 - printed) <= e["printed_digits"]
+
+
+def test_printed_axial_values():
+    check_printed_axial()
+
+
+def test_depth_of_bin_matches_eq3():
+    """Bin pitch of the depth DFT is Lambda/2 (Eq. 3) when the k step is Delta k / T."""
+    lam1, lam2, T = 870e-9, 820e-9, 256
+    lam = synth.sweep_wavelengths(T, lam1, lam2)
+    pitch = O.depth_of_bin(1, lam)
+    # endpoints inclusive: dk = Delta k / (T - 1)  =>  pitch = (Lambda/2)(T-1)/T
+    assert pitch * T / (T - 1) == pytest.approx(O.twice_axial_pitch(lam1, lam2) / 2, rel=1e-12)
+    assert O.depth_of_bin(T - 1, lam) == pytest.approx(-pitch, rel=1e-12)
+
+
+def test_eq4_reconstructed_pitch_and_zb():
+    assert O.reconstructed_pitch(870e-9, 0.3, 128, 20e-6) == pytest.approx(870e-9 * 0.3 / (128 * 20e-6))
+    zb = O.boundary_distance(1024, 12e-6, 870e-9)
+    assert zb == pytest.approx(0.16949, rel=1e-4)   # paper camera: z = 0.3 m is above z_b
+
+
+# --------------------------------------------------------------------------
+# Step 1: rescale (Eq. 5)
+# --------------------------------------------------------------------------
+
+def check_rescale():
+    rng = np.random.default_rng(5)
+    N = 32
+    I = rng.integers(0, 65536, size=(N, N)).astype(np.uint16)
+    # s = 1: every sample falls on its own pixel
+    assert np.array_equal(O.rescale(I, 1.0), I.astype(np.float64))
+    # a constant frame stays constant
+    assert np.allclose(O.rescale(np.full((N, N), 777, np.uint16), 0.9), 777.0, rtol=0, atol=1e-9)
+    # a bilinear ramp a + b x + e y is reproduced exactly at the scaled positions
+    m, n = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    ramp = 100.0 + 3.0 * n + 7.0 * m
+    for s in (0.92, 0.8137, 0.5):
+        J = O.rescale(ramp, s)
+        c = np.arange(N) - N // 2
+        X = N // 2 + c * s
+        expect = 100.0 + 3.0 * X[None, :] + 7.0 * X[:, None]
+        assert np.allclose(J, expect, rtol=0, atol=1e-9)
+
+
+def test_rescale_pins():
+    check_rescale()
+
+
+# --------------------------------------------------------------------------
+# Step 2: Fresnel transform (Eq. 6)
+# --------------------------------------------------------------------------
+
+def check_fresnel_closed_forms():
+    N = 16
+    c = np.arange(N) - N // 2
+    # impulse at (m0, n0): h[u, v] = exp(+2 pi i (c_u c_m0 + c_v c_n0) / N)
+    x = np.zeros((N, N), complex)
+    x[3, 11] = 1.0
+    h = O.fresnel_fft(x)
+    expect = np.exp(2j * np.pi * (c[:, None] * c[3] + c[None, :] * c[11]) / N)
+    assert np.allclose(h, expect, atol=1e-12)
+    # plane wave exp(-2 pi i (a c_m + b c_n)/N) focuses to N^2 at (c_u, c_v) = (a, b)
+    a, b = 3, -5
+    x = np.exp(-2j * np.pi * (a * c[:, None] + b * c[None, :]) / N)
+    h = O.fresnel_fft(x)
+    k = np.unravel_index(np.argmax(np.abs(h)), h.shape)
+    assert (c[k[0]], c[k[1]]) == (a, b)
+    assert abs(h[k]) == pytest.approx(N * N)
+    h[k] = 0
+    assert np.max(np.abs(h)) < 1e-9
+
+
+def test_fresnel_closed_forms():
+    check_fresnel_closed_forms()
+
+
+def test_fresnel_brute_force():
+    """Direct double sum of Eq. 6 (with the centring and + sign) on 8x8 and 16x16."""
+    rng = np.random.default_rng(7)
+    for N in (8, 16):
+        x = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+        h = O.fresnel_fft(x)
+        hb = np.zeros((N, N), complex)
+        for u in range(N):
+            for v in range(N):
+                acc = 0j
+                for m in range(N):
+                    for n in range(N):
+                        acc += x[m, n] * complex(np.exp(2j * np.pi * ((u - N // 2) * (m - N // 2)
+                                                                      + (v - N // 2) * (n - N // 2)) / N))
+                hb[u, v] = acc
+        assert np.allclose(h, hb, rtol=0, atol=1e-9 * np.abs(hb).max())
+
+
+def check_point_source_focus():
+    """A spherical wave exp(+i pi |r' - r0|^2 / (lambda z)) focuses at c = r0 / d' (Eq. 4, 6)."""
+    N, d, z, lam = 64, 20e-6, 0.1, 800e-9
+    dprime = O.reconstructed_pitch(lam, z, N, d)
+    c = np.arange(N) - N // 2
+    xs = c * d
+    for (cy, cx) in ((5, -9), (0, 0), (-13, 7)):
+        y0, x0 = cy * dprime, cx * dprime
+        field = np.exp(1j * np.pi * ((xs[:, None] - y0) ** 2 + (xs[None, :] - x0) ** 2) / (lam * z))
+        frames = np.zeros((1, N, N))
+        # drive the oracle through its own chirp by passing the field as the "rescaled" frame
+        alpha = O.chirp_rates([lam], d, z)[0]
+        h = O.fresnel_fft(O.chirp(N, alpha) * field)
+        k = np.unravel_index(np.argmax(np.abs(h)), h.shape)
+        assert (c[k[0]], c[k[1]]) == (cy, cx)
+        del frames
+
+
+def test_point_source_focus():
+    check_point_source_focus()
+
+
+def test_pitch_equalisation():
+    check_pitch_equalisation()
+
+
+def check_pitch_equalisation():
+    """Eq. 4 + Eq. 5: with the rescale, two points dx apart are dx/d'(lambda_1) pixels apart at
+    every wavelength; without it (single-frame sweep, s = 1) they are dx N d/(lambda_t z) apart."""
+    N, d, z = 128, 20e-6, 0.3
+    lam1, lamt = 870e-9, 800e-9
+    dp1 = O.reconstructed_pitch(lam1, z, N, d)
+    sep_px = 24.0
+    dx = sep_px * dp1
+    c = np.arange(N) - N // 2
+    xs = c * d
+    fc = 1.0 / (8 * d)
+
+    def hologram(lt):
+        ref = np.exp(2j * np.pi * fc * lam1 / lt * xs)
+        Elo = np.outer(ref, ref)
+        E = np.zeros((N, N), complex)
+        for x0 in (-dx / 2, dx / 2):
+            E += 0.2 * np.exp(1j * np.pi * ((xs[:, None]) ** 2 + (xs[None, :] - x0) ** 2) / (lt * z))
+        return np.abs(Elo + E) ** 2
+
+    def centroids(V):
+        M = np.abs(V[0]) ** 2
+        row = M[N // 2 + N // 8]
+        # two peaks around the +1 order; centroid of each
+        cols = np.arange(N)
+        left = (cols > N // 2) & (cols < N // 2 + N // 8)
+        right = (cols >= N // 2 + N // 8) & (cols < N)
+        pk = []
+        for msk in (left, right):
+            w = np.where(msk, row, 0.0)
+            i = int(np.argmax(w))
+            win = slice(i - 2, i + 3)
+            pk.append(np.sum(cols[win] * row[win]) / np.sum(row[win]))
+        return pk[1] - pk[0]
+
+    I1 = hologram(lam1)
+    It = hologram(lamt)
+    frames = np.stack([I1, It])
+    V = O.render(frames, [lam1, lamt], d, z, exact_chirp=True)
+    # rescaled: bin 0 of the depth transform mixes both frames; transform each frame alone
+    V1 = O.render(frames[:1], [lam1], d, z)
+    Vt_rescaled = np.fft.ifft(V, axis=0)[1:2] * 2   # frame t back from the 2-point DFT
+    Vt_raw = O.render(frames[1:], [lamt], d, z)
+    assert centroids(V1) == pytest.approx(sep_px, abs=0.05)
+    assert centroids(Vt_rescaled) == pytest.approx(sep_px, abs=0.05)
+    assert centroids(Vt_raw) == pytest.approx(dx * N * d / (lamt * z), abs=0.05)
+
+
+# --------------------------------------------------------------------------
+# Step 3: depth DFT (Eq. 7)
+# --------------------------------------------------------------------------
+
+def check_depth_tone():
+    """A tone exp(+2 i k_t delta) on bin q_m gives exactly T at q_m (sign of Eq. 7)."""
+    T, qm = 16, 5
+    t = np.arange(T)
+    h = np.exp(2j * np.pi * qm * t / T)[:, None, None] * np.ones((1, 2, 2))
+    V = O.depth_dft(h)
+    expect = np.zeros(T)
+    expect[qm] = T
+    assert np.allclose(np.abs(V[:, 0, 0]), expect, atol=1e-9)
+
+
+def test_depth_tone():
+    check_depth_tone()
+
+
+def test_depth_brute_force():
+    rng = np.random.default_rng(3)
+    T = 7
+    h = rng.standard_normal((T, 3, 2)) + 1j * rng.standard_normal((T, 3, 2))
+    V = O.depth_dft(h)
+    Vb = np.zeros_like(h)
+    for q in range(T):
+        for t in range(T):
+            Vb[q] += h[t] * np.exp(-2j * np.pi * q * t / T)
+    assert np.allclose(V, Vb, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Whole chain
+# --------------------------------------------------------------------------
+
+def _small_case(T=6, N=16, seed=11):
+    rng = np.random.default_rng(seed)
+    frames = rng.integers(0, 65536, size=(T, N, N)).astype(np.uint16)
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9)
+    phi = rng.uniform(-2, 2, T)
+    zc = rng.normal(0, 0.5, 15)
+    return frames, lam, 20e-6, 0.05, phi, zc
+
+
+def check_parseval():
+    frames, lam, d, z, phi, zc = _small_case()
+    T, N, _ = frames.shape
+    s = O.scale_factors(lam)
+    EJ = sum(np.sum(O.rescale(frames[t], s[t]) ** 2) for t in range(T))
+    for exact in (False, True):
+        V = O.render(frames, lam, d, z, phi, zc, exact_chirp=exact)
+        assert np.sum(np.abs(V) ** 2) == pytest.approx(T * N * N * EJ, rel=1e-12)
+
+
+def test_parseval():
+    check_parseval()
+
+
+def test_render_matches_direct_sums():
+    """FFT-based render vs the term-by-term sums of Eq. 6 and Eq. 7 (every pixel, tiny size)."""
+    frames, lam, d, z, phi, zc = _small_case(T=5, N=16)
+    N = frames.shape[1]
+    pix = [(u, v) for u in range(N) for v in range(N)]
+    for kw in ({}, {"exact_chirp": True}, {"eq6_phase": True}):
+        V = O.render(frames, lam, d, z, phi, zc, **kw)
+        Vc = O.render_columns(frames, lam, d, z, pix, phi, zc, **kw)
+        assert np.allclose(V.reshape(V.shape[0], -1), Vc, rtol=0, atol=1e-9 * np.abs(Vc).max())
+
+
+def test_eq6_phase_only_scales_magnitude():
+    frames, lam, d, z, phi, zc = _small_case()
+    V0 = O.render(frames, lam, d, z, phi, zc)
+    V1 = O.render(frames, lam, d, z, phi, zc, eq6_phase=True)
+    lam1 = O.reference_wavelength(lam)
+    assert np.allclose(np.abs(V1), np.abs(V0) * d * d / (lam1 * z), rtol=1e-10, atol=0)
+
+
+def test_generator_scatterers_focus():
+    """Synthetic ground truth: every scatterer of the tiny workload peaks at its pixel and bin."""
+    sw = synth.make_config("tiny")
+    for exact in (False, True):
+        M = np.abs(O.render(sw.frames, sw.lam, sw.pitch, sw.z, exact_chirp=exact))
+        for u, v, q, _ in sw.scatterers:
+            u, v, q = int(u), int(v), int(q)
+            win = M[q, u - 2:u + 3, v - 2:v + 3]
+            assert np.unravel_index(np.argmax(win), win.shape) == (2, 2)
+            assert int(np.argmax(M[1:M.shape[0] // 2, u, v])) + 1 == q
+
+
+def test_cuts_indexing():
+    T, N = 5, 8
+    q, u, v = np.meshgrid(np.arange(T), np.arange(N), np.arange(N), indexing="ij")
+    vol = (1000 * q + 10 * u + v) * np.exp(1j * (q + u - v))
+    xy, xz, yz = O.cuts(vol, x0=3, y0=6, q0=2)
+    assert np.allclose(xy, 2000 + 10 * u[0] + v[0])
+    assert np.allclose(xz, 1000 * q[:, 0, :] + 60 + v[:, 0, :])
+    assert np.allclose(yz, 1000 * q[:, :, 0] + 10 * u[:, :, 0] + 3)
+    xy2, _, _ = O.cuts(vol, 3, 6, 2, power=True)
+    assert np.allclose(xy2, xy ** 2)
+
+
+# --------------------------------------------------------------------------
+# Zernike basis
+# --------------------------------------------------------------------------
+
+def test_zernike_closed_forms_and_orthonormality():
+    rho = np.linspace(0, 1, 7)
+    th = np.linspace(-3, 3, 7)
+    assert np.allclose(O.zernike(0, rho, th), 1.0)
+    assert np.allclose(O.zernike(4, rho, th), math.sqrt(3) * (2 * rho ** 2 - 1))
+    assert np.allclose(O.zernike(12, rho, th), math.sqrt(5) * (6 * rho ** 4 - 6 * rho ** 2 + 1))
+    assert np.allclose(O.zernike(3, rho, th), math.sqrt(6) * rho ** 2 * np.sin(2 * th))
+    assert np.allclose(O.zernike(9, rho, th), math.sqrt(8) * rho ** 3 * np.cos(3 * th))
+    # (1/pi) int_disk Z_j Z_k rho d rho d theta = delta_jk (Gauss-Legendre x uniform angle)
+    xr, wr = np.polynomial.legendre.leggauss(24)
+    r = 0.5 * (xr + 1)
+    wr = 0.5 * wr
+    na = 64
+    a = 2 * np.pi * np.arange(na) / na
+    R, A = np.meshgrid(r, a, indexing="ij")
+    W = (wr[:, None] * R) * (2 * np.pi / na) / np.pi
+    Z = np.stack([O.zernike(j, R, A) for j in range(15)])
+    G = np.einsum("jab,kab,ab->jk", Z, Z, W)
+    assert np.allclose(G, np.eye(15), atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Adjoint and gradient
+# --------------------------------------------------------------------------
+
+def test_dot_product_adjoint():
+    rng = np.random.default_rng(1)
+    T, N = 6, 16
+    x = rng.standard_normal((T, N, N)) + 1j * rng.standard_normal((T, N, N))
+    G = rng.standard_normal((T, N, N)) + 1j * rng.standard_normal((T, N, N))
+    phi = rng.uniform(-3, 3, T)
+    lhs = np.vdot(G, O.forward_linear(x, phi))
+    rhs = np.vdot(O.adjoint_linear(G, phi), x)
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def _fd_case():
+    frames, lam, d, z, phi, zc = _small_case(T=6, N=16, seed=21)
+    return frames, lam, d, z, phi, zc
+
+
+def check_gradient_fd(exact=False):
+    frames, lam, d, z, phi, zc = _fd_case()
+    L, dz, dc, dphi = O.sharpness_grad(frames, lam, d, z, phi, zc, exact)
+
+    def loss(z_=z, phi_=phi, zc_=zc):
+        return O.sharpness(O.render(frames, lam, d, z_, phi_, zc_, exact))
+
+    h = 1e-6 * z
+    fd = (loss(z_=z + h) - loss(z_=z - h)) / (2 * h)
+    assert dz == pytest.approx(fd, rel=1e-6)
+    for j in (1, 4, 7, 12):
+        e = np.zeros(15)
+        e[j] = 1e-4
+        fd = (loss(zc_=zc + e) - loss(zc_=zc - e)) / 2e-4
+        assert dc[j] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(L))
+    for t in (0, 3, 5):
+        e = np.zeros(frames.shape[0])
+        e[t] = 1e-4
+        fd = (loss(phi_=phi + e) - loss(phi_=phi - e)) / 2e-4
+        assert dphi[t] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(L))
+    return L, dz, dc, dphi
+
+
+def test_gradient_finite_differences():
+    check_gradient_fd(False)
+    check_gradient_fd(True)
+
+
+def test_gradient_invariants():
+    """Global phase invariance: sum_t dL/dphi_t = 0 and dL/dc_0 = 0 (Z_0 = 1)."""
+    frames, lam, d, z, phi, zc = _fd_case()
+    L, dz, dc, dphi = O.sharpness_grad(frames, lam, d, z, phi, zc)
+    scale = np.max(np.abs(dphi))
+    assert abs(np.sum(dphi)) < 1e-9 * scale
+    assert abs(dc[0]) < 1e-9 * np.max(np.abs(dc))
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each plausible error in the oracle must fail a pin
+# --------------------------------------------------------------------------
+
+def _plants():
+    yield "depth sign", "depth_dft", lambda orig: (lambda h: np.conj(orig(np.conj(h)))), check_depth_tone
+    yield "fresnel sign", "fresnel_fft", lambda orig: (lambda x: np.conj(orig(np.conj(x)))), \
+        check_fresnel_closed_forms
+    yield "fresnel no centring", "fresnel_fft", \
+        lambda orig: (lambda x: x.shape[-1] ** 2 * np.fft.ifft2(x, axes=(-2, -1))), check_fresnel_closed_forms
+    yield "rescale inverted", "scale_factors", lambda orig: (lambda lam: 1.0 / orig(lam)), check_pitch_equalisation
+    yield "rescale off-centre", "interp_positions", lambda orig: (
+        lambda N, s: orig(N, s) if s == 1.0 else _shifted_positions(N, s)), check_rescale
+    yield "chirp sign", "chirp", lambda orig: (lambda N, a: np.conj(orig(N, a))), check_point_source_focus
+    yield "chirp factor 2", "chirp_rates", lambda orig: (lambda *a, **k: 2 * orig(*a, **k)), \
+        check_point_source_focus
+    yield "axial range halved", "axial_range", lambda orig: (lambda a, b, n: orig(a, b, n) / 2), \
+        check_printed_axial
+
+
+def _shifted_positions(N, s):
+    P = np.arange(N) * s
+    j0 = np.floor(P).astype(np.int64)
+    return j0, np.minimum(j0 + 1, N - 1), P - j0
+
+
+def check_rescale_chain():
+    """Rescale through the whole chain keeps every sample inside the frame (s <= 1)."""
+    lam = synth.sweep_wavelengths(4, 870e-9, 800e-9)
+    s = O.scale_factors(lam)
+    assert np.all(s <= 1.0) and s[0] == 1.0
+
+
+@pytest.mark.parametrize("name,attr,mutate,pin", list(_plants()), ids=[p[0] for p in _plants()])
+def test_planted_mistakes(monkeypatch, name, attr, mutate, pin):
+    pin()                                   # passes on the real oracle
+    orig = getattr(O, attr)
+    monkeypatch.setattr(O, attr, mutate(orig))
+    with pytest.raises(AssertionError):
+        pin()
