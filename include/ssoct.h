@@ -1,0 +1,152 @@
+/*
+ * ssoct.h -- C ABI of the MI355X (gfx950) renderer for swept-source optical
+ * coherence tomography by off-axis Fresnel-transform digital holography
+ * (Charpentier et al., arXiv 2003.08960).
+ *
+ * Pipeline of one call to ssoct_render (flowchart of Fig. 3):
+ *   1. chromatic rescale of each 16-bit interferogram by linear interpolation,
+ *      I'(x, y, t) = I(x lambda_t / lambda_1, y lambda_t / lambda_1, t)
+ *      about the frame centre (Eq. 5; makes the Fresnel pixel of Eq. 4
+ *      wavelength independent)
+ *   2. discrete Fresnel transform with lambda_1 for every frame (Eq. 6):
+ *      chirp exp(-i pi d^2 c^2 / (lambda_1 z)) on the sensor grid, then the
+ *      centred, positive-exponent, unnormalised 2-D DFT
+ *   3. DFT along the sweep over one rectangular gate of all T frames
+ *      (Eq. 7): V[q] = sum_t h_t exp(-2 pi i q t / T), natural bin order
+ *   4. envelope |V| and three orthogonal cuts (text after Eq. 7)
+ *
+ * lambda_1 is the longest wavelength of the sweep (the start wavelength of
+ * the paper's sweep).  Optional extensions: a per-frame dispersion phase
+ * exp(i phi_t) on h_t, an aberration screen exp(i sum_j c_j Z_j) (ANSI/OSA
+ * Zernike j = 0..14, orthonormal, rho = r / (N d / sqrt 2)) on the rescaled
+ * frame, and the gradient of the sharpness loss sum |V|^4 with respect to z,
+ * c and phi.
+ *
+ * Conventions for every entry point:
+ *   - Arrays named frames, vol, grad_vol, cut_*, workspace and grad_out are
+ *     DEVICE pointers on the plan's device, owned by the caller; lambda,
+ *     disp_phase and zernike are HOST arrays read before the call returns.
+ *   - frames: uint16 [T][N][N], row-major (t, y, x).
+ *   - vol: complex64 [T][N][N] = interleaved float (re, im), index (q, u, v)
+ *     with u = row (y), v = column (x); or float [T][N][N] = |V| when the plan
+ *     has SSOCT_WRITE_ABS.
+ *   - All work is enqueued asynchronously on the plan's stream; nothing is
+ *     synchronised.  A plan is not thread safe: use one plan per thread.
+ *   - Return value: SSOCT_OK (0), a warning (> 0, the result is computed) or
+ *     an error (< 0, nothing was enqueued).  ssoct_last_error() gives the
+ *     text of the last error of the calling thread.  No C++ exception
+ *     crosses this interface.
+ */
+#ifndef SSOCT_H
+#define SSOCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSOCT_VERSION 1
+
+/* status codes */
+#define SSOCT_OK 0
+#define SSOCT_WARN_UNDERSAMPLED 1 /* |z| < z_b = N d^2 / lambda_1 (validity bound after Eq. 6) */
+#define SSOCT_EINVAL (-1)         /* null pointer, bad size, lambda <= 0, z == 0, non-finite value */
+#define SSOCT_EUNSUPPORTED (-2)   /* N not a power of two in [16, 2048], T not in [1, 1024], option not available */
+#define SSOCT_EHIP (-3)           /* HIP runtime error (text in ssoct_last_error) */
+#define SSOCT_ENOMEM (-4)         /* device allocation failed, or workspace too small */
+#define SSOCT_EALIAS (-5)         /* output overlaps an input or the workspace */
+
+/* plan flags */
+#define SSOCT_PREC_FP32 0u        /* depth transform on FP32 MFMA */
+#define SSOCT_PREC_FP16 1u        /* depth transform on FP16 MFMA, FP32 accumulation */
+#define SSOCT_PREC_BF16 2u        /* depth transform on BF16 MFMA, FP32 accumulation */
+#define SSOCT_PREC_MASK 3u
+#define SSOCT_SPLIT 4u            /* FP16/BF16 operands split hi + lo (3 products) */
+#define SSOCT_CHIRP_EXACT 8u      /* chirp rate pi d^2 (lambda_t/lambda_1) / (lambda_1 z) instead of lambda_1 only */
+#define SSOCT_EQ6_PHASE 16u       /* apply the Eq. 6 prefactor (i d^2/(lambda_1 z)) e^{-i k_1 z} and output phase */
+#define SSOCT_WRITE_ABS 32u       /* ssoct_render writes |V| (float) instead of V (complex64) */
+#define SSOCT_CUT_POWER 64u       /* ssoct_cuts returns |V|^2 instead of |V| */
+#define SSOCT_BACKWARD 128u       /* workspace also sized for the gradient entry points */
+#define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
+
+typedef struct ssoct_plan ssoct_plan;
+
+/* Library version (SSOCT_VERSION). */
+int ssoct_version(void);
+
+/* Text of the last error returned to the calling thread ("" if none). */
+const char* ssoct_last_error(void);
+
+/* Bytes of device workspace ssoct_render (and, with SSOCT_BACKWARD, the
+ * gradient entry points) need for T frames of N x N; 0 for unsupported
+ * sizes.  The workspace holds the hologram stack H (T N^2 x 8 bytes), one
+ * chunk of row-transformed frames, and with SSOCT_BACKWARD a second stack and
+ * the FP64 reduction partials. */
+size_t ssoct_workspace_size(int T, int N, uint32_t flags);
+
+/* Create a plan for T frames of N x N on the current HIP device, enqueuing
+ * its work on `stream` (0 = null stream).  Allocates the small FP64-derived
+ * tables (twiddles, depth DFT matrix in MFMA register order; O(T N + T^2)).
+ * On error *plan is NULL. */
+int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream_t stream);
+
+/* Change the stream of a plan. */
+int ssoct_plan_set_stream(ssoct_plan* plan, hipStream_t stream);
+
+/* Release a plan (waits for its stream). NULL is accepted. */
+int ssoct_plan_destroy(ssoct_plan* plan);
+
+/* Render one sweep: frames [T][N][N] uint16 -> vol [T][N][N] (steps 1-3).
+ *   lambda     host double [T], metres, > 0 (any order; lambda_1 = max)
+ *   pitch      sensor pixel pitch d, metres, > 0
+ *   z          reconstruction distance, metres, != 0
+ *   disp_phase host double [T] radians, or NULL (zero)
+ *   zernike    host double [15] radians, or NULL (no aberration)
+ *   workspace  device, at least ssoct_workspace_size(T, N, flags) bytes
+ * Rescale/chirp tables are rebuilt (FP64 on the GPU) only when lambda, pitch,
+ * z, disp_phase or zernike change between calls. */
+int ssoct_render(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
+                 const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                 void* vol);
+
+/* Three orthogonal cuts of the envelope (step 4) of a complex64 volume:
+ *   cut_xy[u][v] = M[q0][u][v]   float [N][N]
+ *   cut_xz[q][v] = M[q][y0][v]   float [T][N]
+ *   cut_yz[q][u] = M[q][u][x0]   float [T][N]
+ * with M = |V| (|V|^2 with SSOCT_CUT_POWER); 0 <= x0, y0 < N, 0 <= q0 < T. */
+int ssoct_cuts(ssoct_plan* plan, const void* vol, int x0, int y0, int q0, float* cut_xy, float* cut_xz,
+               float* cut_yz);
+
+/* Vector-Jacobian product of ssoct_render for a real loss L with
+ * dL = Re sum conj(G) dV, G = grad_vol (complex64 [T][N][N], PyTorch's
+ * convention G = 2 dL/d conj(V)).  Writes device double grad_out[2 + 15 + T]:
+ * [0] = 0, [1] = dL/dz, [2..16] = dL/dc_j, [17..17+T) = dL/dphi_t.
+ * The forward transform is not needed: the rescaled, chirped frames are
+ * recomputed inside the adjoint.  Needs a plan with SSOCT_PREC_FP32 or any
+ * precision (the adjoint always runs in FP32) and a workspace sized with
+ * SSOCT_BACKWARD; SSOCT_EQ6_PHASE is not supported (SSOCT_EUNSUPPORTED). */
+int ssoct_backward(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
+                   const double* disp_phase, const double* zernike, const void* grad_vol, void* workspace,
+                   size_t workspace_bytes, double* grad_out);
+
+/* Sharpness loss L = sum |V|^4 and its gradient in one call: recomputes the
+ * FP32 forward, forms G = 4 |V|^2 V with a power-of-two rescaling that keeps
+ * it finite in FP32, and runs the adjoint; the volume is never stored.
+ * grad_out as for ssoct_backward with grad_out[0] = L (FP64 accumulation). */
+int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch,
+                             double z, const double* disp_phase, const double* zernike, void* workspace,
+                             size_t workspace_bytes, double* grad_out);
+
+/* With SSOCT_PROFILE: wait for the last ssoct_render of the plan and return
+ * the elapsed milliseconds of its stages: ms[0] tables, ms[1] Fresnel stage
+ * (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth transform. */
+int ssoct_profile_read(ssoct_plan* plan, float* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSOCT_H */

@@ -1,0 +1,481 @@
+// C ABI: plans, argument checks, table caching and the order of kernel
+// launches for render, cuts and the two gradient entry points.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ssoct.h"
+#include "internal.hpp"
+
+using namespace ssoct;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return SSOCT_EHIP;
+}
+
+#define SSOCT_HIP(call)                              \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
+
+int frames_per_chunk(int T, int N) {
+  // keep one chunk of row-transformed frames (8 bytes per pixel) near 64 MiB
+  const size_t per = (size_t)N * N * 8;
+  size_t f = ((size_t)64 << 20) / per;
+  if (f < 1) f = 1;
+  if (f > (size_t)T) f = (size_t)T;
+  return (int)f;
+}
+
+struct WsLayout {
+  size_t H, inter, B2, mono, loss, total;
+};
+
+WsLayout ws_layout(int T, int N, uint32_t flags, int F) {
+  WsLayout w{};
+  const size_t stack = (size_t)T * N * N * 8;
+  size_t off = 0;
+  w.H = off;
+  off += align256(stack);
+  w.inter = off;
+  off += align256((size_t)F * N * N * 8);
+  if (flags & SSOCT_BACKWARD) {
+    w.B2 = off;
+    off += align256(stack);
+    w.mono = off;
+    off += align256((size_t)T * row_adj_blocks(N) * N_MONO * sizeof(double));
+    w.loss = off;
+    off += align256((size_t)4096 * sizeof(double));
+  }
+  w.total = off;
+  return w;
+}
+
+// Zernike j (ANSI/OSA, orthonormal) expanded in the monomials x^a y^b of the
+// fixed order (a + b <= 4): Z_j = norm * R_n^|m|(rho) * {cos, sin}(|m| theta),
+// with rho^|m| cos(|m| theta) = Re (x + i y)^|m|, rho^|m| sin = Im, and the
+// remaining even power of rho as (x^2 + y^2)^k.
+void zernike_monomials(double zmat[15][N_MONO]) {
+  static const int A[N_MONO] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
+  static const int B[N_MONO] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
+  auto fact = [](int n) {
+    double r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+  };
+  auto binom = [&](int n, int k) { return fact(n) / (fact(k) * fact(n - k)); };
+  for (int j = 0; j < 15; ++j) {
+    int n = (int)std::ceil((-3.0 + std::sqrt(9.0 + 8.0 * j)) / 2.0);
+    int m = 2 * j - n * (n + 2);
+    int am = m < 0 ? -m : m;
+    double poly[5][5] = {};  // poly[a][b]
+    // angular factor Re/Im (x + i y)^am
+    double ang[5][5] = {};
+    for (int r = 0; r <= am; ++r) {
+      const double c = binom(am, r);
+      // term c x^(am-r) (i y)^r ; i^r = (-1)^(r/2) for even r, i (-1)^((r-1)/2) for odd r
+      if (m >= 0 && r % 2 == 0) ang[am - r][r] += c * ((r / 2) % 2 ? -1.0 : 1.0);
+      if (m < 0 && r % 2 == 1) ang[am - r][r] += c * (((r - 1) / 2) % 2 ? -1.0 : 1.0);
+    }
+    const int p = (n - am) / 2;
+    for (int k = 0; k <= p; ++k) {
+      const double rc = ((k % 2) ? -1.0 : 1.0) * fact(n - k) / (fact(k) * fact((n + am) / 2 - k) * fact((n - am) / 2 - k));
+      const int e = p - k;  // (x^2 + y^2)^e
+      for (int r = 0; r <= e; ++r) {
+        const double bc = binom(e, r);
+        for (int a = 0; a + 2 * (e - r) <= 4; ++a)
+          for (int b = 0; b + 2 * r <= 4; ++b)
+            if (ang[a][b] != 0.0 && a + 2 * (e - r) <= 4 && b + 2 * r <= 4)
+              poly[a + 2 * (e - r)][b + 2 * r] += rc * bc * ang[a][b];
+      }
+    }
+    const double norm = std::sqrt((m == 0 ? 1.0 : 2.0) * (n + 1));
+    for (int k = 0; k < N_MONO; ++k) zmat[j][k] = norm * poly[A[k]][B[k]];
+  }
+}
+
+}  // namespace
+
+struct ssoct_plan {
+  int T = 0, N = 0, F = 0, device = 0, cu = 0;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  DepthLayout dl{};
+  AxisTab* rows = nullptr;
+  AxisTab* cols = nullptr;
+  float2* tw = nullptr;
+  float2* outfac = nullptr;
+  float2* aberr = nullptr;
+  double* params = nullptr;      // ParamLayout + alpha/z [T] + zmat [225]
+  float* a_f32 = nullptr;
+  uint4* a_f16 = nullptr;
+  uint4* a_bf16 = nullptr;
+  double zmat[15][N_MONO];
+  std::vector<double> cache;     // last parameter set the tables were built from
+  bool have_aberr = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ev_recorded = false;
+};
+
+namespace {
+
+void plan_free(ssoct_plan* p) {
+  if (!p) return;
+  (void)hipFree(p->rows);
+  (void)hipFree(p->cols);
+  (void)hipFree(p->tw);
+  (void)hipFree(p->outfac);
+  (void)hipFree(p->aberr);
+  (void)hipFree(p->params);
+  (void)hipFree(p->a_f32);
+  (void)hipFree(p->a_f16);
+  (void)hipFree(p->a_bf16);
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+}
+
+bool finite_all(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+int depth_prec(uint32_t flags) {
+  const uint32_t pr = flags & SSOCT_PREC_MASK;
+  const bool split = (flags & SSOCT_SPLIT) != 0;
+  if (pr == SSOCT_PREC_FP16) return split ? DP_F16_SPLIT : DP_F16;
+  if (pr == SSOCT_PREC_BF16) return split ? DP_BF16_SPLIT : DP_BF16;
+  return DP_F32;
+}
+
+int h_format(int prec) {
+  if (prec == DP_F16 || prec == DP_F16_SPLIT) return HF_F16;
+  if (prec == DP_BF16 || prec == DP_BF16_SPLIT) return HF_BF16;
+  return HF_F32;
+}
+
+const void* amat_for(const ssoct_plan* p, int prec) {
+  if (prec == DP_F32) return p->a_f32;
+  if (prec == DP_F16 || prec == DP_F16_SPLIT) return p->a_f16;
+  return p->a_bf16;
+}
+
+// Validate the per-call physical parameters and (re)build the tables when
+// they changed.  Returns SSOCT_OK, SSOCT_WARN_UNDERSAMPLED or an error.
+int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, const double* disp,
+                  const double* zern, bool for_backward) {
+  const int T = p->T, N = p->N;
+  if (!lambda) return fail(SSOCT_EINVAL, "lambda is NULL");
+  if (!finite_all(lambda, T)) return fail(SSOCT_EINVAL, "lambda has a non-finite entry");
+  for (int t = 0; t < T; ++t)
+    if (!(lambda[t] > 0)) return fail(SSOCT_EINVAL, "lambda must be > 0");
+  if (!(pitch > 0) || !std::isfinite(pitch)) return fail(SSOCT_EINVAL, "pitch must be finite and > 0");
+  if (!(z != 0) || !std::isfinite(z)) return fail(SSOCT_EINVAL, "z must be finite and non-zero");
+  if (disp && !finite_all(disp, T)) return fail(SSOCT_EINVAL, "disp_phase has a non-finite entry");
+  if (zern && !finite_all(zern, 15)) return fail(SSOCT_EINVAL, "zernike has a non-finite entry");
+  if (for_backward && (p->flags & SSOCT_EQ6_PHASE))
+    return fail(SSOCT_EUNSUPPORTED, "gradients are not available with SSOCT_EQ6_PHASE");
+
+  double lam1 = lambda[0];
+  for (int t = 1; t < T; ++t) lam1 = lambda[t] > lam1 ? lambda[t] : lam1;
+  const int status = (std::fabs(z) < (double)N * pitch * pitch / lam1) ? SSOCT_WARN_UNDERSAMPLED : SSOCT_OK;
+
+  std::vector<double> key;
+  key.reserve(3 * T + 20);
+  key.insert(key.end(), lambda, lambda + T);
+  key.push_back(pitch);
+  key.push_back(z);
+  key.push_back(disp ? 1.0 : 0.0);
+  if (disp) key.insert(key.end(), disp, disp + T);
+  key.push_back(zern ? 1.0 : 0.0);
+  if (zern) key.insert(key.end(), zern, zern + 15);
+  if (key == p->cache) return status;
+
+  const bool exact = (p->flags & SSOCT_CHIRP_EXACT) != 0;
+  const bool eq6 = (p->flags & SSOCT_EQ6_PHASE) != 0;
+  std::vector<double> h(ParamLayout::count(T) + T + 15 * N_MONO, 0.0);
+  const double two_pi = 6.283185307179586476925;
+  const double eq6_cyc = eq6 ? 0.25 - (z / lam1 - std::floor(z / lam1)) : 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double s = lambda[t] / lam1;
+    const double kappa = pitch * pitch * (exact ? s : 1.0) / (2.0 * lam1 * z);   // alpha_t / (2 pi)
+    double* pf = &h[(size_t)ParamLayout::PER_FRAME * t];
+    pf[0] = s;
+    pf[1] = kappa;
+    pf[2] = (disp ? disp[t] / two_pi : 0.0) + eq6_cyc;
+    pf[3] = eq6 ? pitch * pitch / (lam1 * z) : 1.0;
+    h[ParamLayout::count(T) + t] = two_pi * kappa / z;   // alpha_t / z
+  }
+  double* g = &h[ParamLayout::globals(T)];
+  g[ParamLayout::G_KAPPA_OUT] = lam1 * z / (2.0 * (double)N * N * pitch * pitch);
+  if (zern) {
+    for (int k = 0; k < N_MONO; ++k) {
+      double c = 0.0;
+      for (int j = 0; j < 15; ++j) c += zern[j] * p->zmat[j][k];
+      g[ParamLayout::G_POLY + k] = c;
+    }
+    g[ParamLayout::G_HAS_ABERR] = 1.0;
+  }
+  std::memcpy(&h[ParamLayout::count(T) + T], &p->zmat[0][0], sizeof(double) * 15 * N_MONO);
+  if (zern && !p->aberr) {
+    SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
+  }
+  SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
+  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->tw, p->outfac, zern ? p->aberr : nullptr, p->stream));
+  p->have_aberr = zern != nullptr;
+  p->cache.swap(key);
+  return status;
+}
+
+int check_plan(const ssoct_plan* p) {
+  if (!p) return fail(SSOCT_EINVAL, "plan is NULL");
+  return SSOCT_OK;
+}
+
+int forward_stage_a(ssoct_plan* p, const uint16_t* frames, void* H, float2* inter, int fmt, int sigma) {
+  const int T = p->T, N = p->N;
+  for (int t0 = 0; t0 < T; t0 += p->F) {
+    const int Fc = T - t0 < p->F ? T - t0 : p->F;
+    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->aberr : nullptr,
+                              p->outfac, inter, p->stream));
+    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, fmt, sigma, p->stream));
+  }
+  return SSOCT_OK;
+}
+
+int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
+                  const double* loss_partials, int n_loss, double grad_scale, double* out) {
+  const int T = p->T, N = p->N;
+  float2* beta = reinterpret_cast<float2*>(ws + L.H);
+  float2* inter = reinterpret_cast<float2*>(ws + L.inter);
+  double* mono = reinterpret_cast<double*>(ws + L.mono);
+  const int grid = depth_grid(T, N * N, p->cu);
+  SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, grid, p->stream));
+  for (int t0 = 0; t0 < T; t0 += p->F) {
+    const int Fc = T - t0 < p->F ? T - t0 : p->F;
+    SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->stream));
+    SSOCT_HIP(launch_row_pass_adj(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->aberr : nullptr,
+                                  inter, mono, p->stream));
+  }
+  const double* aoz = p->params + ParamLayout::count(T);
+  const double* zm = aoz + T;
+  SSOCT_HIP(launch_grad_finish(T, N, row_adj_blocks(N), mono, loss_partials, n_loss, aoz, zm, grad_scale, out,
+                               p->stream));
+  return SSOCT_OK;
+}
+
+int fresnel_sigma(const ssoct_plan* p, int prec, double pitch, double z, double lam1) {
+  if (h_format(prec) != HF_F16) return 0;
+  // |H| <= N^2 * 65535 * amplitude; keep it below 2^15 in FP16
+  double amp = 1.0;
+  if (p->flags & SSOCT_EQ6_PHASE) amp = std::fabs(pitch * pitch / (lam1 * z));
+  const double bound = (double)p->N * p->N * 65535.0 * amp;
+  return (int)std::ceil(std::log2(bound / 32768.0));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssoct_version(void) { return SSOCT_VERSION; }
+
+const char* ssoct_last_error(void) { return g_err.c_str(); }
+
+size_t ssoct_workspace_size(int T, int N, uint32_t flags) {
+  if (T < 1 || T > 1024 || !pow2_in_range(N)) return 0;
+  return ws_layout(T, N, flags, frames_per_chunk(T, N)).total;
+}
+
+int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream_t stream) {
+  if (!plan) return fail(SSOCT_EINVAL, "plan pointer is NULL");
+  *plan = nullptr;
+  if (T < 1 || T > 1024) return fail(SSOCT_EUNSUPPORTED, "T must be in [1, 1024]");
+  if (!pow2_in_range(N)) return fail(SSOCT_EUNSUPPORTED, "N must be a power of two in [16, 2048]");
+  if ((flags & SSOCT_PREC_MASK) == 3u) return fail(SSOCT_EINVAL, "unknown precision");
+  if ((flags & SSOCT_SPLIT) && (flags & SSOCT_PREC_MASK) == SSOCT_PREC_FP32)
+    return fail(SSOCT_EINVAL, "SSOCT_SPLIT needs SSOCT_PREC_FP16 or SSOCT_PREC_BF16");
+  ssoct_plan* p = new (std::nothrow) ssoct_plan();
+  if (!p) return fail(SSOCT_ENOMEM, "host allocation failed");
+  p->T = T;
+  p->N = N;
+  p->flags = flags;
+  p->stream = stream;
+  p->F = frames_per_chunk(T, N);
+  p->dl = depth_layout(T);
+  zernike_monomials(p->zmat);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  const size_t axis = (size_t)T * N * sizeof(AxisTab);
+  const size_t nparams = ParamLayout::count(T) + T + 15 * N_MONO;
+  const size_t na32 = (size_t)p->dl.nrb * (p->dl.T_pad / 2) * 64;
+  const size_t na16 = (size_t)p->dl.nrb * (p->dl.T_pad / 16) * 128;
+  if (e == hipSuccess) e = hipMalloc(&p->rows, axis);
+  if (e == hipSuccess) e = hipMalloc(&p->cols, axis);
+  if (e == hipSuccess) e = hipMalloc(&p->tw, (size_t)N * sizeof(float2));
+  if (e == hipSuccess && (flags & SSOCT_EQ6_PHASE)) e = hipMalloc(&p->outfac, (size_t)N * sizeof(float2));
+  if (e == hipSuccess) e = hipMalloc(&p->params, nparams * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->a_f32, na32 * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&p->a_f16, na16 * sizeof(uint4));
+  if (e == hipSuccess) e = hipMalloc(&p->a_bf16, na16 * sizeof(uint4));
+  if (e == hipSuccess && (flags & SSOCT_PROFILE))
+    for (auto& ev : p->ev)
+      if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
+  if (e != hipSuccess) {
+    const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
+                                              : hip_fail(e, "ssoct_plan_create");
+    plan_free(p);
+    return rc;
+  }
+  *plan = p;
+  return SSOCT_OK;
+}
+
+int ssoct_plan_set_stream(ssoct_plan* plan, hipStream_t stream) {
+  if (int rc = check_plan(plan)) return rc;
+  plan->stream = stream;
+  return SSOCT_OK;
+}
+
+int ssoct_plan_destroy(ssoct_plan* plan) {
+  if (!plan) return SSOCT_OK;
+  (void)hipStreamSynchronize(plan->stream);
+  plan_free(plan);
+  return SSOCT_OK;
+}
+
+int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
+                 const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                 void* vol) {
+  if (int rc = check_plan(p)) return rc;
+  if (!frames || !workspace || !vol) return fail(SSOCT_EINVAL, "frames, workspace and vol must be non-NULL");
+  const int T = p->T, N = p->N;
+  const WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
+  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size()");
+  const size_t vol_bytes = (size_t)T * N * N * ((p->flags & SSOCT_WRITE_ABS) ? 4 : 8);
+  if (overlap(vol, vol_bytes, frames, (size_t)T * N * N * 2) || overlap(vol, vol_bytes, workspace, workspace_bytes))
+    return fail(SSOCT_EALIAS, "vol overlaps frames or workspace");
+  SSOCT_HIP(hipSetDevice(p->device));
+  const bool prof = (p->flags & SSOCT_PROFILE) != 0;
+  if (prof) SSOCT_HIP(hipEventRecord(p->ev[0], p->stream));
+  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
+  if (status < 0) return status;
+  const int prec = depth_prec(p->flags);
+  const int fmt = h_format(prec);
+  double lam1 = lambda[0];
+  for (int t = 1; t < T; ++t) lam1 = lambda[t] > lam1 ? lambda[t] : lam1;
+  const int sigma = fresnel_sigma(p, prec, pitch, z, lam1);
+  char* ws = static_cast<char*>(workspace);
+  void* H = ws + L.H;
+  if (prof) SSOCT_HIP(hipEventRecord(p->ev[1], p->stream));
+  if (int rc = forward_stage_a(p, frames, H, reinterpret_cast<float2*>(ws + L.inter), fmt, sigma)) return rc;
+  if (prof) SSOCT_HIP(hipEventRecord(p->ev[2], p->stream));
+  const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
+  const int grid = depth_grid(T, N * N, p->cu);
+  SSOCT_HIP(launch_depth(T, N * N, prec, +1, epi, H, amat_for(p, prec), vol, sigma, 0, nullptr, grid, p->stream));
+  if (prof) {
+    SSOCT_HIP(hipEventRecord(p->ev[3], p->stream));
+    p->ev_recorded = true;
+  }
+  return status;
+}
+
+int ssoct_cuts(ssoct_plan* p, const void* vol, int x0, int y0, int q0, float* cut_xy, float* cut_xz, float* cut_yz) {
+  if (int rc = check_plan(p)) return rc;
+  if (!vol || !cut_xy || !cut_xz || !cut_yz) return fail(SSOCT_EINVAL, "vol and cut pointers must be non-NULL");
+  if (p->flags & SSOCT_WRITE_ABS) return fail(SSOCT_EUNSUPPORTED, "cuts need a complex64 volume");
+  if (x0 < 0 || x0 >= p->N || y0 < 0 || y0 >= p->N || q0 < 0 || q0 >= p->T)
+    return fail(SSOCT_EINVAL, "cut position out of range");
+  const size_t vb = (size_t)p->T * p->N * p->N * 8;
+  const size_t nxy = (size_t)p->N * p->N * 4, nz = (size_t)p->T * p->N * 4;
+  if (overlap(vol, vb, cut_xy, nxy) || overlap(vol, vb, cut_xz, nz) || overlap(vol, vb, cut_yz, nz))
+    return fail(SSOCT_EALIAS, "a cut overlaps the volume");
+  SSOCT_HIP(hipSetDevice(p->device));
+  SSOCT_HIP(launch_cuts(p->T, p->N, static_cast<const float2*>(vol), x0, y0, q0,
+                        (p->flags & SSOCT_CUT_POWER) ? 1 : 0, cut_xy, cut_xz, cut_yz, p->stream));
+  return SSOCT_OK;
+}
+
+int ssoct_backward(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
+                   const double* disp_phase, const double* zernike, const void* grad_vol, void* workspace,
+                   size_t workspace_bytes, double* grad_out) {
+  if (int rc = check_plan(p)) return rc;
+  if (!frames || !grad_vol || !workspace || !grad_out)
+    return fail(SSOCT_EINVAL, "frames, grad_vol, workspace and grad_out must be non-NULL");
+  const int T = p->T, N = p->N;
+  const WsLayout L = ws_layout(T, N, p->flags | SSOCT_BACKWARD, p->F);
+  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
+  if (overlap(grad_out, (size_t)(17 + T) * 8, workspace, workspace_bytes) ||
+      overlap(grad_vol, (size_t)T * N * N * 8, workspace, workspace_bytes))
+    return fail(SSOCT_EALIAS, "grad_vol or grad_out overlaps the workspace");
+  SSOCT_HIP(hipSetDevice(p->device));
+  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, true);
+  if (status < 0) return status;
+  if (int rc = adjoint_chain(p, frames, grad_vol, static_cast<char*>(workspace), L, nullptr, 0, 1.0, grad_out))
+    return rc;
+  return status;
+}
+
+int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
+                             const double* disp_phase, const double* zernike, void* workspace,
+                             size_t workspace_bytes, double* grad_out) {
+  if (int rc = check_plan(p)) return rc;
+  if (!frames || !workspace || !grad_out) return fail(SSOCT_EINVAL, "frames, workspace and grad_out must be non-NULL");
+  const int T = p->T, N = p->N;
+  const WsLayout L = ws_layout(T, N, p->flags | SSOCT_BACKWARD, p->F);
+  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
+  if (overlap(grad_out, (size_t)(17 + T) * 8, workspace, workspace_bytes))
+    return fail(SSOCT_EALIAS, "grad_out overlaps the workspace");
+  SSOCT_HIP(hipSetDevice(p->device));
+  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, true);
+  if (status < 0) return status;
+  char* ws = static_cast<char*>(workspace);
+  void* H = ws + L.H;
+  float2* gam = reinterpret_cast<float2*>(ws + L.B2);
+  double* loss = reinterpret_cast<double*>(ws + L.loss);
+  if (int rc = forward_stage_a(p, frames, H, reinterpret_cast<float2*>(ws + L.inter), HF_F32, 0)) return rc;
+  // |V| <= T N^2 65535: scale by 2^-e so that 4 |V^|^3 stays finite in FP32
+  const double bound = (double)T * N * N * 65535.0;
+  int e = (int)std::ceil(std::log2(bound)) - 40;
+  if (e < 0) e = 0;
+  const int grid = depth_grid(T, N * N, p->cu);
+  SSOCT_HIP(launch_depth(T, N * N, DP_F32, +1, EPI_GAMMA, H, p->a_f32, gam, 0, e, loss, grid, p->stream));
+  if (int rc = adjoint_chain(p, frames, gam, ws, L, loss, grid, std::ldexp(1.0, 3 * e), grad_out)) return rc;
+  return status;
+}
+
+int ssoct_profile_read(ssoct_plan* p, float* ms) {
+  if (int rc = check_plan(p)) return rc;
+  if (!ms) return fail(SSOCT_EINVAL, "ms is NULL");
+  if (!(p->flags & SSOCT_PROFILE) || !p->ev_recorded) return fail(SSOCT_EINVAL, "no profiled render recorded");
+  SSOCT_HIP(hipEventSynchronize(p->ev[3]));
+  for (int i = 0; i < 3; ++i) SSOCT_HIP(hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
+  return SSOCT_OK;
+}
+
+}  // extern "C"

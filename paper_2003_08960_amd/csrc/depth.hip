@@ -1,0 +1,288 @@
+// Depth transform (Eq. 7 with a rectangular gate over the T frames of a
+// sweep) as a dense real GEMM on MFMA.
+//
+// The complex DFT matrix W[q][t] = exp(-2 pi i q t / T) has W_{T-q} =
+// conj(W_q).  With A_q = sum_t Re(W_q[t]) h_t and B_q = sum_t Im(W_q[t]) h_t,
+//     V[q]   = A_q + i B_q,     V[T-q] = A_q - i B_q,
+// so one T x T real matrix whose rows are the pairs (Re W_q, Im W_q)
+// (q = 1 .. T-1-T/2, plus the pair (W_0, W_{T/2})) applied to the complex
+// stack viewed as reals gives the whole spectrum with 4 T^2 real flops per
+// pixel instead of 8 T^2.  The adjoint (exp(+2 pi i q t / T)) swaps V[q] and
+// V[T-q].
+//
+// Work split: a workgroup owns all M rows (one wave per 32-row block, rows
+// kept in registers for the life of the kernel) and walks 32-pixel tiles of
+// the stack; each tile of KC frames x 32 pixels is staged in LDS and read by
+// every wave.  Row pairs (2k, 2k+1) and the re/im columns of a pixel land in
+// the same lane of the 32x32 accumulator, so the epilogue needs no exchange.
+//
+// Operand precisions: FP32 (v_mfma_f32_32x32x2_f32), FP16/BF16 hi only, and
+// FP16/BF16 split hi*hi + hi*lo + lo*hi (v_mfma_f32_32x32x16_{f16,bf16}),
+// always with FP32 accumulation.
+#include "internal.hpp"
+
+namespace ssoct {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int PT = 32;  // pixels per tile
+
+template <int PREC>
+struct PrecTraits {
+  static constexpr bool F32 = PREC == DP_F32;
+  static constexpr bool SPLIT = PREC == DP_F16_SPLIT || PREC == DP_BF16_SPLIT;
+  static constexpr bool BF = PREC == DP_BF16 || PREC == DP_BF16_SPLIT;
+};
+
+template <bool BF>
+__device__ __forceinline__ v16f mfma_x16(uint4 a, uint4 b, v16f c) {
+  if constexpr (BF) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0,
+                                                  0);
+  }
+}
+
+// lo 16 bits of x0, x1 packed, and hi 16 bits packed
+__device__ __forceinline__ uint32_t pack_lo(uint32_t x0, uint32_t x1) { return __builtin_amdgcn_perm(x1, x0, 0x05040100u); }
+__device__ __forceinline__ uint32_t pack_hi(uint32_t x0, uint32_t x1) { return __builtin_amdgcn_perm(x1, x0, 0x07060302u); }
+
+template <int PREC, int KC, int WAVES, int DIR, int EPI>
+__global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ in, const void* __restrict__ amat,
+                                                      void* __restrict__ out, int T, int T_pad, int P, int slabs,
+                                                      float out_scale, float gamma_scale,
+                                                      double* __restrict__ loss_partials) {
+  using PT_ = PrecTraits<PREC>;
+  constexpr int NA = PT_::F32 ? KC / 2 : (PT_::SPLIT ? KC / 2 : KC / 4);  // dwords of A per lane
+  __shared__ uint2 btile[KC * PT];
+  __shared__ double red[WAVES];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nch = T_pad / KC;
+  const int ntp = P / PT;
+  const int ntiles = ntp * slabs;
+  const int h = T / 2;
+  const int npairs = T - h;
+  uint32_t a[NA];
+  double loss = 0.0;
+  int a_slab = -1, a_chunk = -1;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int slab = tile / ntp;
+    const int p0 = (tile % ntp) * PT;
+    const int rb = slab * WAVES + w;       // this wave's row block
+    v16f acc_re = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    v16f acc_im = acc_re;
+    for (int ch = 0; ch < nch; ++ch) {
+      // ---- A rows for (slab, chunk): loaded once when there is one slab and one chunk
+      if (a_slab != slab || a_chunk != ch) {
+        if constexpr (PT_::F32) {
+          const float* src = reinterpret_cast<const float*>(amat) + ((size_t)rb * (T_pad / 2) + ch * (KC / 2)) * 64 + l;
+#pragma unroll
+          for (int s = 0; s < KC / 2; ++s) a[s] = __float_as_uint(src[(size_t)s * 64]);
+        } else {
+          const uint4* src = reinterpret_cast<const uint4*>(amat) + ((size_t)rb * (T_pad / 16) + ch * (KC / 16)) * 128 + l;
+#pragma unroll
+          for (int s = 0; s < KC / 16; ++s) {
+            const uint4 hi = src[(size_t)s * 128];
+            a[(PT_::SPLIT ? 8 : 4) * s + 0] = hi.x;
+            a[(PT_::SPLIT ? 8 : 4) * s + 1] = hi.y;
+            a[(PT_::SPLIT ? 8 : 4) * s + 2] = hi.z;
+            a[(PT_::SPLIT ? 8 : 4) * s + 3] = hi.w;
+            if constexpr (PT_::SPLIT) {
+              const uint4 lo = src[(size_t)s * 128 + 64];
+              a[8 * s + 4] = lo.x;
+              a[8 * s + 5] = lo.y;
+              a[8 * s + 6] = lo.z;
+              a[8 * s + 7] = lo.w;
+            }
+          }
+        }
+        a_slab = slab;
+        a_chunk = ch;
+      }
+      // ---- stage the B tile: KC frames x 32 pixels, 8 bytes each, zero past T
+      __syncthreads();
+      {
+        const int tid = threadIdx.x;
+        constexpr int PER_ROW = PT / 2;                 // uint4 per tile row
+        constexpr int ROWS_PER_PASS = WAVES * 64 / PER_ROW;
+        const int cq = tid % PER_ROW, r0 = tid / PER_ROW;
+#pragma unroll 4
+        for (int r = r0; r < KC; r += ROWS_PER_PASS) {
+          const int t = ch * KC + r;
+          uint4 val = make_uint4(0u, 0u, 0u, 0u);
+          if (t < T) val = *reinterpret_cast<const uint4*>(in + (size_t)t * P + p0 + 2 * cq);
+          *reinterpret_cast<uint4*>(&btile[r * PT + 2 * cq]) = val;
+        }
+      }
+      __syncthreads();
+      // ---- MFMA over the chunk
+      if constexpr (PT_::F32) {
+#pragma unroll
+        for (int s = 0; s < KC / 2; ++s) {
+          const uint2 b = btile[(2 * s + (l >> 5)) * PT + (l & 31)];
+          const float av = __uint_as_float(a[s]);
+          acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.x), acc_re, 0, 0, 0);
+          acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.y), acc_im, 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KC / 16; ++s) {
+          uint2 e[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) e[i] = btile[(16 * s + 8 * (l >> 5) + i) * PT + (l & 31)];
+          uint4 re_hi, im_hi, re_lo, im_lo;
+          re_hi.x = pack_lo(e[0].x, e[1].x); re_hi.y = pack_lo(e[2].x, e[3].x);
+          re_hi.z = pack_lo(e[4].x, e[5].x); re_hi.w = pack_lo(e[6].x, e[7].x);
+          im_hi.x = pack_lo(e[0].y, e[1].y); im_hi.y = pack_lo(e[2].y, e[3].y);
+          im_hi.z = pack_lo(e[4].y, e[5].y); im_hi.w = pack_lo(e[6].y, e[7].y);
+          const int ai = (PT_::SPLIT ? 8 : 4) * s;
+          const uint4 ahi = make_uint4(a[ai], a[ai + 1], a[ai + 2], a[ai + 3]);
+          if constexpr (PT_::SPLIT) {
+            re_lo.x = pack_hi(e[0].x, e[1].x); re_lo.y = pack_hi(e[2].x, e[3].x);
+            re_lo.z = pack_hi(e[4].x, e[5].x); re_lo.w = pack_hi(e[6].x, e[7].x);
+            im_lo.x = pack_hi(e[0].y, e[1].y); im_lo.y = pack_hi(e[2].y, e[3].y);
+            im_lo.z = pack_hi(e[4].y, e[5].y); im_lo.w = pack_hi(e[6].y, e[7].y);
+            const uint4 alo = make_uint4(a[ai + 4], a[ai + 5], a[ai + 6], a[ai + 7]);
+            acc_re = mfma_x16<PT_::BF>(alo, re_hi, acc_re);
+            acc_im = mfma_x16<PT_::BF>(alo, im_hi, acc_im);
+            acc_re = mfma_x16<PT_::BF>(ahi, re_lo, acc_re);
+            acc_im = mfma_x16<PT_::BF>(ahi, im_lo, acc_im);
+          }
+          acc_re = mfma_x16<PT_::BF>(ahi, re_hi, acc_re);
+          acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
+        }
+      }
+    }
+    // ---- epilogue: lane holds rows 8 (r/4) + 4 (l/32) + r%4 of its block, column l%32
+    const int p = p0 + (l & 31);
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+      const int row = rb * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+      const int k = row >> 1;
+      if (k >= npairs) continue;
+      const float Ar = acc_re[r] * out_scale, Ai = acc_im[r] * out_scale;
+      const float Br = acc_re[r + 1] * out_scale, Bi = acc_im[r + 1] * out_scale;
+      float2 v1, v2;
+      int q1, q2;
+      if (k == 0) {
+        q1 = 0; v1 = make_float2(Ar, Ai);
+        q2 = (T % 2 == 0) ? h : -1; v2 = make_float2(Br, Bi);
+      } else {
+        const float2 vq = make_float2(Ar - Bi, Ai + Br);
+        const float2 vm = make_float2(Ar + Bi, Ai - Br);
+        q1 = k; q2 = T - k;
+        v1 = DIR > 0 ? vq : vm;
+        v2 = DIR > 0 ? vm : vq;
+      }
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int q = o == 0 ? q1 : q2;
+        if (q < 0) continue;
+        const float2 V = o == 0 ? v1 : v2;
+        const size_t idx = (size_t)q * P + p;
+        if constexpr (EPI == EPI_STORE) {
+          reinterpret_cast<float2*>(out)[idx] = V;
+        } else if constexpr (EPI == EPI_ABS) {
+          reinterpret_cast<float*>(out)[idx] = sqrtf(V.x * V.x + V.y * V.y);
+        } else {
+          const double a2 = (double)V.x * V.x + (double)V.y * V.y;
+          loss += a2 * a2;
+          const float sx = V.x * gamma_scale, sy = V.y * gamma_scale;
+          const float m2 = 4.0f * (sx * sx + sy * sy);
+          reinterpret_cast<float2*>(out)[idx] = make_float2(m2 * sx, m2 * sy);
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_GAMMA) {
+    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+    if (l == 0) red[w] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int i = 0; i < WAVES; ++i) s += red[i];
+      loss_partials[blockIdx.x] = s;
+    }
+  }
+}
+
+template <int PREC, int KC, int WAVES, int DIR, int EPI>
+static hipError_t depth_go(int grid, hipStream_t s, const void* in, const void* amat, void* out, int T, int T_pad,
+                           int P, int slabs, float out_scale, float gamma_scale, double* partials) {
+  hipLaunchKernelGGL((k_depth<PREC, KC, WAVES, DIR, EPI>), dim3(grid), dim3(WAVES * 64), 0, s,
+                     reinterpret_cast<const uint2*>(in), amat, out, T, T_pad, P, slabs, out_scale, gamma_scale,
+                     partials);
+  return hipGetLastError();
+}
+
+template <int PREC, int KC, int WAVES>
+static hipError_t depth_dir_epi(int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
+                                void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part) {
+  if (dir > 0) {
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, +1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    if (epi == EPI_ABS) return depth_go<PREC, KC, WAVES, +1, EPI_ABS>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    if constexpr (PREC == DP_F32)
+      return depth_go<PREC, KC, WAVES, +1, EPI_GAMMA>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    return hipErrorInvalidValue;
+  }
+  if constexpr (PREC == DP_F32) {
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, -1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int PREC, int KC>
+static hipError_t depth_waves(int waves, int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
+                              void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part) {
+  switch (waves) {
+    case 1: return depth_dir_epi<PREC, KC, 1>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 2: return depth_dir_epi<PREC, KC, 2>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 4: return depth_dir_epi<PREC, KC, 4>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 8: return depth_dir_epi<PREC, KC, 8>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC>
+static hipError_t depth_kc(int KC, int waves, int dir, int epi, int grid, hipStream_t s, const void* in,
+                           const void* amat, void* out, int T, int T_pad, int P, int slabs, float os, float gs,
+                           double* part) {
+  switch (KC) {
+    case 32: return depth_waves<PREC, 32>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 64: return depth_waves<PREC, 64>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 128: return depth_waves<PREC, 128>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 256: return depth_waves<PREC, 256>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int depth_grid(int T, int P, int cu_count) {
+  DepthLayout L = depth_layout(T);
+  const int ntiles = (P / PT) * L.slabs;
+  int per_cu = 8 / L.waves;          // waves per CU target ~8
+  if (per_cu < 1) per_cu = 1;
+  const int g = cu_count * per_cu;
+  return ntiles < g ? ntiles : g;
+}
+
+hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat, void* out,
+                        int sigma, int gamma_exp, double* partials, int grid, hipStream_t s) {
+  DepthLayout L = depth_layout(T);
+  const float os = ldexpf(1.0f, sigma);
+  const float gs = ldexpf(1.0f, -gamma_exp);
+  switch (prec) {
+    case DP_F32: return depth_kc<DP_F32>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    case DP_F16: return depth_kc<DP_F16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    case DP_BF16: return depth_kc<DP_BF16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    case DP_F16_SPLIT: return depth_kc<DP_F16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    case DP_BF16_SPLIT: return depth_kc<DP_BF16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ssoct

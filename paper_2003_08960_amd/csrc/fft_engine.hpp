@@ -1,0 +1,225 @@
+// Register/LDS Stockham FFT engine for gfx950 (wave64).
+//
+// One FFT of size N (power of two, 16..2048) is computed by a group of
+// G = N/16 threads; every thread holds 16 complex values in registers.
+// Passes are radix-16 while 16 divides the remaining length, then one pass of
+// radix 2, 4 or 8.  Between passes the data moves through LDS in the
+// self-sorting (Stockham) order, so input and output are both in natural
+// order and no bit reversal is needed.
+//
+// Direction DIR = +1 computes X[k] = sum_n x[n] exp(+2 pi i n k / N), the
+// kernel of the Fresnel transform (Eq. 6 expanded, positive exponent);
+// DIR = -1 is its adjoint.
+//
+// Register convention shared by every kernel that uses the engine:
+//   input : v[k] = x[j + k G]                      (k = 0..15)
+//   output: v[e] = X[j + out_offset<N>(e)]         (e = 0..15)
+// so for every register slot the G threads of a group touch G consecutive
+// elements (coalesced global loads and stores).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssoct {
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// multiply by DIR * i
+template <int DIR>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+  return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by exp(DIR * i * theta) with cos = c, sin = s (compile-time constants)
+template <int DIR>
+__device__ __forceinline__ float2 rot(float2 a, float c, float s) {
+  const float sd = DIR > 0 ? s : -s;
+  return make_float2(a.x * c - a.y * sd, a.y * c + a.x * sd);
+}
+// exp(DIR i pi/4) and exp(DIR i 3pi/4)
+template <int DIR>
+__device__ __forceinline__ float2 rot8_1(float2 a) {
+  const float h = 0.70710678118654752440f;
+  return DIR > 0 ? make_float2((a.x - a.y) * h, (a.y + a.x) * h) : make_float2((a.x + a.y) * h, (a.y - a.x) * h);
+}
+template <int DIR>
+__device__ __forceinline__ float2 rot8_3(float2 a) {
+  const float h = 0.70710678118654752440f;
+  return DIR > 0 ? make_float2((-a.x - a.y) * h, (a.x - a.y) * h) : make_float2((a.y - a.x) * h, (-a.y - a.x) * h);
+}
+
+// ---------------------------------------------------------------- small DFTs (natural order out)
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  float2 a0 = cadd(x0, x2), a1 = csub(x0, x2);
+  float2 a2 = cadd(x1, x3), a3 = mul_i<DIR>(csub(x1, x3));
+  x0 = cadd(a0, a2);
+  x2 = csub(a0, a2);
+  x1 = cadd(a1, a3);
+  x3 = csub(a1, a3);
+}
+
+// 8 = 2 x 4: n = n2 + 2 n1, k = k1 + 4 k2
+template <int DIR>
+__device__ __forceinline__ void dft8(float2* v) {
+  dft4<DIR>(v[0], v[2], v[4], v[6]);
+  dft4<DIR>(v[1], v[3], v[5], v[7]);
+  v[3] = rot8_1<DIR>(v[3]);
+  v[5] = mul_i<DIR>(v[5]);
+  v[7] = rot8_3<DIR>(v[7]);
+  float2 X[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    X[k1] = cadd(v[2 * k1], v[2 * k1 + 1]);
+    X[k1 + 4] = csub(v[2 * k1], v[2 * k1 + 1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = X[k];
+}
+
+// 16 = 4 x 4: n = n2 + 4 n1, k = k1 + 4 k2
+template <int DIR>
+__device__ __forceinline__ void dft16(float2* v) {
+  const float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  const float s1 = 0.38268343236508977173f;  // sin(pi/8)
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<DIR>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+  // Y[n2][k1] sits in v[n2 + 4 k1]; twiddle exp(DIR 2 pi i n2 k1 / 16)
+  v[1 + 4] = rot<DIR>(v[1 + 4], c1, s1);       // e = 1
+  v[1 + 8] = rot8_1<DIR>(v[1 + 8]);            // e = 2
+  v[1 + 12] = rot<DIR>(v[1 + 12], s1, c1);     // e = 3
+  v[2 + 4] = rot8_1<DIR>(v[2 + 4]);            // e = 2
+  v[2 + 8] = mul_i<DIR>(v[2 + 8]);             // e = 4
+  v[2 + 12] = rot8_3<DIR>(v[2 + 12]);          // e = 6
+  v[3 + 4] = rot<DIR>(v[3 + 4], s1, c1);       // e = 3
+  v[3 + 8] = rot8_3<DIR>(v[3 + 8]);            // e = 6
+  v[3 + 12] = rot<DIR>(v[3 + 12], -c1, -s1);   // e = 9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<DIR>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // X[k1 + 4 k2] sits in v[4 k1 + k2]
+  float2 X[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) X[k] = v[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = X[k];
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_small(float2* v) {
+  if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+  else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else dft16<DIR>(v);
+}
+
+// ---------------------------------------------------------------- plan (compile time)
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+template <int N>
+struct FFTShape {
+  static_assert(N >= 16 && N <= 2048 && (N & (N - 1)) == 0, "N must be a power of two in [16, 2048]");
+  static constexpr int G = N / 16;                         // threads per FFT
+  static constexpr int LOG = ilog2(N);
+  static constexpr int P16 = LOG / 4;                      // radix-16 passes
+  static constexpr int L = N >> (4 * P16);                 // last radix (1 = none)
+  static constexpr int LDS = N + (N >> 4);                 // padded complex slots per FFT
+};
+
+// LDS slot of element i (one pad slot every 16 keeps stride-16 writes conflict-free)
+__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+
+// output register e of thread j holds element j + out_offset<N>(e)
+template <int N>
+__device__ __forceinline__ constexpr int out_offset(int e) {
+  using S = FFTShape<N>;
+  if constexpr (S::L == 1) {
+    return e * S::G;
+  } else {
+    return S::G * (e / S::L) + (e % S::L) * (N / S::L);
+  }
+}
+
+// Twiddle exp(DIR 2 pi i idx / N) from the table tw[idx] = exp(+2 pi i idx / N).
+template <int DIR>
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int idx) {
+  float2 w = tw[idx];
+  return DIR > 0 ? w : cconj(w);
+}
+
+// Full N-point FFT of one group.  `lds` points to this group's LDS region of
+// FFTShape<N>::LDS complex slots with element stride `ls` (1 for row FFTs,
+// C for a C-column tile).  Every thread of the workgroup must call this the
+// same number of times: the exchanges use workgroup barriers.
+template <int N, int DIR>
+__device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, int ls,
+                                          const float2* __restrict__ tw) {
+  using S = FFTShape<N>;
+  constexpr int G = S::G;
+  int Ns = 1;
+#pragma unroll
+  for (int p = 0; p < S::P16; ++p) {
+    if (p > 0) {
+      const int kk = j % Ns;
+      const int step = kk * (N / (Ns * 16));
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<DIR>(tw, step * r));
+    }
+    dft16<DIR>(v);
+    const bool last = (p == S::P16 - 1) && (S::L == 1);
+    if (!last) {
+      const int base = (j / Ns) * Ns * 16 + (j % Ns);
+      __syncthreads();  // previous reads of this region are complete
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds[lds_slot(base + k * Ns) * ls] = v[k];
+      __syncthreads();
+      Ns *= 16;
+      if constexpr (S::L == 1) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+      } else {
+        if (p < S::P16 - 1) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+        }
+      }
+    }
+  }
+  if constexpr (S::L > 1) {
+    constexpr int L = S::L;
+    constexpr int NB = 16 / L;  // butterflies per thread
+    // Ns == N / L here; butterfly b = j + G i reads x[b + k N/L]
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+#pragma unroll
+      for (int k = 0; k < L; ++k) v[i * L + k] = lds[lds_slot(j + G * i + k * (N / L)) * ls];
+    }
+    if constexpr (S::P16 > 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int b = j + G * i;  // b < N/L = Ns, so kk = b
+#pragma unroll
+        for (int k = 1; k < L; ++k) v[i * L + k] = cmul(v[i * L + k], twiddle<DIR>(tw, b * k));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) dft_small<L, DIR>(&v[i * L]);
+  }
+}
+
+}  // namespace ssoct

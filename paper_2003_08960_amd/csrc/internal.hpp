@@ -1,0 +1,117 @@
+// Internal interfaces between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ssoct {
+
+// Per (frame, FFT position) entry of the rescale/chirp tables.  FFT position i
+// holds the original sample i' = (i + N/2) mod N (the input half-swap that,
+// with the (-1)^i' sign folded into `fac`, turns the centred DFT of Eq. 6 into
+// a plain DFT).  `i0`, `f`: bilinear source index and weight of Eq. 5;
+// `fac`: (-1)^i' exp(-i alpha_t c^2) (times exp(i phi_t) and the Eq. 6
+// prefactor for the row table).
+struct __align__(16) AxisTab {
+  int i0;
+  float f;
+  float2 fac;
+};
+
+// Storage of the hologram stack H[t][pixel] between the Fresnel stage and the
+// depth transform.  All formats use 8 bytes per complex pixel.
+enum HFormat : int {
+  HF_F32 = 0,   // float2 (re, im)
+  HF_F16 = 1,   // 4 x fp16: re_hi, re_lo, im_hi, im_lo, scaled by 2^-sigma
+  HF_BF16 = 2,  // 4 x bf16: re_hi, re_lo, im_hi, im_lo
+};
+
+// Depth-transform operand precision.
+enum DepthPrec : int {
+  DP_F32 = 0,
+  DP_F16 = 1,
+  DP_BF16 = 2,
+  DP_F16_SPLIT = 3,
+  DP_BF16_SPLIT = 4,
+};
+
+// Epilogue of the depth transform.
+enum DepthEpi : int {
+  EPI_STORE = 0,      // complex volume V[q][pixel]
+  EPI_ABS = 1,        // |V| as float
+  EPI_GAMMA = 2,      // Gamma^ = 4 |V^|^2 V^ with V^ = 2^-e V, plus FP64 partials of sum |V|^4
+};
+
+// Per-frame scalar parameters in device memory (FP64), 4 doubles per frame
+// followed by globals; filled on the host, consumed by the table kernels.
+struct ParamLayout {
+  static constexpr int PER_FRAME = 4;  // s_t, kappa_t (cycles per c^2), row phase (cycles), row amplitude
+  __host__ __device__ static size_t globals(int T) { return (size_t)PER_FRAME * T; }
+  // globals: [0] kappa_out (cycles per c^2, Eq. 6 output phase), [1..15] aberration polynomial
+  //          coefficients (rad) in monomial order, [16] aberration flag
+  static constexpr int G_KAPPA_OUT = 0;
+  static constexpr int G_POLY = 1;
+  static constexpr int G_HAS_ABERR = 16;
+  static constexpr int N_GLOBALS = 17;
+  __host__ __device__ static size_t count(int T) { return globals(T) + N_GLOBALS; }
+};
+
+// Monomial order used for aberration phases and gradient moments: x^a y^b with
+// (a, b) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2) (3,0) (2,1) (1,2) (0,3)
+//          (4,0) (3,1) (2,2) (1,3) (0,4)
+constexpr int N_MONO = 15;
+
+struct DepthLayout {
+  int T;        // frames
+  int KC;       // frames per K chunk (32, 64, 128 or 256)
+  int T_pad;    // T rounded up to KC
+  int rows;     // real rows of the depth matrix (T, or T + 1 for odd T)
+  int M_pad;    // rows rounded up to 32
+  int nrb;      // row blocks of 32
+  int waves;    // waves per workgroup (row blocks per slab, <= 8)
+  int slabs;    // ceil(nrb / waves)
+};
+DepthLayout depth_layout(int T);
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows, AxisTab* cols,
+                              hipStream_t s);
+hipError_t launch_misc_tables(const double* params, int T, int N, float2* tw, float2* outfac,
+                              float2* aberr, hipStream_t s);
+hipError_t launch_depth_tables(int T, float* a_f32, uint4* a_f16, uint4* a_bf16, hipStream_t s);
+
+// Forward Fresnel stage on frames [t0, t0 + F): rescale + chirp + row DFT into
+// `inter` ([F][N][N] complex64), then column DFT into H (format `fmt`).
+hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
+                           const AxisTab* cols, const float2* tw, const float2* aberr,
+                           const float2* outfac, float2* inter, hipStream_t s);
+hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
+                           const float2* outfac, void* H, int fmt, int sigma, hipStream_t s);
+
+// Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
+// into `inter`, then row DFT^- fused with the recomputed row input and the
+// per-frame FP64 moments of Im(conj(g) z) (partials [T][nblk][N_MONO]).
+hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw,
+                               float2* inter, hipStream_t s);
+hipError_t launch_row_pass_adj(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
+                               const AxisTab* cols, const float2* tw, const float2* aberr,
+                               const float2* inter, double* partials, hipStream_t s);
+int row_adj_blocks(int N);
+
+// Depth transform over the whole stack: out[q][p] = sum_t W[q][t] in[t][p]
+// (dir = +1) or sum_t conj(W[q][t]) in[t][p] (dir = -1).
+hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat,
+                        void* out, int sigma, int gamma_exp, double* partials, int grid,
+                        hipStream_t s);
+int depth_grid(int T, int P, int cu_count);
+
+hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,
+                       float* cut_xy, float* cut_xz, float* cut_yz, hipStream_t s);
+
+// Final reduction of the gradient: out[0] = L (or 0), out[1] = dL/dz,
+// out[2..16] = dL/dc, out[17..17+T) = dL/dphi.
+hipError_t launch_grad_finish(int T, int N, int nblk, const double* mono_partials,
+                              const double* loss_partials, int n_loss, const double* alpha_over_z,
+                              const double* zmat, double grad_scale, double* out, hipStream_t s);
+
+}  // namespace ssoct

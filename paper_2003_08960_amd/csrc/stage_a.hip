@@ -1,0 +1,370 @@
+// Fresnel stage (steps 1-2 of the flowchart, Fig. 3): chromatic rescale by
+// linear interpolation (Eq. 5) fused with the chirp of Eq. 6 into the row
+// DFT, then the column DFT, which writes the hologram stack H[t][pixel] in the
+// operand format of the depth transform.  Adjoint kernels (DIR = -1) serve
+// the gradient of the sharpness loss.
+//
+// Index conventions: FFT position i carries original sample (i + N/2) mod N;
+// the tables already hold (-1)^i' and the chirp, so both passes are plain
+// positive-exponent DFTs and the output lands at natural (u, v).
+#include "fft_engine.hpp"
+#include "internal.hpp"
+
+namespace ssoct {
+
+// rows handled by one row-pass workgroup, and its size
+template <int N>
+struct RowCfg {
+  static constexpr int G = FFTShape<N>::G;
+  static constexpr int ROWS = (256 / G) < N ? (256 / G) : N;
+  static constexpr int THREADS = ROWS * G;
+};
+// columns handled by one column-pass workgroup (>= 8 so that every row segment is >= 64 B)
+template <int N>
+struct ColCfg {
+  static constexpr int C0 = 4096 / N;
+  static constexpr int C = C0 < 8 ? 8 : (C0 > N ? N : C0);
+  static constexpr int THREADS = C * FFTShape<N>::G;
+};
+
+// y-lerp of the two source rows of Eq. 5 for one output row into rbuf[0..N):
+// thread j of the group covers source columns [16 j, 16 j + 16).
+template <int N>
+__device__ __forceinline__ void lerp_rows(const uint16_t* __restrict__ I, int y0, float fy, float* rbuf, int j) {
+  const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
+  const uint4* r0 = reinterpret_cast<const uint4*>(I + (size_t)y0 * N + 16 * j);
+  const uint4* r1 = reinterpret_cast<const uint4*>(I + (size_t)y1 * N + 16 * j);
+  uint4 a[2] = {r0[0], r0[1]};
+  uint4 b[2] = {r1[0], r1[1]};
+  float out[16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t wa[4] = {a[h].x, a[h].y, a[h].z, a[h].w};
+    const uint32_t wb[4] = {b[h].x, b[h].y, b[h].z, b[h].w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float a0 = (float)(wa[q] & 0xffffu), a1 = (float)(wa[q] >> 16);
+      const float b0 = (float)(wb[q] & 0xffffu), b1 = (float)(wb[q] >> 16);
+      out[8 * h + 2 * q] = a0 + fy * (b0 - a0);
+      out[8 * h + 2 * q + 1] = a1 + fy * (b1 - a1);
+    }
+  }
+  float4* dst = reinterpret_cast<float4*>(rbuf + 16 * j);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+}
+
+// Row input z[m][n] of the DFT at FFT position n (x-lerp of the y-lerped row,
+// times the separable chirp, dispersion, sign and optional aberration).
+template <int N, bool ABERR>
+__device__ __forceinline__ float2 row_input(const float* rbuf, const AxisTab& ct, float2 rowfac,
+                                            const float2* __restrict__ aberr_row, int n) {
+  const int x0 = ct.i0;
+  const int x1 = x0 + 1 < N ? x0 + 1 : N - 1;
+  const float r0 = rbuf[x0], r1 = rbuf[x1];
+  const float J = r0 + ct.f * (r1 - r0);
+  float2 fac = cmul(ct.fac, rowfac);
+  if constexpr (ABERR) fac = cmul(fac, aberr_row[n]);
+  return make_float2(J * fac.x, J * fac.y);
+}
+
+// ------------------------------------------------------------------ forward row pass
+template <int N, bool ABERR, bool EQ6>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass(
+    const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
+    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const float2* __restrict__ outfac, float2* __restrict__ inter) {
+  using S = FFTShape<N>;
+  using R = RowCfg<N>;
+  constexpr int G = S::G;
+  __shared__ float rbuf[R::ROWS][N];
+  __shared__ float2 xbuf[R::ROWS][S::LDS];
+  const int g = threadIdx.x / G, j = threadIdx.x % G;
+  const int m = blockIdx.x * R::ROWS + g;
+  const int f = blockIdx.y;
+  const int t = t0 + f;
+  const uint16_t* I = frames + (size_t)t * N * N;
+  const AxisTab rt = rows[(size_t)t * N + m];
+  lerp_rows<N>(I, rt.i0, rt.f, rbuf[g], j);
+  __syncthreads();
+  const AxisTab* ctab = cols + (size_t)t * N;
+  const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int n = j + k * G;
+    v[k] = row_input<N, ABERR>(rbuf[g], ctab[n], rt.fac, arow, n);
+  }
+  fft_group<N, +1>(v, j, xbuf[g], 1, tw);
+  float2* dst = inter + ((size_t)f * N + m) * N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int vv = j + out_offset<N>(e);
+    float2 val = v[e];
+    if constexpr (EQ6) val = cmul(val, outfac[vv]);
+    dst[vv] = val;
+  }
+}
+
+// ------------------------------------------------------------------ H storage formats
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// hi + lo split of one real value, packed as hi | lo << 16
+template <int FMT>
+__device__ __forceinline__ uint32_t split_pack(float x) {
+  if constexpr (FMT == HF_F16) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);
+    return (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
+  } else {
+    const uint16_t h = bf16_rne(x);
+    const uint16_t l = bf16_rne(x - bf16_val(h));
+    return (uint32_t)h | ((uint32_t)l << 16);
+  }
+}
+
+template <int FMT>
+__device__ __forceinline__ void store_h(void* __restrict__ H, size_t idx, float2 val, float scale) {
+  if constexpr (FMT == HF_F32) {
+    reinterpret_cast<float2*>(H)[idx] = val;
+  } else {
+    uint2 w;
+    w.x = split_pack<FMT>(val.x * scale);
+    w.y = split_pack<FMT>(val.y * scale);
+    reinterpret_cast<uint2*>(H)[idx] = w;
+  }
+}
+
+// ------------------------------------------------------------------ column pass (both directions)
+// src, dst: frame 0 of this launch; frame f at + f N^2.  DIR = +1 writes H in
+// format FMT (and applies the Eq. 6 output phase when EQ6); DIR = -1 writes
+// complex64.
+template <int N, int DIR, int FMT, bool EQ6>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* __restrict__ src,
+                                                                 const float2* __restrict__ tw,
+                                                                 const float2* __restrict__ outfac,
+                                                                 void* __restrict__ dst, float scale) {
+  using S = FFTShape<N>;
+  constexpr int G = S::G;
+  constexpr int C = ColCfg<N>::C;
+  __shared__ float2 xbuf[S::LDS * C];
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+  const int col = blockIdx.x * C + c;
+  const size_t fo = (size_t)blockIdx.y * N * N;
+  const float2* s = src + fo + col;
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = s[(size_t)(j + k * G) * N];
+  fft_group<N, DIR>(v, j, xbuf + c, C, tw);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int u = j + out_offset<N>(e);
+    float2 val = v[e];
+    if constexpr (EQ6) val = cmul(val, outfac[u]);
+    store_h<FMT>(dst, fo + (size_t)u * N + col, val, scale);
+  }
+}
+
+// ------------------------------------------------------------------ adjoint row pass + moments
+// g[m][n] = DFT^-_v inter[f][m][v]; u = Im(conj(g) z) with z recomputed as in
+// the forward row pass; per-frame FP64 moments sum u x^a y^b (a + b <= 4) at
+// the original sample (x, y) = (c_n', c_m') sqrt(2) / N.
+template <int N, bool ABERR>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
+    const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
+    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const float2* __restrict__ inter, double* __restrict__ partials) {
+  using S = FFTShape<N>;
+  using R = RowCfg<N>;
+  constexpr int G = S::G;
+  constexpr int NW = (R::THREADS + 63) / 64;
+  __shared__ float rbuf[R::ROWS][N];
+  __shared__ float2 xbuf[R::ROWS][S::LDS];
+  __shared__ double red[NW][N_MONO];
+  const int g = threadIdx.x / G, j = threadIdx.x % G;
+  const int m = blockIdx.x * R::ROWS + g;
+  const int f = blockIdx.y;
+  const int t = t0 + f;
+  const uint16_t* I = frames + (size_t)t * N * N;
+  const AxisTab rt = rows[(size_t)t * N + m];
+  lerp_rows<N>(I, rt.i0, rt.f, rbuf[g], j);
+  const float2* srow = inter + ((size_t)f * N + m) * N;
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = srow[j + k * G];
+  fft_group<N, -1>(v, j, xbuf[g], 1, tw);
+  __syncthreads();  // rbuf complete for every group
+  const AxisTab* ctab = cols + (size_t)t * N;
+  const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+  const double inv = 1.4142135623730950488 / (double)N;
+  const int half = N >> 1;
+  const double y = (double)(m < half ? m : m - N) * inv;
+  const double y2 = y * y;
+  double acc[N_MONO];
+#pragma unroll
+  for (int k = 0; k < N_MONO; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int n = j + out_offset<N>(e);
+    const float2 z = row_input<N, ABERR>(rbuf[g], ctab[n], rt.fac, arow, n);
+    const float2 gg = v[e];
+    const double u = (double)gg.x * (double)z.y - (double)gg.y * (double)z.x;  // Im(conj(g) z)
+    const double x = (double)(n < half ? n : n - N) * inv;
+    const double x2 = x * x;
+    const double ux = u * x, uy = u * y;
+    acc[0] += u;
+    acc[1] += ux;
+    acc[2] += uy;
+    acc[3] += ux * x;
+    acc[4] += ux * y;
+    acc[5] += uy * y;
+    acc[6] += ux * x2;
+    acc[7] += ux * x * y;
+    acc[8] += ux * y2;
+    acc[9] += uy * y2;
+    acc[10] += ux * x * x2;
+    acc[11] += ux * x2 * y;
+    acc[12] += ux * x * y2;
+    acc[13] += ux * y2 * y;
+    acc[14] += uy * y * y2;
+  }
+  // wave reduction, then across waves in fixed order
+  constexpr int WIDTH = R::THREADS < 64 ? R::THREADS : 64;  // lanes that exist in a wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N_MONO; ++k) {
+    double a = acc[k];
+    for (int o = WIDTH / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, WIDTH);
+    acc[k] = a;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N_MONO; ++k) red[wv][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < N_MONO) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+    partials[((size_t)t * gridDim.x + blockIdx.x) * N_MONO + threadIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int N>
+static hipError_t row_pass_n(int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                             const float2* tw, const float2* aberr, const float2* outfac, float2* inter,
+                             hipStream_t s) {
+  using R = RowCfg<N>;
+  dim3 grid(N / R::ROWS, F), block(R::THREADS);
+  if (aberr && outfac)
+    hipLaunchKernelGGL((k_row_pass<N, true, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+  else if (aberr)
+    hipLaunchKernelGGL((k_row_pass<N, true, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+  else if (outfac)
+    hipLaunchKernelGGL((k_row_pass<N, false, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+  else
+    hipLaunchKernelGGL((k_row_pass<N, false, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
+                             int fmt, int sigma, hipStream_t s) {
+  using C = ColCfg<N>;
+  dim3 grid(N / C::C, F), block(C::THREADS);
+  const float scale = ldexpf(1.0f, -sigma);
+  char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
+  const bool eq6 = outfac != nullptr;
+#define SSOCT_COL(FMT, E) \
+  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E>), grid, block, 0, s, inter, tw, outfac, (void*)dst, scale)
+  if (fmt == HF_F32) { if (eq6) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
+  else if (fmt == HF_F16) { if (eq6) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
+  else { if (eq6) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
+#undef SSOCT_COL
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* tw, float2* inter, hipStream_t s) {
+  using C = ColCfg<N>;
+  dim3 grid(N / C::C, F), block(C::THREADS);
+  const float2* src = B + (size_t)t0 * N * N;
+  hipLaunchKernelGGL((k_col_pass<N, -1, HF_F32, false>), grid, block, 0, s, src, tw, (const float2*)nullptr,
+                     (void*)inter, 1.0f);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t row_pass_adj_n(int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                                 const float2* tw, const float2* aberr, const float2* inter, double* partials,
+                                 hipStream_t s) {
+  using R = RowCfg<N>;
+  dim3 grid(N / R::ROWS, F), block(R::THREADS);
+  if (aberr)
+    hipLaunchKernelGGL((k_row_pass_adj<N, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, inter, partials);
+  else
+    hipLaunchKernelGGL((k_row_pass_adj<N, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, inter, partials);
+  return hipGetLastError();
+}
+
+#define SSOCT_DISPATCH_N(N, CALL)        \
+  switch (N) {                           \
+    case 16: return CALL(16);            \
+    case 32: return CALL(32);            \
+    case 64: return CALL(64);            \
+    case 128: return CALL(128);          \
+    case 256: return CALL(256);          \
+    case 512: return CALL(512);          \
+    case 1024: return CALL(1024);        \
+    case 2048: return CALL(2048);        \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                           const float2* tw, const float2* aberr, const float2* outfac, float2* inter, hipStream_t s) {
+#define CALL(n) row_pass_n<n>(F, t0, frames, rows, cols, tw, aberr, outfac, inter, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
+                           int fmt, int sigma, hipStream_t s) {
+#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw, float2* inter, hipStream_t s) {
+#define CALL(n) col_pass_adj_n<n>(F, t0, B, tw, inter, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_row_pass_adj(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
+                               const AxisTab* cols, const float2* tw, const float2* aberr, const float2* inter,
+                               double* partials, hipStream_t s) {
+#define CALL(n) row_pass_adj_n<n>(F, t0, frames, rows, cols, tw, aberr, inter, partials, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+int row_adj_blocks(int N) {
+  switch (N) {
+    case 16: return 16 / RowCfg<16>::ROWS;
+    case 32: return 32 / RowCfg<32>::ROWS;
+    case 64: return 64 / RowCfg<64>::ROWS;
+    case 128: return 128 / RowCfg<128>::ROWS;
+    case 256: return 256 / RowCfg<256>::ROWS;
+    case 512: return 512 / RowCfg<512>::ROWS;
+    case 1024: return 1024 / RowCfg<1024>::ROWS;
+    case 2048: return 2048 / RowCfg<2048>::ROWS;
+    default: return 0;
+  }
+}
+
+}  // namespace ssoct

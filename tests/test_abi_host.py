@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/ssoct.h declares, and rejects bad arguments before any
+HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssoct.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2003_08960_amd import native
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2003_08960_amd import build
+        build.build()
+    return native.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssoct_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ssoct_plan_create", "ssoct_render", "ssoct_cuts", "ssoct_backward",
+                     "ssoct_backward_sharpness", "ssoct_workspace_size"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2003_08960_amd import native
+    names = declared_functions()
+    assert sorted(native.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version(lib):
+    assert lib.ssoct_version() == 1
+
+
+def test_workspace_size(lib):
+    from paper_2003_08960_amd import native
+    T, N = 256, 1024
+    stack = T * N * N * 8
+    ws = lib.ssoct_workspace_size(T, N, 0)
+    assert stack < ws <= stack + (65 << 20)
+    wsb = lib.ssoct_workspace_size(T, N, native.BACKWARD)
+    assert wsb >= 2 * stack
+    for bad in ((0, 128), (1025, 128), (8, 100), (8, 8), (8, 4096)):
+        assert lib.ssoct_workspace_size(bad[0], bad[1], 0) == 0
+
+
+def test_plan_create_rejects_bad_sizes(lib):
+    from paper_2003_08960_amd import native
+    for T, N in ((0, 128), (1025, 128), (4, 100), (4, 8), (4, 4096)):
+        h = ctypes.c_void_p(1234)
+        rc = lib.ssoct_plan_create(ctypes.byref(h), T, N, 0, None)
+        assert rc == native.EUNSUPPORTED
+        assert not h.value
+        assert lib.ssoct_last_error()
+    h = ctypes.c_void_p()
+    assert lib.ssoct_plan_create(ctypes.byref(h), 8, 64, native.PREC_FP32 | native.SPLIT, None) == native.EINVAL
+    assert lib.ssoct_plan_create(ctypes.byref(h), 8, 64, 3, None) == native.EINVAL
+    assert lib.ssoct_plan_create(None, 8, 64, 0, None) == native.EINVAL
+
+
+def test_null_plan_is_rejected(lib):
+    from paper_2003_08960_amd import native
+    lam = (ctypes.c_double * 4)(1e-6, 1e-6, 1e-6, 1e-6)
+    assert lib.ssoct_render(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL
+    assert lib.ssoct_cuts(None, None, 0, 0, 0, None, None, None) == native.EINVAL
+    assert lib.ssoct_backward(None, None, lam, 1e-5, 0.1, None, None, None, None, 0, None) == native.EINVAL
+    assert lib.ssoct_backward_sharpness(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL
+    ms = (ctypes.c_float * 3)()
+    assert lib.ssoct_profile_read(None, ms) == native.EINVAL
+    assert lib.ssoct_plan_destroy(None) == native.OK
+    assert b"NULL" in lib.ssoct_last_error() or b"null" in lib.ssoct_last_error()
+
+
+def test_binding_raises_with_message(lib):
+    from paper_2003_08960_amd import native
+    with pytest.raises(native.SsoctError) as e:
+        native.check(native.EINVAL)
+    assert "EINVAL" in str(e.value)
+    assert native.check(native.WARN_UNDERSAMPLED) == native.WARN_UNDERSAMPLED

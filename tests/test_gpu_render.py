@@ -1,0 +1,198 @@
+"""GPU parity of ssoct_render / ssoct_cuts against the FP64 oracle.
+
+Bars: relative L2 error over all voxels <= 1e-5 for the FP32 path and
+<= 1e-4 for the split FP16/BF16 depth transform; plain FP16/BF16 errors are
+reported (they are expected above 1e-4) with a sanity bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssoct_oracle as O
+from paper_2003_08960_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_BAR = 1e-5
+SPLIT_BAR = 1e-4
+PLAIN_SANITY = 2e-2
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def gpu_render(frames, lam, pitch, z, precision="fp32", disp=None, zern=None, **kw):
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = frames.shape
+    print(f"\n[gpu] render T={T} N={N} precision={precision} disp={disp is not None} "
+          f"zern={zern is not None} {kw}", flush=True)
+    plan = Plan(T, N, precision=precision, **kw)
+    fr = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+    V = plan.render(fr, lam, pitch, z, disp, zern)
+    torch.cuda.synchronize()
+    return plan, fr, V
+
+
+def random_case(T, N, seed, lo=0, hi=65535):
+    frames = synth.random_frames(T, N, seed, lo, hi)
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9)
+    return frames, lam
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.make_config("tiny")
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return synth.make_config("mid")
+
+
+# ---------------------------------------------------------------- small sizes, every FFT length class
+
+@pytest.mark.parametrize("T,N", [(4, 16), (5, 32), (7, 64), (33, 128), (3, 256), (2, 512), (2, 1024), (1, 2048)])
+def test_fp32_small_sizes(gpu_lib, T, N):
+    frames, lam = random_case(T, N, seed=100 + N + T)
+    _, _, V = gpu_render(frames, lam, 20e-6, 0.05)
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"rel-L2 {err:.3e}")
+    assert err <= FP32_BAR
+
+
+@pytest.mark.parametrize("T", [1, 2, 31, 33, 64, 100, 127, 129, 256, 300])
+def test_fp32_ragged_sweeps(gpu_lib, T):
+    """Sweep lengths that are not multiples of the depth-transform tiles (zero-padded K, odd T)."""
+    N = 32
+    frames, lam = random_case(T, N, seed=7 * T)
+    _, _, V = gpu_render(frames, lam, 20e-6, 0.05)
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"T={T} rel-L2 {err:.3e}")
+    assert err <= FP32_BAR
+
+
+# ---------------------------------------------------------------- tiny workload (T=32, N=128)
+
+def test_tiny_fp32_and_cuts(gpu_lib, tiny):
+    plan, fr, V = gpu_render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
+    err = rel_l2(V.cpu().numpy(), ref)
+    err_nodc = rel_l2(V.cpu().numpy()[1:], ref[1:])
+    print(f"rel-L2 {err:.3e}  (bins q>0: {err_nodc:.3e})")
+    assert err <= FP32_BAR
+    # cuts at a scatterer and at the default position
+    for (x0, y0, q0) in ((int(tiny.scatterers[0, 1]), int(tiny.scatterers[0, 0]), int(tiny.scatterers[0, 2])),
+                         (64, 64, 8)):
+        xy, xz, yz = plan.cuts(V, x0, y0, q0)
+        rxy, rxz, ryz = O.cuts(ref, x0, y0, q0)
+        for a, b in ((xy, rxy), (xz, rxz), (yz, ryz)):
+            assert rel_l2(a.cpu().numpy(), b) <= FP32_BAR
+        # the cuts are exactly |V| of the GPU volume
+        M = V.abs()
+        assert torch.equal(xy, M[q0]) or rel_l2(xy.cpu().numpy(), M[q0].cpu().numpy()) < 1e-7
+
+
+def test_tiny_options(gpu_lib, tiny):
+    rng = np.random.default_rng(3)
+    T = tiny.frames.shape[0]
+    disp = rng.uniform(-3, 3, T)
+    zern = rng.normal(0, 0.5, 15)
+    cases = [dict(exact_chirp=True), dict(disp=disp), dict(zern=zern), dict(disp=disp, zern=zern, exact_chirp=True),
+             dict(eq6_phase=True)]
+    for kw in cases:
+        k = dict(kw)
+        d = k.pop("disp", None)
+        z_ = k.pop("zern", None)
+        _, _, V = gpu_render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, disp=d, zern=z_, **k)
+        ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, d, z_,
+                       exact_chirp=k.get("exact_chirp", False), eq6_phase=k.get("eq6_phase", False))
+        err = rel_l2(V.cpu().numpy(), ref)
+        print(f"{sorted(kw)} rel-L2 {err:.3e}")
+        assert err <= FP32_BAR
+
+
+def test_tiny_focus_ground_truth(gpu_lib, tiny):
+    _, _, V = gpu_render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
+    M = V.abs().cpu().numpy()
+    for u, v, q, _ in tiny.scatterers:
+        u, v, q = int(u), int(v), int(q)
+        win = M[q, u - 2:u + 3, v - 2:v + 3]
+        assert np.unravel_index(np.argmax(win), win.shape) == (2, 2)
+
+
+def test_write_abs_and_power_cuts(gpu_lib, tiny):
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = tiny.frames.shape
+    fr = torch.from_numpy(tiny.frames).cuda()
+    plan = Plan(T, N, write_abs=True)
+    A = plan.render(fr, tiny.lam, tiny.pitch, tiny.z)
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
+    assert A.dtype == torch.float32
+    assert rel_l2(A.cpu().numpy(), np.abs(ref)) <= FP32_BAR
+    plan2 = Plan(T, N, cut_power=True)
+    V = plan2.render(fr, tiny.lam, tiny.pitch, tiny.z)
+    xy, xz, yz = plan2.cuts(V, 10, 20, 5)
+    rxy, rxz, ryz = O.cuts(ref, 10, 20, 5, power=True)
+    assert rel_l2(xy.cpu().numpy(), rxy) <= 3 * FP32_BAR
+    assert rel_l2(yz.cpu().numpy(), ryz) <= 3 * FP32_BAR
+
+
+def test_deterministic_and_table_cache(gpu_lib, tiny):
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = tiny.frames.shape
+    fr = torch.from_numpy(tiny.frames).cuda()
+    plan = Plan(T, N)
+    V1 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()
+    V2 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()
+    assert torch.equal(V1, V2)
+    V3 = plan.render(fr, tiny.lam, tiny.pitch, 0.2)          # new z: tables rebuilt
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, 0.2)
+    assert rel_l2(V3.cpu().numpy(), ref) <= FP32_BAR
+    V4 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z)
+    assert torch.equal(V1, V4)
+
+
+def test_bad_arguments_raise(gpu_lib, tiny):
+    from paper_2003_08960_amd import native
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = tiny.frames.shape
+    fr = torch.from_numpy(tiny.frames).cuda()
+    plan = Plan(T, N)
+    with pytest.raises(native.SsoctError):
+        plan.render(fr, tiny.lam, tiny.pitch, 0.0)
+    bad = np.array(tiny.lam)
+    bad[3] = -1
+    with pytest.raises(native.SsoctError):
+        plan.render(fr, bad, tiny.pitch, tiny.z)
+    with pytest.raises(native.SsoctError):
+        V = plan.render(fr, tiny.lam, tiny.pitch, tiny.z)
+        plan.cuts(V, N, 0, 0)
+    # undersampled distance: computed, with a warning status
+    plan.render(fr, tiny.lam, tiny.pitch, 0.01)
+    assert plan.last_status == native.WARN_UNDERSAMPLED
+
+
+# ---------------------------------------------------------------- mid workload (T=128, N=512)
+
+@pytest.mark.parametrize("precision,bar", [("fp32", FP32_BAR), ("fp16_split", SPLIT_BAR), ("bf16_split", SPLIT_BAR),
+                                           ("fp16", PLAIN_SANITY), ("bf16", PLAIN_SANITY)])
+def test_mid_precisions(gpu_lib, mid, precision, bar):
+    _, _, V = gpu_render(mid.frames, mid.lam, mid.pitch, mid.z, precision=precision)
+    ref = _mid_ref(mid)
+    Vn = V.cpu().numpy()
+    err = rel_l2(Vn, ref)
+    err_nodc = rel_l2(Vn[1:], ref[1:])
+    print(f"{precision}: rel-L2 {err:.3e} (bins q>0: {err_nodc:.3e})")
+    assert err <= bar
+
+
+_MID_REF = {}
+
+
+def _mid_ref(mid):
+    if "v" not in _MID_REF:
+        _MID_REF["v"] = O.render(mid.frames, mid.lam, mid.pitch, mid.z)
+    return _MID_REF["v"]
