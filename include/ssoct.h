@@ -140,9 +140,12 @@ int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const dou
                              double z, const double* disp_phase, const double* zernike, void* workspace,
                              size_t workspace_bytes, double* grad_out);
 
-/* With SSOCT_PROFILE: wait for the last ssoct_render of the plan and return
- * the elapsed milliseconds of its stages: ms[0] tables, ms[1] Fresnel stage
- * (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth transform. */
+/* With SSOCT_PROFILE every ssoct_render records HIP events on the plan's
+ * stream around its stages.  This call waits for the last recorded render
+ * and returns the mean elapsed milliseconds over the renders recorded since
+ * the previous call (at most the last 256): ms[0] tables, ms[1] Fresnel
+ * stage (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth
+ * transform, ms[3] the number of renders averaged.  Resets the record. */
 int ssoct_profile_read(ssoct_plan* plan, float* ms);
 
 #ifdef __cplusplus

@@ -137,7 +137,7 @@ class Plan:
         return out
 
     def profile_read(self):
-        """Stage times (ms) of the last render: (tables, fresnel stage, depth transform)."""
-        ms = (ctypes.c_float * 3)()
+        """Mean stage times (ms) since the last read: (tables, fresnel stage, depth transform, count)."""
+        ms = (ctypes.c_float * 4)()
         native.check(self.lib.ssoct_profile_read(self._h, ms))
         return tuple(ms)

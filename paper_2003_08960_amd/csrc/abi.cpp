@@ -130,8 +130,9 @@ struct ssoct_plan {
   double zmat[15][N_MONO];
   std::vector<double> cache;     // last parameter set the tables were built from
   bool have_aberr = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool ev_recorded = false;
+  static constexpr int MAXREC = 256;  // renders kept by the profiling record
+  std::vector<hipEvent_t> ev;          // [MAXREC][4] with SSOCT_PROFILE
+  int rec = 0;                         // renders recorded since the last read
 };
 
 namespace {
@@ -147,7 +148,7 @@ void plan_free(ssoct_plan* p) {
   (void)hipFree(p->a_f32);
   (void)hipFree(p->a_f16);
   (void)hipFree(p->a_bf16);
-  for (auto& e : p->ev)
+  for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
 }
@@ -342,9 +343,11 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess) e = hipMalloc(&p->a_f32, na32 * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&p->a_f16, na16 * sizeof(uint4));
   if (e == hipSuccess) e = hipMalloc(&p->a_bf16, na16 * sizeof(uint4));
-  if (e == hipSuccess && (flags & SSOCT_PROFILE))
+  if (e == hipSuccess && (flags & SSOCT_PROFILE)) {
+    p->ev.assign((size_t)ssoct_plan::MAXREC * 4, nullptr);
     for (auto& ev : p->ev)
       if (e == hipSuccess) e = hipEventCreate(&ev);
+  }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
@@ -382,7 +385,8 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
     return fail(SSOCT_EALIAS, "vol overlaps frames or workspace");
   SSOCT_HIP(hipSetDevice(p->device));
   const bool prof = (p->flags & SSOCT_PROFILE) != 0;
-  if (prof) SSOCT_HIP(hipEventRecord(p->ev[0], p->stream));
+  hipEvent_t* ev = prof ? &p->ev[(size_t)(p->rec % ssoct_plan::MAXREC) * 4] : nullptr;
+  if (prof) SSOCT_HIP(hipEventRecord(ev[0], p->stream));
   const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
   if (status < 0) return status;
   const int prec = depth_prec(p->flags);
@@ -392,15 +396,15 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
   const int sigma = fresnel_sigma(p, prec, pitch, z, lam1);
   char* ws = static_cast<char*>(workspace);
   void* H = ws + L.H;
-  if (prof) SSOCT_HIP(hipEventRecord(p->ev[1], p->stream));
+  if (prof) SSOCT_HIP(hipEventRecord(ev[1], p->stream));
   if (int rc = forward_stage_a(p, frames, H, reinterpret_cast<float2*>(ws + L.inter), fmt, sigma)) return rc;
-  if (prof) SSOCT_HIP(hipEventRecord(p->ev[2], p->stream));
+  if (prof) SSOCT_HIP(hipEventRecord(ev[2], p->stream));
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
   const int grid = depth_grid(T, N * N, p->cu);
   SSOCT_HIP(launch_depth(T, N * N, prec, +1, epi, H, amat_for(p, prec), vol, sigma, 0, nullptr, grid, p->stream));
   if (prof) {
-    SSOCT_HIP(hipEventRecord(p->ev[3], p->stream));
-    p->ev_recorded = true;
+    SSOCT_HIP(hipEventRecord(ev[3], p->stream));
+    ++p->rec;
   }
   return status;
 }
@@ -472,9 +476,23 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
 int ssoct_profile_read(ssoct_plan* p, float* ms) {
   if (int rc = check_plan(p)) return rc;
   if (!ms) return fail(SSOCT_EINVAL, "ms is NULL");
-  if (!(p->flags & SSOCT_PROFILE) || !p->ev_recorded) return fail(SSOCT_EINVAL, "no profiled render recorded");
-  SSOCT_HIP(hipEventSynchronize(p->ev[3]));
-  for (int i = 0; i < 3; ++i) SSOCT_HIP(hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
+  if (!(p->flags & SSOCT_PROFILE) || p->rec == 0) return fail(SSOCT_EINVAL, "no profiled render recorded");
+  const int n = p->rec < ssoct_plan::MAXREC ? p->rec : ssoct_plan::MAXREC;
+  const int last = (p->rec - 1) % ssoct_plan::MAXREC;
+  SSOCT_HIP(hipEventSynchronize(p->ev[(size_t)last * 4 + 3]));
+  double sum[3] = {0, 0, 0};
+  for (int r = 0; r < n; ++r) {
+    const int slot = (p->rec - 1 - r) % ssoct_plan::MAXREC;
+    hipEvent_t* e = &p->ev[(size_t)slot * 4];
+    for (int i = 0; i < 3; ++i) {
+      float t = 0.f;
+      SSOCT_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
+      sum[i] += t;
+    }
+  }
+  for (int i = 0; i < 3; ++i) ms[i] = (float)(sum[i] / n);
+  ms[3] = (float)n;
+  p->rec = 0;
   return SSOCT_OK;
 }
 

@@ -1,0 +1,139 @@
+"""GPU parity of the gradient entry points (ssoct_backward, ssoct_backward_sharpness)
+against the FP64 oracle's adjoint (itself pinned to finite differences on the CPU),
+plus finite differences of the GPU loss and the global-phase invariants."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssoct_oracle as O
+from paper_2003_08960_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def small_case(T, N, seed):
+    rng = np.random.default_rng(seed)
+    frames = synth.random_frames(T, N, seed)
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9)
+    return frames, lam, rng.uniform(-2, 2, T), rng.normal(0, 0.4, 15)
+
+
+@pytest.mark.parametrize("T,N,exact,with_params", [(6, 32, False, True), (6, 32, True, True), (5, 64, False, False),
+                                                  (33, 128, True, True)])
+def test_vjp_random_cotangent(gpu_lib, T, N, exact, with_params):
+    from paper_2003_08960_amd.api import Plan
+    frames, lam, phi, zc = small_case(T, N, seed=T * N)
+    if not with_params:
+        phi, zc = None, None
+    rng = np.random.default_rng(9)
+    G = (rng.standard_normal((T, N, N)) + 1j * rng.standard_normal((T, N, N))).astype(np.complex64)
+    print(f"\n[gpu] vjp T={T} N={N} exact={exact} params={with_params}", flush=True)
+    plan = Plan(T, N, backward=True, exact_chirp=exact)
+    g = plan.backward(torch.from_numpy(frames).cuda(), lam, 20e-6, 0.05, torch.from_numpy(G).cuda(), phi, zc)
+    g = g.cpu().numpy()
+    dz, dc, dphi = O.vjp(frames, lam, 20e-6, 0.05, G.astype(np.complex128), phi, zc, exact)
+    print(f"dz {g[1]:.6e} vs {dz:.6e}; dc rel {rel(g[2:17], dc):.2e}; dphi rel {rel(g[17:], dphi):.2e}")
+    assert g[0] == 0.0
+    assert abs(g[1] - dz) <= 1e-4 * abs(dz)
+    assert rel(g[2:17], dc) <= 1e-4
+    assert rel(g[17:], dphi) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def diff():
+    return synth.make_config("diff")
+
+
+def test_sharpness_gradient_diff_workload(gpu_lib, diff):
+    """T=128, N=512 with aberration and dispersion in the data; gradient at a random point."""
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = diff.frames.shape
+    rng = np.random.default_rng(4)
+    zc = rng.normal(0, 0.3, 15)
+    phi = rng.uniform(-1, 1, T)
+    z = diff.z * 1.01
+    print(f"\n[gpu] sharpness T={T} N={N}", flush=True)
+    plan = Plan(T, N, backward=True)
+    fr = torch.from_numpy(diff.frames).cuda()
+    g = plan.backward_sharpness(fr, diff.lam, diff.pitch, z, phi, zc).cpu().numpy()
+    L, dz, dc, dphi = O.sharpness_grad(diff.frames, diff.lam, diff.pitch, z, phi, zc)
+    print(f"L {g[0]:.9e} vs {L:.9e}; dz {g[1]:.6e} vs {dz:.6e}; dc rel {rel(g[2:17], dc):.2e}; "
+          f"dphi rel {rel(g[17:], dphi):.2e}")
+    assert abs(g[0] - L) <= 1e-5 * L
+    assert abs(g[1] - dz) <= 1e-3 * abs(dz)
+    assert rel(g[2:17], dc) <= 1e-3
+    assert rel(g[17:], dphi) <= 1e-3
+    # global phase invariance holds for the GPU gradient too
+    assert abs(np.sum(g[17:])) <= 1e-4 * np.max(np.abs(g[17:])) * np.sqrt(T)
+    assert abs(g[2]) <= 1e-4 * np.max(np.abs(g[2:17]))
+
+
+def test_sharpness_finite_difference_on_gpu(gpu_lib):
+    """Central differences of the GPU loss (FP32 volume, FP64 sum) against the GPU gradient."""
+    from paper_2003_08960_amd.api import Plan
+    sw = synth.make_sweep(synth.SweepConfig(T=32, N=128, pitch=20e-6, z=0.3, lam_max=870e-9, lam_min=800e-9,
+                                            n_scatterers=6, aberration_rms=0.3, dispersion_kappa=2.0), seed=12)
+    T, N = 32, 128
+    rng = np.random.default_rng(2)
+    zc = rng.normal(0, 0.3, 15)
+    phi = rng.uniform(-1, 1, T)
+    plan = Plan(T, N, backward=True)
+    fr = torch.from_numpy(sw.frames).cuda()
+
+    def run(z=sw.z, zc_=zc, phi_=phi):
+        return plan.backward_sharpness(fr, sw.lam, sw.pitch, z, phi_, zc_).cpu().numpy()
+
+    g = run()
+    h = 1e-3 * sw.z
+    fd = (run(z=sw.z + h)[0] - run(z=sw.z - h)[0]) / (2 * h)
+    print(f"\ndz {g[1]:.6e} fd {fd:.6e}")
+    assert abs(g[1] - fd) <= 2e-2 * abs(fd)
+    for j in (4, 7):
+        e = np.zeros(15)
+        e[j] = 0.02
+        fd = (run(zc_=zc + e)[0] - run(zc_=zc - e)[0]) / 0.04
+        print(f"dc[{j}] {g[2 + j]:.6e} fd {fd:.6e}")
+        assert abs(g[2 + j] - fd) <= 2e-2 * np.max(np.abs(g[2:17]))
+    for t in (3, 20):
+        e = np.zeros(T)
+        e[t] = 0.02
+        fd = (run(phi_=phi + e)[0] - run(phi_=phi - e)[0]) / 0.04
+        print(f"dphi[{t}] {g[17 + t]:.6e} fd {fd:.6e}")
+        assert abs(g[17 + t] - fd) <= 2e-2 * np.max(np.abs(g[17:]))
+
+
+def test_autograd_function_matches_fused_backward(gpu_lib):
+    from paper_2003_08960_amd.api import Plan
+    from paper_2003_08960_amd.autograd import render
+    T, N = 8, 64
+    frames, lam, phi, zc = small_case(T, N, seed=77)
+    plan = Plan(T, N, backward=True)
+    fr = torch.from_numpy(frames).cuda()
+    z = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(zc, dtype=torch.float64, requires_grad=True)
+    p = torch.tensor(phi, dtype=torch.float64, requires_grad=True)
+    V = render(fr, z, c, p, plan, lam, 20e-6)
+    s = 1e7
+    loss = ((V / s).abs() ** 4).sum(dtype=torch.float64)
+    gz, gc, gp = torch.autograd.grad(loss, (z, c, p))
+    ref = plan.backward_sharpness(fr, lam, 20e-6, 0.05, phi, zc).cpu().numpy() / s ** 4
+    print(f"\nautograd dz {gz.item():.6e} fused {ref[1]:.6e}")
+    assert abs(loss.item() - ref[0]) <= 1e-4 * ref[0]
+    assert abs(gz.item() - ref[1]) <= 1e-4 * abs(ref[1])
+    assert rel(gc.numpy(), ref[2:17]) <= 1e-4
+    assert rel(gp.numpy(), ref[17:]) <= 1e-4
+
+
+def test_backward_rejects_eq6(gpu_lib):
+    from paper_2003_08960_amd import native
+    from paper_2003_08960_amd.api import Plan
+    T, N = 4, 32
+    frames, lam, _, _ = small_case(T, N, 1)
+    plan = Plan(T, N, backward=True, eq6_phase=True)
+    with pytest.raises(native.SsoctError):
+        plan.backward_sharpness(torch.from_numpy(frames).cuda(), lam, 20e-6, 0.05)
