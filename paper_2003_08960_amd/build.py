@@ -41,28 +41,34 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, out: str | None = None,
+          defines: dict | None = None) -> str:
+    """Compile every source and link libssoct.so (or `out`); `defines` are -D
+    tuning macros of the kernels (a variant build goes to its own object dir)."""
     cc = hipcc()
-    os.makedirs(BUILD, exist_ok=True)
+    out = out or OUT
+    defs = [f"-D{k}={v}" for k, v in sorted((defines or {}).items())]
+    bdir = BUILD if not defs else os.path.join(BUILD, "variant_" + "_".join(d[2:] for d in defs).replace("=", ""))
+    os.makedirs(bdir, exist_ok=True)
     cmds = []
     objs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        cmds.append([cc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE)
+        obj = os.path.join(bdir, src + ".o")
+        cmds.append([cc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE + defs)
         objs.append(obj)
     for src in CPP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        cmds.append([cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + [f"--offload-arch={ARCH}"])
+        obj = os.path.join(bdir, src + ".o")
+        cmds.append([cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + [f"--offload-arch={ARCH}"] + defs)
         objs.append(obj)
     jobs = jobs or min(len(cmds), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for out in ex.map(_run, cmds):
-            if verbose and out.strip():
-                print(out)
-    tmp = OUT + ".tmp"
+        for res in ex.map(_run, cmds):
+            if verbose and res.strip():
+                print(res)
+    tmp = out + ".tmp"
     _run([cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -35,10 +35,14 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
 
+#ifndef SSOCT_CHUNK_MIB
+#define SSOCT_CHUNK_MIB 64  // row-transformed frames kept between the two DFT passes (MALL resident)
+#endif
+
 int frames_per_chunk(int T, int N) {
-  // keep one chunk of row-transformed frames (8 bytes per pixel) near 64 MiB
+  // keep one chunk of row-transformed frames (8 bytes per pixel) near SSOCT_CHUNK_MIB
   const size_t per = (size_t)N * N * 8;
-  size_t f = ((size_t)64 << 20) / per;
+  size_t f = ((size_t)SSOCT_CHUNK_MIB << 20) / per;
   if (f < 1) f = 1;
   if (f > (size_t)T) f = (size_t)T;
   return (int)f;
@@ -247,7 +251,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   }
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
-  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->tw, p->outfac, zern ? p->aberr : nullptr, p->stream));
+  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern ? p->aberr : nullptr, p->stream));
   p->have_aberr = zern != nullptr;
   p->cache.swap(key);
   return status;
@@ -337,7 +341,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   const size_t na16 = (size_t)p->dl.nrb * (p->dl.T_pad / 16) * 128;
   if (e == hipSuccess) e = hipMalloc(&p->rows, axis);
   if (e == hipSuccess) e = hipMalloc(&p->cols, axis);
-  if (e == hipSuccess) e = hipMalloc(&p->tw, (size_t)N * sizeof(float2));
+  const size_t ntw = twiddle_table_size(N);
+  if (e == hipSuccess) e = hipMalloc(&p->tw, (ntw > 0 ? ntw : 1) * sizeof(float2));
   if (e == hipSuccess && (flags & SSOCT_EQ6_PHASE)) e = hipMalloc(&p->outfac, (size_t)N * sizeof(float2));
   if (e == hipSuccess) e = hipMalloc(&p->params, nparams * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->a_f32, na32 * sizeof(float));
@@ -349,6 +354,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
       if (e == hipSuccess) e = hipEventCreate(&ev);
   }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
+  if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");

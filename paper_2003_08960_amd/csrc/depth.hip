@@ -58,6 +58,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
                                                       double* __restrict__ loss_partials) {
   using PT_ = PrecTraits<PREC>;
   constexpr int NA = PT_::F32 ? KC / 2 : (PT_::SPLIT ? KC / 2 : KC / 4);  // dwords of A per lane
+  constexpr int PER_ROW = PT / 2;                                       // uint4 per tile row
+  constexpr int ROWS_PER_PASS = WAVES * 64 / PER_ROW;
+  constexpr int NLD = (KC + ROWS_PER_PASS - 1) / ROWS_PER_PASS;         // prefetch registers (uint4)
   __shared__ uint2 btile[KC * PT];
   __shared__ double red[WAVES];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -66,98 +69,117 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
   const int ntiles = ntp * slabs;
   const int h = T / 2;
   const int npairs = T - h;
+  const int my_tiles = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int nitems = my_tiles * nch;                                    // (tile, chunk) work items
+  const int cq = threadIdx.x % PER_ROW, r0 = threadIdx.x / PER_ROW;
   uint32_t a[NA];
+  uint4 pf[NLD];
   double loss = 0.0;
   int a_slab = -1, a_chunk = -1;
+  v16f acc_re, acc_im;
 
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // global loads of work item `it` (KC frames x 32 pixels) into pf, zero past T
+  auto issue = [&](int it) {
+    const int tile = blockIdx.x + (it / nch) * gridDim.x;
+    const int ch = it % nch;
+    const int p0 = (tile % ntp) * PT;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int r = r0 + i * ROWS_PER_PASS;
+      const int t = ch * KC + r;
+      pf[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (r < KC && t < T) pf[i] = *reinterpret_cast<const uint4*>(in + (size_t)t * P + p0 + 2 * cq);
+    }
+  };
+
+  if (nitems > 0) issue(0);
+  for (int it = 0; it < nitems; ++it) {
+    const int tile = blockIdx.x + (it / nch) * gridDim.x;
+    const int ch = it % nch;
     const int slab = tile / ntp;
     const int p0 = (tile % ntp) * PT;
     const int rb = slab * WAVES + w;       // this wave's row block
-    v16f acc_re = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    v16f acc_im = acc_re;
-    for (int ch = 0; ch < nch; ++ch) {
-      // ---- A rows for (slab, chunk): loaded once when there is one slab and one chunk
-      if (a_slab != slab || a_chunk != ch) {
-        if constexpr (PT_::F32) {
-          const float* src = reinterpret_cast<const float*>(amat) + ((size_t)rb * (T_pad / 2) + ch * (KC / 2)) * 64 + l;
+    if (ch == 0) {
 #pragma unroll
-          for (int s = 0; s < KC / 2; ++s) a[s] = __float_as_uint(src[(size_t)s * 64]);
-        } else {
-          const uint4* src = reinterpret_cast<const uint4*>(amat) + ((size_t)rb * (T_pad / 16) + ch * (KC / 16)) * 128 + l;
-#pragma unroll
-          for (int s = 0; s < KC / 16; ++s) {
-            const uint4 hi = src[(size_t)s * 128];
-            a[(PT_::SPLIT ? 8 : 4) * s + 0] = hi.x;
-            a[(PT_::SPLIT ? 8 : 4) * s + 1] = hi.y;
-            a[(PT_::SPLIT ? 8 : 4) * s + 2] = hi.z;
-            a[(PT_::SPLIT ? 8 : 4) * s + 3] = hi.w;
-            if constexpr (PT_::SPLIT) {
-              const uint4 lo = src[(size_t)s * 128 + 64];
-              a[8 * s + 4] = lo.x;
-              a[8 * s + 5] = lo.y;
-              a[8 * s + 6] = lo.z;
-              a[8 * s + 7] = lo.w;
-            }
-          }
-        }
-        a_slab = slab;
-        a_chunk = ch;
-      }
-      // ---- stage the B tile: KC frames x 32 pixels, 8 bytes each, zero past T
-      __syncthreads();
-      {
-        const int tid = threadIdx.x;
-        constexpr int PER_ROW = PT / 2;                 // uint4 per tile row
-        constexpr int ROWS_PER_PASS = WAVES * 64 / PER_ROW;
-        const int cq = tid % PER_ROW, r0 = tid / PER_ROW;
-#pragma unroll 4
-        for (int r = r0; r < KC; r += ROWS_PER_PASS) {
-          const int t = ch * KC + r;
-          uint4 val = make_uint4(0u, 0u, 0u, 0u);
-          if (t < T) val = *reinterpret_cast<const uint4*>(in + (size_t)t * P + p0 + 2 * cq);
-          *reinterpret_cast<uint4*>(&btile[r * PT + 2 * cq]) = val;
-        }
-      }
-      __syncthreads();
-      // ---- MFMA over the chunk
-      if constexpr (PT_::F32) {
-#pragma unroll
-        for (int s = 0; s < KC / 2; ++s) {
-          const uint2 b = btile[(2 * s + (l >> 5)) * PT + (l & 31)];
-          const float av = __uint_as_float(a[s]);
-          acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.x), acc_re, 0, 0, 0);
-          acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.y), acc_im, 0, 0, 0);
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < KC / 16; ++s) {
-          uint2 e[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) e[i] = btile[(16 * s + 8 * (l >> 5) + i) * PT + (l & 31)];
-          uint4 re_hi, im_hi, re_lo, im_lo;
-          re_hi.x = pack_lo(e[0].x, e[1].x); re_hi.y = pack_lo(e[2].x, e[3].x);
-          re_hi.z = pack_lo(e[4].x, e[5].x); re_hi.w = pack_lo(e[6].x, e[7].x);
-          im_hi.x = pack_lo(e[0].y, e[1].y); im_hi.y = pack_lo(e[2].y, e[3].y);
-          im_hi.z = pack_lo(e[4].y, e[5].y); im_hi.w = pack_lo(e[6].y, e[7].y);
-          const int ai = (PT_::SPLIT ? 8 : 4) * s;
-          const uint4 ahi = make_uint4(a[ai], a[ai + 1], a[ai + 2], a[ai + 3]);
-          if constexpr (PT_::SPLIT) {
-            re_lo.x = pack_hi(e[0].x, e[1].x); re_lo.y = pack_hi(e[2].x, e[3].x);
-            re_lo.z = pack_hi(e[4].x, e[5].x); re_lo.w = pack_hi(e[6].x, e[7].x);
-            im_lo.x = pack_hi(e[0].y, e[1].y); im_lo.y = pack_hi(e[2].y, e[3].y);
-            im_lo.z = pack_hi(e[4].y, e[5].y); im_lo.w = pack_hi(e[6].y, e[7].y);
-            const uint4 alo = make_uint4(a[ai + 4], a[ai + 5], a[ai + 6], a[ai + 7]);
-            acc_re = mfma_x16<PT_::BF>(alo, re_hi, acc_re);
-            acc_im = mfma_x16<PT_::BF>(alo, im_hi, acc_im);
-            acc_re = mfma_x16<PT_::BF>(ahi, re_lo, acc_re);
-            acc_im = mfma_x16<PT_::BF>(ahi, im_lo, acc_im);
-          }
-          acc_re = mfma_x16<PT_::BF>(ahi, re_hi, acc_re);
-          acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
-        }
+      for (int i = 0; i < 16; ++i) {
+        acc_re[i] = 0.f;
+        acc_im[i] = 0.f;
       }
     }
+    // ---- A rows for (slab, chunk): loaded once when there is one slab and one chunk
+    if (a_slab != slab || a_chunk != ch) {
+      if constexpr (PT_::F32) {
+        const float* src = reinterpret_cast<const float*>(amat) + ((size_t)rb * (T_pad / 2) + ch * (KC / 2)) * 64 + l;
+#pragma unroll
+        for (int s = 0; s < KC / 2; ++s) a[s] = __float_as_uint(src[(size_t)s * 64]);
+      } else {
+        const uint4* src = reinterpret_cast<const uint4*>(amat) + ((size_t)rb * (T_pad / 16) + ch * (KC / 16)) * 128 + l;
+#pragma unroll
+        for (int s = 0; s < KC / 16; ++s) {
+          const uint4 hi = src[(size_t)s * 128];
+          a[(PT_::SPLIT ? 8 : 4) * s + 0] = hi.x;
+          a[(PT_::SPLIT ? 8 : 4) * s + 1] = hi.y;
+          a[(PT_::SPLIT ? 8 : 4) * s + 2] = hi.z;
+          a[(PT_::SPLIT ? 8 : 4) * s + 3] = hi.w;
+          if constexpr (PT_::SPLIT) {
+            const uint4 lo = src[(size_t)s * 128 + 64];
+            a[8 * s + 4] = lo.x;
+            a[8 * s + 5] = lo.y;
+            a[8 * s + 6] = lo.z;
+            a[8 * s + 7] = lo.w;
+          }
+        }
+      }
+      a_slab = slab;
+      a_chunk = ch;
+    }
+    // ---- publish the prefetched tile, then start loading the next one
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int r = r0 + i * ROWS_PER_PASS;
+      if (r < KC) *reinterpret_cast<uint4*>(&btile[r * PT + 2 * cq]) = pf[i];
+    }
+    __syncthreads();
+    if (it + 1 < nitems) issue(it + 1);
+    // ---- MFMA over the chunk
+    if constexpr (PT_::F32) {
+#pragma unroll
+      for (int s = 0; s < KC / 2; ++s) {
+        const uint2 b = btile[(2 * s + (l >> 5)) * PT + (l & 31)];
+        const float av = __uint_as_float(a[s]);
+        acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.x), acc_re, 0, 0, 0);
+        acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(b.y), acc_im, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KC / 16; ++s) {
+        uint2 e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = btile[(16 * s + 8 * (l >> 5) + i) * PT + (l & 31)];
+        uint4 re_hi, im_hi, re_lo, im_lo;
+        re_hi.x = pack_lo(e[0].x, e[1].x); re_hi.y = pack_lo(e[2].x, e[3].x);
+        re_hi.z = pack_lo(e[4].x, e[5].x); re_hi.w = pack_lo(e[6].x, e[7].x);
+        im_hi.x = pack_lo(e[0].y, e[1].y); im_hi.y = pack_lo(e[2].y, e[3].y);
+        im_hi.z = pack_lo(e[4].y, e[5].y); im_hi.w = pack_lo(e[6].y, e[7].y);
+        const int ai = (PT_::SPLIT ? 8 : 4) * s;
+        const uint4 ahi = make_uint4(a[ai], a[ai + 1], a[ai + 2], a[ai + 3]);
+        if constexpr (PT_::SPLIT) {
+          re_lo.x = pack_hi(e[0].x, e[1].x); re_lo.y = pack_hi(e[2].x, e[3].x);
+          re_lo.z = pack_hi(e[4].x, e[5].x); re_lo.w = pack_hi(e[6].x, e[7].x);
+          im_lo.x = pack_hi(e[0].y, e[1].y); im_lo.y = pack_hi(e[2].y, e[3].y);
+          im_lo.z = pack_hi(e[4].y, e[5].y); im_lo.w = pack_hi(e[6].y, e[7].y);
+          const uint4 alo = make_uint4(a[ai + 4], a[ai + 5], a[ai + 6], a[ai + 7]);
+          acc_re = mfma_x16<PT_::BF>(alo, re_hi, acc_re);
+          acc_im = mfma_x16<PT_::BF>(alo, im_hi, acc_im);
+          acc_re = mfma_x16<PT_::BF>(ahi, re_lo, acc_re);
+          acc_im = mfma_x16<PT_::BF>(ahi, im_lo, acc_im);
+        }
+        acc_re = mfma_x16<PT_::BF>(ahi, re_hi, acc_re);
+        acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
+      }
+    }
+    if (ch != nch - 1) continue;
     // ---- epilogue: lane holds rows 8 (r/4) + 4 (l/32) + r%4 of its block, column l%32
     const int p = p0 + (l & 31);
 #pragma unroll

@@ -155,18 +155,50 @@ __device__ __forceinline__ constexpr int out_offset(int e) {
   }
 }
 
-// Twiddle exp(DIR 2 pi i idx / N) from the table tw[idx] = exp(+2 pi i idx / N).
+// Per-thread twiddle table.  For every pass that needs twiddles, thread j of
+// a group reads E consecutive entries (one base address, immediate offsets):
+//   radix-16 pass p >= 1 (Ns = 16^p): entry r-1 = exp(+2 pi i s r / N),
+//       s = (j mod Ns) N / (16 Ns), r = 1..15
+//   final radix-L pass (Ns = N/L):   entry i (L-1) + k-1 = exp(+2 pi i b k / N),
+//       b = j + G i, i = 0..16/L-1, k = 1..L-1
+// The table is built in FP64 on the GPU (tables.hip) from this same layout.
+template <int N>
+struct TwPlan {
+  using S = FFTShape<N>;
+  static constexpr int G = S::G;
+  static constexpr int E16 = 15;
+  static constexpr int NB = S::L > 1 ? 16 / S::L : 0;
+  static constexpr int EL = S::L > 1 ? NB * (S::L - 1) : 0;
+  static constexpr int OFF_L = (S::P16 - 1) * G * E16;
+  static constexpr int SIZE = OFF_L + G * EL;
+  static constexpr int off16(int p) { return (p - 1) * G * E16; }
+};
+
 template <int DIR>
-__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int idx) {
-  float2 w = tw[idx];
+__device__ __forceinline__ float2 tw_dir(float2 w) {
   return DIR > 0 ? w : cconj(w);
+}
+
+// Barrier between LDS writes and reads of one exchange.  A group that lives
+// inside one wavefront (G <= 64) only needs its own LDS accesses ordered:
+// the LDS unit executes the instructions of a wave in order, so a compiler
+// fence at wavefront scope is enough.  Larger groups use the workgroup
+// barrier.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
 }
 
 // Full N-point FFT of one group.  `lds` points to this group's LDS region of
 // FFTShape<N>::LDS complex slots with element stride `ls` (1 for row FFTs,
-// C for a C-column tile).  Every thread of the workgroup must call this the
-// same number of times: the exchanges use workgroup barriers.
-template <int N, int DIR>
+// C for a C-column tile).  With WAVE = false every thread of the workgroup
+// must call this the same number of times (workgroup barriers).
+template <int N, int DIR, bool WAVE = false>
 __device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, int ls,
                                           const float2* __restrict__ tw) {
   using S = FFTShape<N>;
@@ -175,19 +207,18 @@ __device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, i
 #pragma unroll
   for (int p = 0; p < S::P16; ++p) {
     if (p > 0) {
-      const int kk = j % Ns;
-      const int step = kk * (N / (Ns * 16));
+      const float2* twj = tw + TwPlan<N>::off16(p) + j * TwPlan<N>::E16;
 #pragma unroll
-      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<DIR>(tw, step * r));
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_dir<DIR>(twj[r - 1]));
     }
     dft16<DIR>(v);
     const bool last = (p == S::P16 - 1) && (S::L == 1);
     if (!last) {
       const int base = (j / Ns) * Ns * 16 + (j % Ns);
-      __syncthreads();  // previous reads of this region are complete
+      exchange_sync<WAVE>();  // previous reads of this region are complete
 #pragma unroll
       for (int k = 0; k < 16; ++k) lds[lds_slot(base + k * Ns) * ls] = v[k];
-      __syncthreads();
+      exchange_sync<WAVE>();
       Ns *= 16;
       if constexpr (S::L == 1) {
 #pragma unroll
@@ -210,11 +241,11 @@ __device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, i
       for (int k = 0; k < L; ++k) v[i * L + k] = lds[lds_slot(j + G * i + k * (N / L)) * ls];
     }
     if constexpr (S::P16 > 0) {
+      const float2* twj = tw + TwPlan<N>::OFF_L + j * TwPlan<N>::EL;
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const int b = j + G * i;  // b < N/L = Ns, so kk = b
 #pragma unroll
-        for (int k = 1; k < L; ++k) v[i * L + k] = cmul(v[i * L + k], twiddle<DIR>(tw, b * k));
+        for (int k = 1; k < L; ++k) v[i * L + k] = cmul(v[i * L + k], tw_dir<DIR>(twj[i * (L - 1) + k - 1]));
       }
     }
 #pragma unroll

@@ -76,8 +76,10 @@ DepthLayout depth_layout(int T);
 // ---------------------------------------------------------------- launchers
 hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows, AxisTab* cols,
                               hipStream_t s);
-hipError_t launch_misc_tables(const double* params, int T, int N, float2* tw, float2* outfac,
-                              float2* aberr, hipStream_t s);
+hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float2* aberr, hipStream_t s);
+// FFT engine twiddles (per-thread layout), FP64 -> FP32; size in float2 entries
+hipError_t launch_twiddles(int N, float2* tw, hipStream_t s);
+size_t twiddle_table_size(int N);
 hipError_t launch_depth_tables(int T, float* a_f32, uint4* a_f16, uint4* a_bf16, hipStream_t s);
 
 // Forward Fresnel stage on frames [t0, t0 + F): rescale + chirp + row DFT into

@@ -7,47 +7,82 @@
 // Index conventions: FFT position i carries original sample (i + N/2) mod N;
 // the tables already hold (-1)^i' and the chirp, so both passes are plain
 // positive-exponent DFTs and the output lands at natural (u, v).
+//
+// Both passes are persistent loops with register prefetch: a row group loads
+// the source rows of its next output row while it transforms the current
+// one, and a column workgroup loads its next column tile while it transforms
+// the current one.  The per-frame column table of Eq. 5/6 is staged in LDS
+// once per row workgroup.
 #include "fft_engine.hpp"
 #include "internal.hpp"
 
 namespace ssoct {
 
-// rows handled by one row-pass workgroup, and its size
+// Tuning knobs (compile-time; the defaults are the tuned values)
+#ifndef SSOCT_ROW_RPG
+#define SSOCT_ROW_RPG 4          // rows per row group and workgroup iteration count
+#endif
+#ifndef SSOCT_ROW_WAVESYNC
+#define SSOCT_ROW_WAVESYNC 1     // single-wave row groups exchange with wave-level ordering
+#endif
+#ifndef SSOCT_COL_MIN
+#define SSOCT_COL_MIN 8          // minimum adjacent columns per column workgroup
+#endif
+#ifndef SSOCT_COL_PREFETCH
+#define SSOCT_COL_PREFETCH 1     // load the next column tile while transforming the current one
+#endif
+
+// Row pass geometry: GR groups of G = N/16 threads, each group owns RPG
+// consecutive rows; a workgroup covers GR * RPG rows of one frame.
 template <int N>
 struct RowCfg {
   static constexpr int G = FFTShape<N>::G;
-  static constexpr int ROWS = (256 / G) < N ? (256 / G) : N;
-  static constexpr int THREADS = ROWS * G;
+  static constexpr int GR = (256 / G) < N ? (256 / G) : N;
+  static constexpr int RPG = (N / GR) < SSOCT_ROW_RPG ? (N / GR) : SSOCT_ROW_RPG;
+  static constexpr int ROWS = GR * RPG;                  // rows per workgroup
+  static constexpr int THREADS = GR * G;
+  static constexpr bool WAVE = G <= 64 && SSOCT_ROW_WAVESYNC;  // a group lives inside one wavefront
 };
-// columns handled by one column-pass workgroup (>= 8 so that every row segment is >= 64 B)
+// Column pass geometry: C adjacent columns (>= SSOCT_COL_MIN, so row segments
+// are >= 64 B), at most 1024 threads
 template <int N>
 struct ColCfg {
+  static constexpr int G = FFTShape<N>::G;
   static constexpr int C0 = 4096 / N;
-  static constexpr int C = C0 < 8 ? 8 : (C0 > N ? N : C0);
-  static constexpr int THREADS = C * FFTShape<N>::G;
+  static constexpr int C1 = C0 < SSOCT_COL_MIN ? SSOCT_COL_MIN : (C0 > N ? N : C0);
+  static constexpr int C = C1 * G > 1024 ? 1024 / G : C1;
+  static constexpr int THREADS = C * G;
 };
 
-// y-lerp of the two source rows of Eq. 5 for one output row into rbuf[0..N):
-// thread j of the group covers source columns [16 j, 16 j + 16).
+// Source rows y0 and y0 + 1 of Eq. 5 for one output row, 16 columns per thread.
+struct RowSrc {
+  uint4 a0, a1, b0, b1;
+};
+
 template <int N>
-__device__ __forceinline__ void lerp_rows(const uint16_t* __restrict__ I, int y0, float fy, float* rbuf, int j) {
+__device__ __forceinline__ RowSrc load_rows(const uint16_t* __restrict__ I, int y0, int j) {
   const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
   const uint4* r0 = reinterpret_cast<const uint4*>(I + (size_t)y0 * N + 16 * j);
   const uint4* r1 = reinterpret_cast<const uint4*>(I + (size_t)y1 * N + 16 * j);
-  uint4 a[2] = {r0[0], r0[1]};
-  uint4 b[2] = {r1[0], r1[1]};
+  RowSrc s;
+  s.a0 = r0[0];
+  s.a1 = r0[1];
+  s.b0 = r1[0];
+  s.b1 = r1[1];
+  return s;
+}
+
+// y-lerp of the two source rows into rbuf[16 j .. 16 j + 16)
+__device__ __forceinline__ void lerp_rows(const RowSrc& s, float fy, float* rbuf, int j) {
+  const uint32_t wa[8] = {s.a0.x, s.a0.y, s.a0.z, s.a0.w, s.a1.x, s.a1.y, s.a1.z, s.a1.w};
+  const uint32_t wb[8] = {s.b0.x, s.b0.y, s.b0.z, s.b0.w, s.b1.x, s.b1.y, s.b1.z, s.b1.w};
   float out[16];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const uint32_t wa[4] = {a[h].x, a[h].y, a[h].z, a[h].w};
-    const uint32_t wb[4] = {b[h].x, b[h].y, b[h].z, b[h].w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float a0 = (float)(wa[q] & 0xffffu), a1 = (float)(wa[q] >> 16);
-      const float b0 = (float)(wb[q] & 0xffffu), b1 = (float)(wb[q] >> 16);
-      out[8 * h + 2 * q] = a0 + fy * (b0 - a0);
-      out[8 * h + 2 * q + 1] = a1 + fy * (b1 - a1);
-    }
+  for (int q = 0; q < 8; ++q) {
+    const float a0 = (float)(wa[q] & 0xffffu), a1 = (float)(wa[q] >> 16);
+    const float b0 = (float)(wb[q] & 0xffffu), b1 = (float)(wb[q] >> 16);
+    out[2 * q] = a0 + fy * (b0 - a0);
+    out[2 * q + 1] = a1 + fy * (b1 - a1);
   }
   float4* dst = reinterpret_cast<float4*>(rbuf + 16 * j);
 #pragma unroll
@@ -68,6 +103,19 @@ __device__ __forceinline__ float2 row_input(const float* rbuf, const AxisTab& ct
   return make_float2(J * fac.x, J * fac.y);
 }
 
+template <int N>
+struct RowLds {
+  static constexpr int XS = (FFTShape<N>::LDS + 1) & ~1;  // row stride kept a multiple of 16 bytes
+  AxisTab ctab[N];
+  float2 xbuf[RowCfg<N>::GR][XS];   // exchange buffer; the y-lerped row (float4 stores) aliases its start
+};
+
+// stage the frame's column table in LDS (all threads)
+template <int N>
+__device__ __forceinline__ void stage_ctab(AxisTab* ctab, const AxisTab* __restrict__ src) {
+  for (int i = threadIdx.x; i < N; i += RowCfg<N>::THREADS) ctab[i] = src[i];
+}
+
 // ------------------------------------------------------------------ forward row pass
 template <int N, bool ABERR, bool EQ6>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass(
@@ -77,32 +125,47 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass(
   using S = FFTShape<N>;
   using R = RowCfg<N>;
   constexpr int G = S::G;
-  __shared__ float rbuf[R::ROWS][N];
-  __shared__ float2 xbuf[R::ROWS][S::LDS];
+  __shared__ RowLds<N> lds;
   const int g = threadIdx.x / G, j = threadIdx.x % G;
-  const int m = blockIdx.x * R::ROWS + g;
   const int f = blockIdx.y;
   const int t = t0 + f;
+  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
   const uint16_t* I = frames + (size_t)t * N * N;
-  const AxisTab rt = rows[(size_t)t * N + m];
-  lerp_rows<N>(I, rt.i0, rt.f, rbuf[g], j);
-  __syncthreads();
-  const AxisTab* ctab = cols + (size_t)t * N;
-  const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
-  float2 v[16];
+  const AxisTab* rtab = rows + (size_t)t * N;
+  float* rbuf = reinterpret_cast<float*>(lds.xbuf[g]);
+  stage_ctab<N>(lds.ctab, cols + (size_t)t * N);
+
+  AxisTab rt = rtab[m0];
+  RowSrc src = load_rows<N>(I, rt.i0, j);
+  __syncthreads();  // column table visible
+#pragma unroll 1
+  for (int i = 0; i < R::RPG; ++i) {
+    const int m = m0 + i;
+    const RowSrc cur = src;
+    const AxisTab rc = rt;
+    if (i + 1 < R::RPG) {  // prefetch the next row of this group
+      rt = rtab[m + 1];
+      src = load_rows<N>(I, rt.i0, j);
+    }
+    exchange_sync<R::WAVE>();  // previous row's FFT reads are done
+    lerp_rows(cur, rc.f, rbuf, j);
+    exchange_sync<R::WAVE>();
+    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+    float2 v[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int n = j + k * G;
-    v[k] = row_input<N, ABERR>(rbuf[g], ctab[n], rt.fac, arow, n);
-  }
-  fft_group<N, +1>(v, j, xbuf[g], 1, tw);
-  float2* dst = inter + ((size_t)f * N + m) * N;
+    for (int k = 0; k < 16; ++k) {
+      const int n = j + k * G;
+      v[k] = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, arow, n);
+    }
+    fft_group<N, +1, R::WAVE>(v, j, lds.xbuf[g], 1, tw);
+    float2* dst = inter + ((size_t)f * N + m) * N;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int vv = j + out_offset<N>(e);
-    float2 val = v[e];
-    if constexpr (EQ6) val = cmul(val, outfac[vv]);
-    dst[vv] = val;
+    for (int e = 0; e < 16; ++e) {
+      const int vv = j + out_offset<N>(e);
+      float2 val = v[e];
+      if constexpr (EQ6) val = cmul(val, outfac[vv]);
+      dst[vv] = val;
+    }
   }
 }
 
@@ -141,39 +204,59 @@ __device__ __forceinline__ void store_h(void* __restrict__ H, size_t idx, float2
 }
 
 // ------------------------------------------------------------------ column pass (both directions)
-// src, dst: frame 0 of this launch; frame f at + f N^2.  DIR = +1 writes H in
-// format FMT (and applies the Eq. 6 output phase when EQ6); DIR = -1 writes
-// complex64.
+// Tiles are (frame f, block of C columns) over the F frames of the launch,
+// walked persistently.  src, dst: frame 0 of this launch; frame f at + f N^2.
+// DIR = +1 writes H in format FMT (and the Eq. 6 output phase when EQ6);
+// DIR = -1 writes complex64.
 template <int N, int DIR, int FMT, bool EQ6>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* __restrict__ src,
                                                                  const float2* __restrict__ tw,
                                                                  const float2* __restrict__ outfac,
-                                                                 void* __restrict__ dst, float scale) {
+                                                                 void* __restrict__ dst, float scale, int ntiles) {
   using S = FFTShape<N>;
   constexpr int G = S::G;
   constexpr int C = ColCfg<N>::C;
+  constexpr int NCB = N / C;  // column blocks per frame
   __shared__ float2 xbuf[S::LDS * C];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
-  const int col = blockIdx.x * C + c;
-  const size_t fo = (size_t)blockIdx.y * N * N;
-  const float2* s = src + fo + col;
-  float2 v[16];
+  float2 pf[16];
+  auto issue = [&](int tile) {
+    const int f = tile / NCB, col = (tile % NCB) * C + c;
+    const float2* s = src + (size_t)f * N * N + col;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = s[(size_t)(j + k * G) * N];
-  fft_group<N, DIR>(v, j, xbuf + c, C, tw);
+    for (int k = 0; k < 16; ++k) pf[k] = s[(size_t)(j + k * G) * N];
+  };
+  int tile = blockIdx.x;
+  if (SSOCT_COL_PREFETCH && tile < ntiles) issue(tile);
+#pragma unroll 1
+  for (; tile < ntiles; tile += gridDim.x) {
+    float2 v[16];
+    if constexpr (SSOCT_COL_PREFETCH) {
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int u = j + out_offset<N>(e);
-    float2 val = v[e];
-    if constexpr (EQ6) val = cmul(val, outfac[u]);
-    store_h<FMT>(dst, fo + (size_t)u * N + col, val, scale);
+      for (int k = 0; k < 16; ++k) v[k] = pf[k];
+      if (tile + (int)gridDim.x < ntiles) issue(tile + gridDim.x);
+    } else {
+      issue(tile);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = pf[k];
+    }
+    const int f = tile / NCB, col = (tile % NCB) * C + c;
+    fft_group<N, DIR>(v, j, xbuf + c, C, tw);
+    const size_t fo = (size_t)f * N * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int u = j + out_offset<N>(e);
+      float2 val = v[e];
+      if constexpr (EQ6) val = cmul(val, outfac[u]);
+      store_h<FMT>(dst, fo + (size_t)u * N + col, val, scale);
+    }
   }
 }
 
 // ------------------------------------------------------------------ adjoint row pass + moments
 // g[m][n] = DFT^-_v inter[f][m][v]; u = Im(conj(g) z) with z recomputed as in
-// the forward row pass; per-frame FP64 moments sum u x^a y^b (a + b <= 4) at
-// the original sample (x, y) = (c_n', c_m') sqrt(2) / N.
+// the forward row pass; per-(frame, workgroup) FP64 moments sum u x^a y^b
+// (a + b <= 4) at the original sample (x, y) = (c_n', c_m') sqrt(2) / N.
 template <int N, bool ABERR>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
@@ -183,58 +266,67 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
   using R = RowCfg<N>;
   constexpr int G = S::G;
   constexpr int NW = (R::THREADS + 63) / 64;
-  __shared__ float rbuf[R::ROWS][N];
-  __shared__ float2 xbuf[R::ROWS][S::LDS];
+  constexpr int WIDTH = R::THREADS < 64 ? R::THREADS : 64;  // lanes that exist in a wave
+  __shared__ RowLds<N> lds;
   __shared__ double red[NW][N_MONO];
   const int g = threadIdx.x / G, j = threadIdx.x % G;
-  const int m = blockIdx.x * R::ROWS + g;
   const int f = blockIdx.y;
   const int t = t0 + f;
+  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
   const uint16_t* I = frames + (size_t)t * N * N;
-  const AxisTab rt = rows[(size_t)t * N + m];
-  lerp_rows<N>(I, rt.i0, rt.f, rbuf[g], j);
-  const float2* srow = inter + ((size_t)f * N + m) * N;
-  float2 v[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = srow[j + k * G];
-  fft_group<N, -1>(v, j, xbuf[g], 1, tw);
-  __syncthreads();  // rbuf complete for every group
-  const AxisTab* ctab = cols + (size_t)t * N;
-  const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+  const AxisTab* rtab = rows + (size_t)t * N;
+  float* rbuf = reinterpret_cast<float*>(lds.xbuf[g]);
+  stage_ctab<N>(lds.ctab, cols + (size_t)t * N);
   const double inv = 1.4142135623730950488 / (double)N;
   const int half = N >> 1;
-  const double y = (double)(m < half ? m : m - N) * inv;
-  const double y2 = y * y;
   double acc[N_MONO];
 #pragma unroll
   for (int k = 0; k < N_MONO; ++k) acc[k] = 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int i = 0; i < R::RPG; ++i) {
+    const int m = m0 + i;
+    const AxisTab rc = rtab[m];
+    const RowSrc cur = load_rows<N>(I, rc.i0, j);
+    const float2* srow = inter + ((size_t)f * N + m) * N;
+    float2 v[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int n = j + out_offset<N>(e);
-    const float2 z = row_input<N, ABERR>(rbuf[g], ctab[n], rt.fac, arow, n);
-    const float2 gg = v[e];
-    const double u = (double)gg.x * (double)z.y - (double)gg.y * (double)z.x;  // Im(conj(g) z)
-    const double x = (double)(n < half ? n : n - N) * inv;
-    const double x2 = x * x;
-    const double ux = u * x, uy = u * y;
-    acc[0] += u;
-    acc[1] += ux;
-    acc[2] += uy;
-    acc[3] += ux * x;
-    acc[4] += ux * y;
-    acc[5] += uy * y;
-    acc[6] += ux * x2;
-    acc[7] += ux * x * y;
-    acc[8] += ux * y2;
-    acc[9] += uy * y2;
-    acc[10] += ux * x * x2;
-    acc[11] += ux * x2 * y;
-    acc[12] += ux * x * y2;
-    acc[13] += ux * y2 * y;
-    acc[14] += uy * y * y2;
+    for (int k = 0; k < 16; ++k) v[k] = srow[j + k * G];
+    fft_group<N, -1, R::WAVE>(v, j, lds.xbuf[g], 1, tw);
+    exchange_sync<R::WAVE>();   // FFT reads of xbuf done before rbuf (aliased) is written
+    lerp_rows(cur, rc.f, rbuf, j);
+    exchange_sync<R::WAVE>();
+    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+    const double y = (double)(m < half ? m : m - N) * inv;
+    const double y2 = y * y;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int n = j + out_offset<N>(e);
+      const float2 z = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, arow, n);
+      const float2 gg = v[e];
+      const double u = (double)gg.x * (double)z.y - (double)gg.y * (double)z.x;  // Im(conj(g) z)
+      const double x = (double)(n < half ? n : n - N) * inv;
+      const double x2 = x * x;
+      const double ux = u * x, uy = u * y;
+      acc[0] += u;
+      acc[1] += ux;
+      acc[2] += uy;
+      acc[3] += ux * x;
+      acc[4] += ux * y;
+      acc[5] += uy * y;
+      acc[6] += ux * x2;
+      acc[7] += ux * x * y;
+      acc[8] += ux * y2;
+      acc[9] += uy * y2;
+      acc[10] += ux * x * x2;
+      acc[11] += ux * x2 * y;
+      acc[12] += ux * x * y2;
+      acc[13] += ux * y2 * y;
+      acc[14] += uy * y * y2;
+    }
+    exchange_sync<R::WAVE>();   // rbuf reads done before the next FFT writes xbuf
   }
   // wave reduction, then across waves in fixed order
-  constexpr int WIDTH = R::THREADS < 64 ? R::THREADS : 64;  // lanes that exist in a wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < N_MONO; ++k) {
@@ -272,16 +364,24 @@ static hipError_t row_pass_n(int F, int t0, const uint16_t* frames, const AxisTa
   return hipGetLastError();
 }
 
+static int col_grid(int ntiles) {
+  // persistent: about two resident workgroups per CU of the 256 on MI355X
+  const int g = 512;
+  return ntiles < g ? ntiles : g;
+}
+
 template <int N>
 static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
                              int fmt, int sigma, hipStream_t s) {
   using C = ColCfg<N>;
-  dim3 grid(N / C::C, F), block(C::THREADS);
+  const int ntiles = F * (N / C::C);
+  dim3 grid(col_grid(ntiles)), block(C::THREADS);
   const float scale = ldexpf(1.0f, -sigma);
   char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
   const bool eq6 = outfac != nullptr;
-#define SSOCT_COL(FMT, E) \
-  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E>), grid, block, 0, s, inter, tw, outfac, (void*)dst, scale)
+#define SSOCT_COL(FMT, E)                                                                                  \
+  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E>), grid, block, 0, s, inter, tw, outfac, (void*)dst, scale, \
+                     ntiles)
   if (fmt == HF_F32) { if (eq6) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
   else if (fmt == HF_F16) { if (eq6) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
   else { if (eq6) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
@@ -292,10 +392,11 @@ static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* t
 template <int N>
 static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* tw, float2* inter, hipStream_t s) {
   using C = ColCfg<N>;
-  dim3 grid(N / C::C, F), block(C::THREADS);
+  const int ntiles = F * (N / C::C);
+  dim3 grid(col_grid(ntiles)), block(C::THREADS);
   const float2* src = B + (size_t)t0 * N * N;
   hipLaunchKernelGGL((k_col_pass<N, -1, HF_F32, false>), grid, block, 0, s, src, tw, (const float2*)nullptr,
-                     (void*)inter, 1.0f);
+                     (void*)inter, 1.0f, ntiles);
   return hipGetLastError();
 }
 

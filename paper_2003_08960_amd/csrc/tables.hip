@@ -7,6 +7,7 @@
 //  * misc tables   : FFT twiddles, Eq. 6 output phase, aberration screen
 //  * depth tables  : the T x T real form of the Eq. 7 DFT matrix, packed in
 //                    MFMA register order (FP32, and FP16/BF16 hi+lo pairs)
+#include "fft_engine.hpp"
 #include "internal.hpp"
 
 namespace ssoct {
@@ -60,21 +61,74 @@ __device__ __forceinline__ double mono(int k, double x, double y) {
   return r;
 }
 
-__global__ void k_misc_tables(const double* __restrict__ params, int T, int N, float2* __restrict__ tw,
-                              float2* __restrict__ outfac, float2* __restrict__ aberr) {
+// Per-thread twiddle table of the FFT engine (layout: TwPlan in fft_engine.hpp).
+template <int N>
+__global__ void k_twiddles(float2* __restrict__ tw) {
+  using P = TwPlan<N>;
+  using S = FFTShape<N>;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P::SIZE) return;
+  long long num;
+  if (idx < P::OFF_L) {
+    const int p = idx / (P::G * P::E16) + 1, rem = idx % (P::G * P::E16);
+    const int j = rem / P::E16, r = rem % P::E16 + 1;
+    const int Ns = 1 << (4 * p);
+    num = (long long)((j % Ns) * (N / (Ns * 16))) * r;
+  } else {
+    const int rem = idx - P::OFF_L, j = rem / P::EL, e = rem % P::EL;
+    const int i = e / (S::L - 1), k = e % (S::L - 1) + 1;
+    num = (long long)(j + P::G * i) * k;
+  }
+  double s, c;
+  sincospi(2.0 * (double)(num % N) / (double)N, &s, &c);
+  tw[idx] = make_float2((float)c, (float)s);
+}
+
+template <int N>
+static hipError_t twiddles_n(float2* tw, hipStream_t s) {
+  constexpr int n = TwPlan<N>::SIZE;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_twiddles<N>, dim3((n + 255) / 256), dim3(256), 0, s, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(int N, float2* tw, hipStream_t s) {
+  switch (N) {
+    case 16: return twiddles_n<16>(tw, s);
+    case 32: return twiddles_n<32>(tw, s);
+    case 64: return twiddles_n<64>(tw, s);
+    case 128: return twiddles_n<128>(tw, s);
+    case 256: return twiddles_n<256>(tw, s);
+    case 512: return twiddles_n<512>(tw, s);
+    case 1024: return twiddles_n<1024>(tw, s);
+    case 2048: return twiddles_n<2048>(tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t twiddle_table_size(int N) {
+  switch (N) {
+    case 16: return TwPlan<16>::SIZE;
+    case 32: return TwPlan<32>::SIZE;
+    case 64: return TwPlan<64>::SIZE;
+    case 128: return TwPlan<128>::SIZE;
+    case 256: return TwPlan<256>::SIZE;
+    case 512: return TwPlan<512>::SIZE;
+    case 1024: return TwPlan<1024>::SIZE;
+    case 2048: return TwPlan<2048>::SIZE;
+    default: return 0;
+  }
+}
+
+__global__ void k_misc_tables(const double* __restrict__ params, int T, int N, float2* __restrict__ outfac,
+                              float2* __restrict__ aberr) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;   // column (FFT position)
   const int m = blockIdx.y;                              // row (FFT position)
   if (n >= N || m >= N) return;
   const double* g = params + ParamLayout::globals(T);
-  if (m == 0) {
-    // tw[n] = exp(+2 pi i n / N)
-    double s, c;
-    sincospi(2.0 * (double)n / (double)N, &s, &c);
-    tw[n] = make_float2((float)c, (float)s);
-    if (outfac) {
-      const double cu = (double)(n - (N >> 1));
-      outfac[n] = expi_cycles(frac_cycles(-g[ParamLayout::G_KAPPA_OUT] * cu * cu), 1.0);
-    }
+  if (m == 0 && outfac) {
+    const double cu = (double)(n - (N >> 1));
+    outfac[n] = expi_cycles(frac_cycles(-g[ParamLayout::G_KAPPA_OUT] * cu * cu), 1.0);
   }
   if (aberr && g[ParamLayout::G_HAS_ABERR] != 0.0) {
     const int half = N >> 1;
@@ -179,10 +233,10 @@ hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows,
   return hipGetLastError();
 }
 
-hipError_t launch_misc_tables(const double* params, int T, int N, float2* tw, float2* outfac,
-                              float2* aberr, hipStream_t s) {
+hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float2* aberr, hipStream_t s) {
+  if (!outfac && !aberr) return hipSuccess;
   dim3 block(256), grid((N + 255) / 256, aberr ? N : 1);
-  hipLaunchKernelGGL(k_misc_tables, grid, block, 0, s, params, T, N, tw, outfac, aberr);
+  hipLaunchKernelGGL(k_misc_tables, grid, block, 0, s, params, T, N, outfac, aberr);
   return hipGetLastError();
 }
 

@@ -9,7 +9,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libssoct.so")
+# SSOCT_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SSOCT_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libssoct.so")
 
 # status codes and flags (include/ssoct.h)
 OK = 0
