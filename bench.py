@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--forms", default="fp32,fp16_split,bf16_split,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one untimed 1 GiB device-to-device copy first: the reference kernel that "
+                         "scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the render of one sweep runs on a single MI355X "
@@ -133,6 +136,13 @@ def main():
     native.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     log("generating the paper-shaped sweep (T=256, N=1024)")
     sw = synth.make_config("paper")
     T, N, _ = sw.frames.shape

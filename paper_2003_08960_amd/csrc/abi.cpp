@@ -35,12 +35,16 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
 
+// Fresnel-stage chunking: the row pass of a chunk of frames writes a buffer
+// of SSOCT_CHUNK_MIB that the column pass reads right after.  (Overlapping
+// the two passes on two streams with a ring of buffers was measured slower:
+// the per-chunk cross-stream waits cost more than the overlap.)
 #ifndef SSOCT_CHUNK_MIB
-#define SSOCT_CHUNK_MIB 64  // row-transformed frames kept between the two DFT passes (MALL resident)
+#define SSOCT_CHUNK_MIB 128
 #endif
 
 int frames_per_chunk(int T, int N) {
-  // keep one chunk of row-transformed frames (8 bytes per pixel) near SSOCT_CHUNK_MIB
+  // one chunk of row-transformed frames (8 bytes per pixel) near SSOCT_CHUNK_MIB
   const size_t per = (size_t)N * N * 8;
   size_t f = ((size_t)SSOCT_CHUNK_MIB << 20) / per;
   if (f < 1) f = 1;
@@ -262,12 +266,14 @@ int check_plan(const ssoct_plan* p) {
   return SSOCT_OK;
 }
 
+// Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
+// row DFT) into the chunk buffer, then column DFT into H.
 int forward_stage_a(ssoct_plan* p, const uint16_t* frames, void* H, float2* inter, int fmt, int sigma) {
   const int T = p->T, N = p->N;
+  const float2* ab = p->have_aberr ? p->aberr : nullptr;
   for (int t0 = 0; t0 < T; t0 += p->F) {
     const int Fc = T - t0 < p->F ? T - t0 : p->F;
-    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->aberr : nullptr,
-                              p->outfac, inter, p->stream));
+    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));
     SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, fmt, sigma, p->stream));
   }
   return SSOCT_OK;
@@ -355,6 +361,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
+  }
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");

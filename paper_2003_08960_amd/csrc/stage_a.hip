@@ -26,10 +26,18 @@ namespace ssoct {
 #define SSOCT_ROW_WAVESYNC 1     // single-wave row groups exchange with wave-level ordering
 #endif
 #ifndef SSOCT_COL_MIN
-#define SSOCT_COL_MIN 8          // minimum adjacent columns per column workgroup
+#define SSOCT_COL_MIN 16         // minimum adjacent columns per column workgroup (128 B row segments)
 #endif
 #ifndef SSOCT_COL_PREFETCH
-#define SSOCT_COL_PREFETCH 1     // load the next column tile while transforming the current one
+#define SSOCT_COL_PREFETCH 0     // load the next column tile while transforming the current one
+#endif
+#ifndef SSOCT_ROW_WAVES_PER_EU
+#define SSOCT_ROW_WAVES_PER_EU 0  // > 0: ask the compiler to fit this many row-pass waves per SIMD
+#endif
+#if SSOCT_ROW_WAVES_PER_EU > 0
+#define SSOCT_ROW_OCC __attribute__((amdgpu_waves_per_eu(SSOCT_ROW_WAVES_PER_EU)))
+#else
+#define SSOCT_ROW_OCC
 #endif
 
 // Row pass geometry: GR groups of G = N/16 threads, each group owns RPG
@@ -54,39 +62,48 @@ struct ColCfg {
   static constexpr int THREADS = C * G;
 };
 
-// Source rows y0 and y0 + 1 of Eq. 5 for one output row, 16 columns per thread.
+// Source rows y0 and y0 + 1 of Eq. 5 for one output row: thread j of a group
+// holds columns [s N/4 + 4 j, s N/4 + 4 j + 4) for s = 0..3, so every load
+// instruction of a group covers a contiguous N/2-byte span and the LDS stores
+// of the y-lerped row are conflict free.
 struct RowSrc {
-  uint4 a0, a1, b0, b1;
+  uint2 a[4], b[4];
 };
 
 template <int N>
 __device__ __forceinline__ RowSrc load_rows(const uint16_t* __restrict__ I, int y0, int j) {
   const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
-  const uint4* r0 = reinterpret_cast<const uint4*>(I + (size_t)y0 * N + 16 * j);
-  const uint4* r1 = reinterpret_cast<const uint4*>(I + (size_t)y1 * N + 16 * j);
+  const uint16_t* r0 = I + (size_t)y0 * N + 4 * j;
+  const uint16_t* r1 = I + (size_t)y1 * N + 4 * j;
   RowSrc s;
-  s.a0 = r0[0];
-  s.a1 = r0[1];
-  s.b0 = r1[0];
-  s.b1 = r1[1];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    s.a[q] = *reinterpret_cast<const uint2*>(r0 + q * (N / 4));
+    s.b[q] = *reinterpret_cast<const uint2*>(r1 + q * (N / 4));
+  }
   return s;
 }
 
-// y-lerp of the two source rows into rbuf[16 j .. 16 j + 16)
+// y-lerp of the two source rows into rbuf (same column split as load_rows);
+// the last thread also zeroes rbuf[N], the right tap of the last sample, which
+// only occurs with weight 0 (s_t <= 1 keeps every position inside [0, N-1])
+template <int N>
 __device__ __forceinline__ void lerp_rows(const RowSrc& s, float fy, float* rbuf, int j) {
-  const uint32_t wa[8] = {s.a0.x, s.a0.y, s.a0.z, s.a0.w, s.a1.x, s.a1.y, s.a1.z, s.a1.w};
-  const uint32_t wb[8] = {s.b0.x, s.b0.y, s.b0.z, s.b0.w, s.b1.x, s.b1.y, s.b1.z, s.b1.w};
-  float out[16];
+  if (j == N / 16 - 1) rbuf[N] = 0.0f;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const float a0 = (float)(wa[q] & 0xffffu), a1 = (float)(wa[q] >> 16);
-    const float b0 = (float)(wb[q] & 0xffffu), b1 = (float)(wb[q] >> 16);
-    out[2 * q] = a0 + fy * (b0 - a0);
-    out[2 * q + 1] = a1 + fy * (b1 - a1);
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t wa[2] = {s.a[q].x, s.a[q].y};
+    const uint32_t wb[2] = {s.b[q].x, s.b[q].y};
+    float out[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float a0 = (float)(wa[h] & 0xffffu), a1 = (float)(wa[h] >> 16);
+      const float b0 = (float)(wb[h] & 0xffffu), b1 = (float)(wb[h] >> 16);
+      out[2 * h] = a0 + fy * (b0 - a0);
+      out[2 * h + 1] = a1 + fy * (b1 - a1);
+    }
+    *reinterpret_cast<float4*>(rbuf + q * (N / 4) + 4 * j) = make_float4(out[0], out[1], out[2], out[3]);
   }
-  float4* dst = reinterpret_cast<float4*>(rbuf + 16 * j);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
 }
 
 // Row input z[m][n] of the DFT at FFT position n (x-lerp of the y-lerped row,
@@ -95,8 +112,7 @@ template <int N, bool ABERR>
 __device__ __forceinline__ float2 row_input(const float* rbuf, const AxisTab& ct, float2 rowfac,
                                             const float2* __restrict__ aberr_row, int n) {
   const int x0 = ct.i0;
-  const int x1 = x0 + 1 < N ? x0 + 1 : N - 1;
-  const float r0 = rbuf[x0], r1 = rbuf[x1];
+  const float r0 = rbuf[x0], r1 = rbuf[x0 + 1];   // rbuf[N] is a zero pad
   const float J = r0 + ct.f * (r1 - r0);
   float2 fac = cmul(ct.fac, rowfac);
   if constexpr (ABERR) fac = cmul(fac, aberr_row[n]);
@@ -118,7 +134,7 @@ __device__ __forceinline__ void stage_ctab(AxisTab* ctab, const AxisTab* __restr
 
 // ------------------------------------------------------------------ forward row pass
 template <int N, bool ABERR, bool EQ6>
-__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass(
+__global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
     const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
     const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ aberr,
     const float2* __restrict__ outfac, float2* __restrict__ inter) {
@@ -148,7 +164,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass(
       src = load_rows<N>(I, rt.i0, j);
     }
     exchange_sync<R::WAVE>();  // previous row's FFT reads are done
-    lerp_rows(cur, rc.f, rbuf, j);
+    lerp_rows<N>(cur, rc.f, rbuf, j);
     exchange_sync<R::WAVE>();
     const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
     float2 v[16];
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     for (int k = 0; k < 16; ++k) v[k] = srow[j + k * G];
     fft_group<N, -1, R::WAVE>(v, j, lds.xbuf[g], 1, tw);
     exchange_sync<R::WAVE>();   // FFT reads of xbuf done before rbuf (aliased) is written
-    lerp_rows(cur, rc.f, rbuf, j);
+    lerp_rows<N>(cur, rc.f, rbuf, j);
     exchange_sync<R::WAVE>();
     const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
     const double y = (double)(m < half ? m : m - N) * inv;
