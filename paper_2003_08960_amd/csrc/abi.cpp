@@ -361,7 +361,6 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
-  }
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");
