@@ -58,6 +58,8 @@ extern "C" {
 #define SSOCT_EHIP (-3)           /* HIP runtime error (text in ssoct_last_error) */
 #define SSOCT_ENOMEM (-4)         /* device allocation failed, or workspace too small */
 #define SSOCT_EALIAS (-5)         /* output overlaps an input or the workspace */
+#define SSOCT_EDROPPED (-6)       /* streaming: a frame-sequence gap or a full ring; the incomplete sweep was discarded */
+#define SSOCT_EAGAIN (-7)         /* streaming: no finished volume yet (non-blocking pop) or no free slot */
 
 /* plan flags */
 #define SSOCT_PREC_FP32 0u        /* depth transform on FP32 MFMA */
@@ -147,6 +149,75 @@ int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const dou
  * stage (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth
  * transform, ms[3] the number of renders averaged.  Resets the record. */
 int ssoct_profile_read(ssoct_plan* plan, float* ms);
+
+/* ---------------------------------------------------------------- tuning
+ * Launch-shape parameters of a plan: tuning[0] frames per chunk of the
+ * Fresnel stage (1 .. the chunk the workspace was sized for), tuning[1]
+ * persistent column-pass workgroups (0 = default), tuning[2] persistent
+ * depth-transform workgroups (0 = default).  They change speed only, never
+ * results. */
+
+/* Time candidate launch shapes on the given inputs (HIP events on the plan's
+ * stream; synchronises the stream), keep the fastest in the plan and write it
+ * to tuning[3].  Arguments as for ssoct_render; vol is overwritten. */
+int ssoct_plan_tune(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
+                    const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                    void* vol, int* tuning);
+
+/* Read or set the launch-shape parameters (e.g. from a tuning cache). */
+int ssoct_plan_get_tuning(const ssoct_plan* plan, int* tuning);
+int ssoct_plan_set_tuning(ssoct_plan* plan, const int* tuning);
+
+/* ---------------------------------------------------------------- streaming
+ * Continuous rendering of consecutive sweeps (one volume per T frames) with
+ * a ring of `slots` volume slots.  Each slot owns device memory for one
+ * sweep of frames, a workspace, the complex volume and the three cuts, a HIP
+ * stream, and a HIP graph captured once at creation (render + cuts + copy of
+ * the cuts to pinned host memory), so successive volumes overlap (the depth
+ * transform of one with the Fresnel stage of the next) and each volume is
+ * one graph launch.  Physical parameters (lambda, pitch, z, disp_phase,
+ * zernike) and cut positions are fixed for the stream; the plan must not be
+ * used concurrently by other calls while the stream exists.  A stream object
+ * is safe to use from two threads (a producer pushing, a consumer popping). */
+typedef struct ssoct_stream ssoct_stream;
+
+int ssoct_stream_create(ssoct_stream** stream, ssoct_plan* plan, const double* lambda, double pitch, double z,
+                        const double* disp_phase, const double* zernike, int slots, int x0, int y0, int q0);
+
+/* Host-fed input: frames [nframes][N][N] in host memory (pinned memory gives
+ * asynchronous DMA; pageable memory is staged), with sequence numbers
+ * first_seq, first_seq + 1, ...  Frame seq belongs to sweep seq / T at
+ * position seq % T.  A sweep is rendered when its T frames have arrived in
+ * order.  A gap in the sequence, or a sweep that starts while every slot is
+ * in flight, discards the incomplete sweep and skips frames up to the next
+ * sweep start (seq % T == 0): the call then returns SSOCT_EDROPPED (after
+ * having accepted every other frame).  The host buffer must stay unchanged
+ * until the volume that contains its frames has been popped. */
+int ssoct_stream_push_frames(ssoct_stream* stream, const uint16_t* host_frames, int nframes, uint64_t first_seq);
+
+/* Device-resident input: take a free slot (SSOCT_EAGAIN if none) and get its
+ * device frame buffer [T][N][N]; fill it (any stream, synchronised before
+ * submit), then submit it as sweep `volume_seq`. */
+int ssoct_stream_acquire(ssoct_stream* stream, int* slot, uint16_t** device_frames);
+int ssoct_stream_submit(ssoct_stream* stream, int slot, uint64_t volume_seq);
+
+/* Oldest rendered volume, in submission order.  wait != 0 blocks until it is
+ * finished, wait == 0 returns SSOCT_EAGAIN if it is not.  Copies the cuts
+ * (host float [N][N], [T][N], [T][N]; any may be NULL) and returns the sweep
+ * number, the slot that rendered it, and the latency from submission (last
+ * frame pushed) to the end of its graph on the GPU, in ms.  Every output
+ * pointer may be NULL.  SSOCT_EAGAIN when nothing is in flight. */
+int ssoct_stream_pop(ssoct_stream* stream, int wait, uint64_t* volume_seq, int* slot, float* cut_xy,
+                     float* cut_xz, float* cut_yz, double* latency_ms);
+
+/* Device complex volume of a slot (valid between its pop and the slot's reuse). */
+int ssoct_stream_slot_volume(ssoct_stream* stream, int slot, const void** device_volume);
+
+/* counters[0] volumes completed, [1] frames dropped, [2] sweeps dropped, [3] volumes in flight */
+int ssoct_stream_stats(ssoct_stream* stream, uint64_t* counters);
+
+/* Wait for every volume in flight and release the stream. NULL is accepted. */
+int ssoct_stream_destroy(ssoct_stream* stream);
 
 #ifdef __cplusplus
 }

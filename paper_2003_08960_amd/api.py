@@ -141,3 +141,166 @@ class Plan:
         ms = (ctypes.c_float * 4)()
         native.check(self.lib.ssoct_profile_read(self._h, ms))
         return tuple(ms)
+
+    # -- launch shapes ---------------------------------------------------------------------------
+    def get_tuning(self):
+        t = (ctypes.c_int * 3)()
+        native.check(self.lib.ssoct_plan_get_tuning(self._h, t))
+        return [int(x) for x in t]
+
+    def set_tuning(self, tuning):
+        t = (ctypes.c_int * 3)(*[int(x) for x in tuning])
+        native.check(self.lib.ssoct_plan_set_tuning(self._h, t))
+
+    def tuning_key(self) -> str:
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        return f"{arch}|T{self.T}|N{self.N}|flags{self.flags & ~native.PROFILE}"
+
+    def tune(self, frames, lam, pitch, z, disp_phase=None, zernike=None, cache_path: str | None = None):
+        """Pick launch shapes by timing candidates (ssoct_plan_tune); with `cache_path`, reuse or store
+        the choice in a JSON cache keyed by GPU architecture, T, N and plan flags."""
+        key = self.tuning_key()
+        if cache_path:
+            cached = _load_cache(cache_path).get(key)
+            if cached is not None:
+                self.set_tuning(cached)
+                return list(cached)
+        _check_frames(frames, self.T, self.N)
+        out = self.render(frames, lam, pitch, z, disp_phase, zernike)
+        t = (ctypes.c_int * 3)()
+        self._sync_stream()
+        native.check(self.lib.ssoct_plan_tune(
+            self._h, ctypes.c_void_p(_ptr(frames)), native.host_doubles(lam, self.T), float(pitch), float(z),
+            native.host_doubles(disp_phase, self.T), native.host_doubles(zernike, 15),
+            ctypes.c_void_p(_ptr(self.workspace)), self.workspace.numel(), ctypes.c_void_p(_ptr(out)), t))
+        choice = [int(x) for x in t]
+        if cache_path:
+            data = _load_cache(cache_path)
+            data[key] = choice
+            _store_cache(cache_path, data)
+        return choice
+
+
+def _load_cache(path):
+    import json
+    import os
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def _store_cache(path, data):
+    import json
+    import os
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+class _DeviceArray:
+    """__cuda_array_interface__ view of library-owned device memory (no copy)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3, "strides": None}
+
+
+class Stream:
+    """ssoct_stream: continuous rendering of consecutive sweeps with a ring of volume slots."""
+
+    def __init__(self, plan: Plan, lam, pitch, z, disp_phase=None, zernike=None, slots: int = 3,
+                 x0: int | None = None, y0: int | None = None, q0: int | None = None):
+        self.plan, self.lib = plan, plan.lib
+        self.T, self.N = plan.T, plan.N
+        self.x0 = self.N // 2 if x0 is None else int(x0)
+        self.y0 = self.N // 2 if y0 is None else int(y0)
+        self.q0 = self.T // 4 if q0 is None else int(q0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            native.check(self.lib.ssoct_stream_create(
+                ctypes.byref(h), plan._h, native.host_doubles(lam, self.T), float(pitch), float(z),
+                native.host_doubles(disp_phase, self.T), native.host_doubles(zernike, 15), int(slots),
+                self.x0, self.y0, self.q0))
+        self._h = h
+        self._keep = []   # host buffers pushed and not yet popped
+
+    def push_frames(self, host_frames, first_seq: int) -> int:
+        """Push frames [n, N, N] uint16 (numpy array or CPU tensor; pinned memory is copied
+        asynchronously).  Returns OK or EDROPPED."""
+        arr = host_frames
+        if isinstance(arr, torch.Tensor):
+            if arr.is_cuda or arr.dtype != torch.uint16 or not arr.is_contiguous():
+                raise ValueError("host_frames must be a contiguous CPU uint16 tensor")
+            ptr, n = arr.data_ptr(), arr.shape[0]
+        else:
+            import numpy as np
+            if arr.dtype != np.uint16 or not arr.flags["C_CONTIGUOUS"]:
+                raise ValueError("host_frames must be a C-contiguous uint16 array")
+            ptr, n = arr.ctypes.data, arr.shape[0]
+        if tuple(arr.shape[1:]) != (self.N, self.N):
+            raise ValueError("frame shape mismatch")
+        self._keep.append(((int(first_seq) + n - 1) // self.T, arr))   # alive until its sweep is popped
+        rc = self.lib.ssoct_stream_push_frames(self._h, ctypes.c_void_p(ptr), int(n), ctypes.c_uint64(first_seq))
+        if rc == native.EDROPPED:
+            return rc
+        return native.check(rc)
+
+    def acquire(self):
+        """(slot, device frame buffer as a torch uint16 tensor [T, N, N]) or None if no slot is free."""
+        slot = ctypes.c_int()
+        ptr = ctypes.c_void_p()
+        rc = self.lib.ssoct_stream_acquire(self._h, ctypes.byref(slot), ctypes.byref(ptr))
+        if rc == native.EAGAIN:
+            return None
+        native.check(rc)
+        view = torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N), "<u2"), device=self.plan.device)
+        return slot.value, view
+
+    def submit(self, slot: int, volume_seq: int):
+        native.check(self.lib.ssoct_stream_submit(self._h, int(slot), ctypes.c_uint64(volume_seq)))
+
+    def pop(self, wait: bool = True, cuts: bool = True):
+        """Oldest finished volume as a dict (seq, slot, latency_ms, cut_xy, cut_xz, cut_yz), or None."""
+        import numpy as np
+        seq = ctypes.c_uint64()
+        slot = ctypes.c_int()
+        lat = ctypes.c_double()
+        xy = np.empty((self.N, self.N), np.float32) if cuts else None
+        xz = np.empty((self.T, self.N), np.float32) if cuts else None
+        yz = np.empty((self.T, self.N), np.float32) if cuts else None
+        ptr = (lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None)
+        rc = self.lib.ssoct_stream_pop(self._h, 1 if wait else 0, ctypes.byref(seq), ctypes.byref(slot), ptr(xy),
+                                       ptr(xz), ptr(yz), ctypes.byref(lat))
+        if rc == native.EAGAIN:
+            return None
+        native.check(rc)
+        self._keep = [(v, a) for v, a in self._keep if v > int(seq.value)]
+        return {"seq": int(seq.value), "slot": int(slot.value), "latency_ms": float(lat.value),
+                "cut_xy": xy, "cut_xz": xz, "cut_yz": yz}
+
+    def slot_volume(self, slot: int) -> torch.Tensor:
+        """Device complex volume of a slot (a view, valid until the slot is reused)."""
+        ptr = ctypes.c_void_p()
+        native.check(self.lib.ssoct_stream_slot_volume(self._h, int(slot), ctypes.byref(ptr)))
+        raw = torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N, 2), "<f4"), device=self.plan.device)
+        return torch.view_as_complex(raw)
+
+    def stats(self):
+        c = (ctypes.c_uint64 * 4)()
+        native.check(self.lib.ssoct_stream_stats(self._h, c))
+        return {"done": int(c[0]), "dropped_frames": int(c[1]), "dropped_sweeps": int(c[2]), "in_flight": int(c[3])}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ssoct_stream_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,17 +1,25 @@
-// C ABI: plans, argument checks, table caching and the order of kernel
-// launches for render, cuts and the two gradient entry points.
+// C ABI: plans, argument checks, table caching, launch shapes (tuning) and
+// the order of kernel launches for render, cuts and the gradient entry points.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/ssoct.h"
-#include "internal.hpp"
+#include "plan.hpp"
 
 using namespace ssoct;
 
-namespace {
+// Fresnel-stage chunking: the row pass of a chunk of frames writes a buffer
+// of SSOCT_CHUNK_MIB that the column pass reads right after.  (Overlapping
+// the two passes on two streams with a ring of buffers was measured slower:
+// the per-chunk cross-stream waits cost more than the overlap.)
+#ifndef SSOCT_CHUNK_MIB
+#define SSOCT_CHUNK_MIB 128
+#endif
+
+namespace ssoct {
 
 thread_local std::string g_err;
 
@@ -25,23 +33,9 @@ int hip_fail(hipError_t e, const char* where) {
   return SSOCT_EHIP;
 }
 
-#define SSOCT_HIP(call)                              \
-  do {                                               \
-    hipError_t e_ = (call);                          \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
-
-// Fresnel-stage chunking: the row pass of a chunk of frames writes a buffer
-// of SSOCT_CHUNK_MIB that the column pass reads right after.  (Overlapping
-// the two passes on two streams with a ring of buffers was measured slower:
-// the per-chunk cross-stream waits cost more than the overlap.)
-#ifndef SSOCT_CHUNK_MIB
-#define SSOCT_CHUNK_MIB 128
-#endif
+static bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
 
 int frames_per_chunk(int T, int N) {
   // one chunk of row-transformed frames (8 bytes per pixel) near SSOCT_CHUNK_MIB
@@ -51,10 +45,6 @@ int frames_per_chunk(int T, int N) {
   if (f > (size_t)T) f = (size_t)T;
   return (int)f;
 }
-
-struct WsLayout {
-  size_t H, inter, B2, mono, loss, total;
-};
 
 WsLayout ws_layout(int T, int N, uint32_t flags, int F) {
   WsLayout w{};
@@ -80,7 +70,7 @@ WsLayout ws_layout(int T, int N, uint32_t flags, int F) {
 // fixed order (a + b <= 4): Z_j = norm * R_n^|m|(rho) * {cos, sin}(|m| theta),
 // with rho^|m| cos(|m| theta) = Re (x + i y)^|m|, rho^|m| sin = Im, and the
 // remaining even power of rho as (x^2 + y^2)^k.
-void zernike_monomials(double zmat[15][N_MONO]) {
+static void zernike_monomials(double zmat[15][N_MONO]) {
   static const int A[N_MONO] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
   static const int B[N_MONO] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
   auto fact = [](int n) {
@@ -90,28 +80,26 @@ void zernike_monomials(double zmat[15][N_MONO]) {
   };
   auto binom = [&](int n, int k) { return fact(n) / (fact(k) * fact(n - k)); };
   for (int j = 0; j < 15; ++j) {
-    int n = (int)std::ceil((-3.0 + std::sqrt(9.0 + 8.0 * j)) / 2.0);
-    int m = 2 * j - n * (n + 2);
-    int am = m < 0 ? -m : m;
-    double poly[5][5] = {};  // poly[a][b]
-    // angular factor Re/Im (x + i y)^am
-    double ang[5][5] = {};
+    const int n = (int)std::ceil((-3.0 + std::sqrt(9.0 + 8.0 * j)) / 2.0);
+    const int m = 2 * j - n * (n + 2);
+    const int am = m < 0 ? -m : m;
+    double poly[5][5] = {};  // poly[a][b]: coefficient of x^a y^b
+    double ang[5][5] = {};   // Re (m >= 0) or Im (m < 0) of (x + i y)^|m|
     for (int r = 0; r <= am; ++r) {
-      const double c = binom(am, r);
-      // term c x^(am-r) (i y)^r ; i^r = (-1)^(r/2) for even r, i (-1)^((r-1)/2) for odd r
+      const double c = binom(am, r);  // c x^(am-r) (i y)^r
       if (m >= 0 && r % 2 == 0) ang[am - r][r] += c * ((r / 2) % 2 ? -1.0 : 1.0);
       if (m < 0 && r % 2 == 1) ang[am - r][r] += c * (((r - 1) / 2) % 2 ? -1.0 : 1.0);
     }
     const int p = (n - am) / 2;
     for (int k = 0; k <= p; ++k) {
-      const double rc = ((k % 2) ? -1.0 : 1.0) * fact(n - k) / (fact(k) * fact((n + am) / 2 - k) * fact((n - am) / 2 - k));
-      const int e = p - k;  // (x^2 + y^2)^e
+      const double rc =
+          ((k % 2) ? -1.0 : 1.0) * fact(n - k) / (fact(k) * fact((n + am) / 2 - k) * fact((n - am) / 2 - k));
+      const int e = p - k;  // times (x^2 + y^2)^e
       for (int r = 0; r <= e; ++r) {
         const double bc = binom(e, r);
         for (int a = 0; a + 2 * (e - r) <= 4; ++a)
           for (int b = 0; b + 2 * r <= 4; ++b)
-            if (ang[a][b] != 0.0 && a + 2 * (e - r) <= 4 && b + 2 * r <= 4)
-              poly[a + 2 * (e - r)][b + 2 * r] += rc * bc * ang[a][b];
+            if (ang[a][b] != 0.0) poly[a + 2 * (e - r)][b + 2 * r] += rc * bc * ang[a][b];
       }
     }
     const double norm = std::sqrt((m == 0 ? 1.0 : 2.0) * (n + 1));
@@ -119,33 +107,7 @@ void zernike_monomials(double zmat[15][N_MONO]) {
   }
 }
 
-}  // namespace
-
-struct ssoct_plan {
-  int T = 0, N = 0, F = 0, device = 0, cu = 0;
-  uint32_t flags = 0;
-  hipStream_t stream = nullptr;
-  DepthLayout dl{};
-  AxisTab* rows = nullptr;
-  AxisTab* cols = nullptr;
-  float2* tw = nullptr;
-  float2* outfac = nullptr;
-  float2* aberr = nullptr;
-  double* params = nullptr;      // ParamLayout + alpha/z [T] + zmat [225]
-  float* a_f32 = nullptr;
-  uint4* a_f16 = nullptr;
-  uint4* a_bf16 = nullptr;
-  double zmat[15][N_MONO];
-  std::vector<double> cache;     // last parameter set the tables were built from
-  bool have_aberr = false;
-  static constexpr int MAXREC = 256;  // renders kept by the profiling record
-  std::vector<hipEvent_t> ev;          // [MAXREC][4] with SSOCT_PROFILE
-  int rec = 0;                         // renders recorded since the last read
-};
-
-namespace {
-
-void plan_free(ssoct_plan* p) {
+static void plan_free(ssoct_plan* p) {
   if (!p) return;
   (void)hipFree(p->rows);
   (void)hipFree(p->cols);
@@ -161,13 +123,13 @@ void plan_free(ssoct_plan* p) {
   delete p;
 }
 
-bool finite_all(const double* a, int n) {
+static bool finite_all(const double* a, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
   return true;
 }
 
-bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
   return pa < pb + nb && pb < pa + na;
@@ -181,16 +143,21 @@ int depth_prec(uint32_t flags) {
   return DP_F32;
 }
 
-int h_format(int prec) {
+static int h_format(int prec) {
   if (prec == DP_F16 || prec == DP_F16_SPLIT) return HF_F16;
   if (prec == DP_BF16 || prec == DP_BF16_SPLIT) return HF_BF16;
   return HF_F32;
 }
 
-const void* amat_for(const ssoct_plan* p, int prec) {
+static const void* amat_for(const ssoct_plan* p, int prec) {
   if (prec == DP_F32) return p->a_f32;
   if (prec == DP_F16 || prec == DP_F16_SPLIT) return p->a_f16;
   return p->a_bf16;
+}
+
+int check_plan(const ssoct_plan* p) {
+  if (!p) return fail(SSOCT_EINVAL, "plan is NULL");
+  return SSOCT_OK;
 }
 
 // Validate the per-call physical parameters and (re)build the tables when
@@ -223,6 +190,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   key.push_back(zern ? 1.0 : 0.0);
   if (zern) key.insert(key.end(), zern, zern + 15);
   if (key == p->cache) return status;
+  if (p->streaming) return fail(SSOCT_EINVAL, "the plan's parameters are fixed while a stream uses it");
 
   const bool exact = (p->flags & SSOCT_CHIRP_EXACT) != 0;
   const bool eq6 = (p->flags & SSOCT_EQ6_PHASE) != 0;
@@ -231,13 +199,13 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   const double eq6_cyc = eq6 ? 0.25 - (z / lam1 - std::floor(z / lam1)) : 0.0;
   for (int t = 0; t < T; ++t) {
     const double s = lambda[t] / lam1;
-    const double kappa = pitch * pitch * (exact ? s : 1.0) / (2.0 * lam1 * z);   // alpha_t / (2 pi)
+    const double kappa = pitch * pitch * (exact ? s : 1.0) / (2.0 * lam1 * z);  // alpha_t / (2 pi)
     double* pf = &h[(size_t)ParamLayout::PER_FRAME * t];
     pf[0] = s;
     pf[1] = kappa;
     pf[2] = (disp ? disp[t] / two_pi : 0.0) + eq6_cyc;
     pf[3] = eq6 ? pitch * pitch / (lam1 * z) : 1.0;
-    h[ParamLayout::count(T) + t] = two_pi * kappa / z;   // alpha_t / z
+    h[ParamLayout::count(T) + t] = two_pi * kappa / z;  // alpha_t / z
   }
   double* g = &h[ParamLayout::globals(T)];
   g[ParamLayout::G_KAPPA_OUT] = lam1 * z / (2.0 * (double)N * N * pitch * pitch);
@@ -250,46 +218,66 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     g[ParamLayout::G_HAS_ABERR] = 1.0;
   }
   std::memcpy(&h[ParamLayout::count(T) + T], &p->zmat[0][0], sizeof(double) * 15 * N_MONO);
-  if (zern && !p->aberr) {
-    SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
-  }
+  if (zern && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
   SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern ? p->aberr : nullptr, p->stream));
   p->have_aberr = zern != nullptr;
+  // FP16 operands: |H| <= N^2 * 65535 * amplitude, kept below 2^15 by an exact power-of-two scale
+  p->sigma = 0;
+  if (h_format(depth_prec(p->flags)) == HF_F16) {
+    const double amp = eq6 ? std::fabs(pitch * pitch / (lam1 * z)) : 1.0;
+    p->sigma = (int)std::ceil(std::log2((double)N * N * 65535.0 * amp / 32768.0));
+  }
   p->cache.swap(key);
   return status;
 }
 
-int check_plan(const ssoct_plan* p) {
-  if (!p) return fail(SSOCT_EINVAL, "plan is NULL");
-  return SSOCT_OK;
-}
-
 // Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
 // row DFT) into the chunk buffer, then column DFT into H.
-int forward_stage_a(ssoct_plan* p, const uint16_t* frames, void* H, float2* inter, int fmt, int sigma) {
-  const int T = p->T, N = p->N;
+static int forward_stage_a(ssoct_plan* p, hipStream_t s, const uint16_t* frames, void* H, float2* inter, int fmt,
+                           int sigma) {
+  const int T = p->T, N = p->N, F = p->F_run;
   const float2* ab = p->have_aberr ? p->aberr : nullptr;
-  for (int t0 = 0; t0 < T; t0 += p->F) {
-    const int Fc = T - t0 < p->F ? T - t0 : p->F;
-    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));
-    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, fmt, sigma, p->stream));
+  for (int t0 = 0; t0 < T; t0 += F) {
+    const int Fc = T - t0 < F ? T - t0 : F;
+    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
+    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, fmt, sigma, p->col_grid, s));
   }
   return SSOCT_OK;
 }
 
-int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
-                  const double* loss_partials, int n_loss, double grad_scale, double* out) {
+static int depth_grid_for(const ssoct_plan* p) {
+  return p->depth_grid > 0 ? p->depth_grid : depth_grid(p->T, p->N * p->N, p->cu);
+}
+
+int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
+                hipEvent_t* ev) {
   const int T = p->T, N = p->N;
+  const int prec = depth_prec(p->flags);
+  const int fmt = h_format(prec);
+  void* H = ws + L.H;
+  if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
+  if (int rc = forward_stage_a(p, s, frames, H, reinterpret_cast<float2*>(ws + L.inter), fmt, p->sigma)) return rc;
+  if (ev) SSOCT_HIP(hipEventRecord(ev[2], s));
+  const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
+  SSOCT_HIP(launch_depth(T, N * N, prec, +1, epi, H, amat_for(p, prec), vol, p->sigma, 0, nullptr, depth_grid_for(p),
+                         s));
+  if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
+  return SSOCT_OK;
+}
+
+static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
+                         const double* loss_partials, int n_loss, double grad_scale, double* out) {
+  const int T = p->T, N = p->N, F = p->F_run;
   float2* beta = reinterpret_cast<float2*>(ws + L.H);
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   double* mono = reinterpret_cast<double*>(ws + L.mono);
-  const int grid = depth_grid(T, N * N, p->cu);
-  SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, grid, p->stream));
-  for (int t0 = 0; t0 < T; t0 += p->F) {
-    const int Fc = T - t0 < p->F ? T - t0 : p->F;
-    SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->stream));
+  SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, depth_grid_for(p),
+                         p->stream));
+  for (int t0 = 0; t0 < T; t0 += F) {
+    const int Fc = T - t0 < F ? T - t0 : F;
+    SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->col_grid, p->stream));
     SSOCT_HIP(launch_row_pass_adj(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->aberr : nullptr,
                                   inter, mono, p->stream));
   }
@@ -300,16 +288,21 @@ int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws
   return SSOCT_OK;
 }
 
-int fresnel_sigma(const ssoct_plan* p, int prec, double pitch, double z, double lam1) {
-  if (h_format(prec) != HF_F16) return 0;
-  // |H| <= N^2 * 65535 * amplitude; keep it below 2^15 in FP16
-  double amp = 1.0;
-  if (p->flags & SSOCT_EQ6_PHASE) amp = std::fabs(pitch * pitch / (lam1 * z));
-  const double bound = (double)p->N * p->N * 65535.0 * amp;
-  return (int)std::ceil(std::log2(bound / 32768.0));
+// argument checks shared by render and tune
+static int check_render_args(ssoct_plan* p, const uint16_t* frames, void* workspace, size_t workspace_bytes,
+                             void* vol, WsLayout* L) {
+  if (int rc = check_plan(p)) return rc;
+  if (!frames || !workspace || !vol) return fail(SSOCT_EINVAL, "frames, workspace and vol must be non-NULL");
+  const int T = p->T, N = p->N;
+  *L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
+  if (workspace_bytes < L->total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size()");
+  const size_t vol_bytes = (size_t)T * N * N * ((p->flags & SSOCT_WRITE_ABS) ? 4 : 8);
+  if (overlap(vol, vol_bytes, frames, (size_t)T * N * N * 2) || overlap(vol, vol_bytes, workspace, workspace_bytes))
+    return fail(SSOCT_EALIAS, "vol overlaps frames or workspace");
+  return SSOCT_OK;
 }
 
-}  // namespace
+}  // namespace ssoct
 
 extern "C" {
 
@@ -337,6 +330,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   p->flags = flags;
   p->stream = stream;
   p->F = frames_per_chunk(T, N);
+  p->F_run = p->F;
   p->dl = depth_layout(T);
   zernike_monomials(p->zmat);
   hipError_t e = hipGetDevice(&p->device);
@@ -345,9 +339,9 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   const size_t nparams = ParamLayout::count(T) + T + 15 * N_MONO;
   const size_t na32 = (size_t)p->dl.nrb * (p->dl.T_pad / 2) * 64;
   const size_t na16 = (size_t)p->dl.nrb * (p->dl.T_pad / 16) * 128;
+  const size_t ntw = twiddle_table_size(N);
   if (e == hipSuccess) e = hipMalloc(&p->rows, axis);
   if (e == hipSuccess) e = hipMalloc(&p->cols, axis);
-  const size_t ntw = twiddle_table_size(N);
   if (e == hipSuccess) e = hipMalloc(&p->tw, (ntw > 0 ? ntw : 1) * sizeof(float2));
   if (e == hipSuccess && (flags & SSOCT_EQ6_PHASE)) e = hipMalloc(&p->outfac, (size_t)N * sizeof(float2));
   if (e == hipSuccess) e = hipMalloc(&p->params, nparams * sizeof(double));
@@ -387,37 +381,16 @@ int ssoct_plan_destroy(ssoct_plan* plan) {
 int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
                  const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                  void* vol) {
-  if (int rc = check_plan(p)) return rc;
-  if (!frames || !workspace || !vol) return fail(SSOCT_EINVAL, "frames, workspace and vol must be non-NULL");
-  const int T = p->T, N = p->N;
-  const WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
-  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size()");
-  const size_t vol_bytes = (size_t)T * N * N * ((p->flags & SSOCT_WRITE_ABS) ? 4 : 8);
-  if (overlap(vol, vol_bytes, frames, (size_t)T * N * N * 2) || overlap(vol, vol_bytes, workspace, workspace_bytes))
-    return fail(SSOCT_EALIAS, "vol overlaps frames or workspace");
+  WsLayout L;
+  if (int rc = check_render_args(p, frames, workspace, workspace_bytes, vol, &L)) return rc;
   SSOCT_HIP(hipSetDevice(p->device));
   const bool prof = (p->flags & SSOCT_PROFILE) != 0;
   hipEvent_t* ev = prof ? &p->ev[(size_t)(p->rec % ssoct_plan::MAXREC) * 4] : nullptr;
   if (prof) SSOCT_HIP(hipEventRecord(ev[0], p->stream));
   const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
   if (status < 0) return status;
-  const int prec = depth_prec(p->flags);
-  const int fmt = h_format(prec);
-  double lam1 = lambda[0];
-  for (int t = 1; t < T; ++t) lam1 = lambda[t] > lam1 ? lambda[t] : lam1;
-  const int sigma = fresnel_sigma(p, prec, pitch, z, lam1);
-  char* ws = static_cast<char*>(workspace);
-  void* H = ws + L.H;
-  if (prof) SSOCT_HIP(hipEventRecord(ev[1], p->stream));
-  if (int rc = forward_stage_a(p, frames, H, reinterpret_cast<float2*>(ws + L.inter), fmt, sigma)) return rc;
-  if (prof) SSOCT_HIP(hipEventRecord(ev[2], p->stream));
-  const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
-  const int grid = depth_grid(T, N * N, p->cu);
-  SSOCT_HIP(launch_depth(T, N * N, prec, +1, epi, H, amat_for(p, prec), vol, sigma, 0, nullptr, grid, p->stream));
-  if (prof) {
-    SSOCT_HIP(hipEventRecord(ev[3], p->stream));
-    ++p->rec;
-  }
+  if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev)) return rc;
+  if (prof) ++p->rec;
   return status;
 }
 
@@ -445,7 +418,8 @@ int ssoct_backward(ssoct_plan* p, const uint16_t* frames, const double* lambda, 
     return fail(SSOCT_EINVAL, "frames, grad_vol, workspace and grad_out must be non-NULL");
   const int T = p->T, N = p->N;
   const WsLayout L = ws_layout(T, N, p->flags | SSOCT_BACKWARD, p->F);
-  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
+  if (workspace_bytes < L.total)
+    return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
   if (overlap(grad_out, (size_t)(17 + T) * 8, workspace, workspace_bytes) ||
       overlap(grad_vol, (size_t)T * N * N * 8, workspace, workspace_bytes))
     return fail(SSOCT_EALIAS, "grad_vol or grad_out overlaps the workspace");
@@ -464,7 +438,8 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   if (!frames || !workspace || !grad_out) return fail(SSOCT_EINVAL, "frames, workspace and grad_out must be non-NULL");
   const int T = p->T, N = p->N;
   const WsLayout L = ws_layout(T, N, p->flags | SSOCT_BACKWARD, p->F);
-  if (workspace_bytes < L.total) return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
+  if (workspace_bytes < L.total)
+    return fail(SSOCT_ENOMEM, "workspace smaller than ssoct_workspace_size(SSOCT_BACKWARD)");
   if (overlap(grad_out, (size_t)(17 + T) * 8, workspace, workspace_bytes))
     return fail(SSOCT_EALIAS, "grad_out overlaps the workspace");
   SSOCT_HIP(hipSetDevice(p->device));
@@ -474,12 +449,14 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   void* H = ws + L.H;
   float2* gam = reinterpret_cast<float2*>(ws + L.B2);
   double* loss = reinterpret_cast<double*>(ws + L.loss);
-  if (int rc = forward_stage_a(p, frames, H, reinterpret_cast<float2*>(ws + L.inter), HF_F32, 0)) return rc;
+  if (int rc = forward_stage_a(p, p->stream, frames, H, reinterpret_cast<float2*>(ws + L.inter), HF_F32, 0))
+    return rc;
   // |V| <= T N^2 65535: scale by 2^-e so that 4 |V^|^3 stays finite in FP32
   const double bound = (double)T * N * N * 65535.0;
   int e = (int)std::ceil(std::log2(bound)) - 40;
   if (e < 0) e = 0;
-  const int grid = depth_grid(T, N * N, p->cu);
+  const int grid = depth_grid_for(p);
+  if (grid > 4096) return fail(SSOCT_EINVAL, "depth grid larger than the loss-partial buffer");
   SSOCT_HIP(launch_depth(T, N * N, DP_F32, +1, EPI_GAMMA, H, p->a_f32, gam, 0, e, loss, grid, p->stream));
   if (int rc = adjoint_chain(p, frames, gam, ws, L, loss, grid, std::ldexp(1.0, 3 * e), grad_out)) return rc;
   return status;
@@ -506,6 +483,87 @@ int ssoct_profile_read(ssoct_plan* p, float* ms) {
   ms[3] = (float)n;
   p->rec = 0;
   return SSOCT_OK;
+}
+
+int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
+  if (int rc = check_plan(p)) return rc;
+  if (!tuning) return fail(SSOCT_EINVAL, "tuning is NULL");
+  tuning[0] = p->F_run;
+  tuning[1] = p->col_grid;
+  tuning[2] = p->depth_grid;
+  return SSOCT_OK;
+}
+
+int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
+  if (int rc = check_plan(p)) return rc;
+  if (!tuning) return fail(SSOCT_EINVAL, "tuning is NULL");
+  if (tuning[0] < 1 || tuning[0] > p->F) return fail(SSOCT_EINVAL, "frames per chunk out of range");
+  if (tuning[1] < 0 || tuning[1] > 65536 || tuning[2] < 0 || tuning[2] > 4096)
+    return fail(SSOCT_EINVAL, "workgroup count out of range");
+  p->F_run = tuning[0];
+  p->col_grid = tuning[1];
+  p->depth_grid = tuning[2];
+  return SSOCT_OK;
+}
+
+int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
+                    const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                    void* vol, int* tuning) {
+  WsLayout L;
+  if (int rc = check_render_args(p, frames, workspace, workspace_bytes, vol, &L)) return rc;
+  SSOCT_HIP(hipSetDevice(p->device));
+  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
+  if (status < 0) return status;
+  hipEvent_t ev[4];
+  for (auto& e : ev) SSOCT_HIP(hipEventCreate(&e));
+  auto measure = [&](float* stage_a, float* stage_b) -> int {
+    float best_a = 1e30f, best_b = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev)) return rc;
+      SSOCT_HIP(hipEventSynchronize(ev[3]));
+      float a = 0, b = 0;
+      SSOCT_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+      SSOCT_HIP(hipEventElapsedTime(&b, ev[2], ev[3]));
+      if (rep > 0) {  // first run warms caches and code
+        best_a = a < best_a ? a : best_a;
+        best_b = b < best_b ? b : best_b;
+      }
+    }
+    *stage_a = best_a;
+    *stage_b = best_b;
+    return SSOCT_OK;
+  };
+  // Fresnel stage: frames per chunk x persistent column workgroups
+  int bestF = p->F_run, bestC = p->col_grid, bestD = p->depth_grid;
+  float best = 1e30f, a, b;
+  const int Fs[3] = {p->F, p->F / 2, p->F / 4};
+  const int Cs[3] = {0, 256, 1024};
+  int rc = SSOCT_OK;
+  for (int fi = 0; fi < 3 && rc == SSOCT_OK; ++fi) {
+    if (Fs[fi] < 1 || (fi > 0 && Fs[fi] == Fs[fi - 1])) continue;
+    for (int ci = 0; ci < 3 && rc == SSOCT_OK; ++ci) {
+      p->F_run = Fs[fi];
+      p->col_grid = Cs[ci];
+      rc = measure(&a, &b);
+      if (rc == SSOCT_OK && a < best) best = a, bestF = Fs[fi], bestC = Cs[ci];
+    }
+  }
+  p->F_run = bestF;
+  p->col_grid = bestC;
+  // depth transform: default persistent grid or twice as many workgroups
+  const int d0 = depth_grid(p->T, p->N * p->N, p->cu);
+  const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};
+  best = 1e30f;
+  for (int di = 0; di < 2 && rc == SSOCT_OK; ++di) {
+    p->depth_grid = Ds[di];
+    rc = measure(&a, &b);
+    if (rc == SSOCT_OK && b < best) best = b, bestD = Ds[di];
+  }
+  p->depth_grid = bestD;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc != SSOCT_OK) return rc;
+  if (tuning) ssoct_plan_get_tuning(p, tuning);
+  return status;
 }
 
 }  // extern "C"

@@ -88,13 +88,13 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
                            const AxisTab* cols, const float2* tw, const float2* aberr,
                            const float2* outfac, float2* inter, hipStream_t s);
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
-                           const float2* outfac, void* H, int fmt, int sigma, hipStream_t s);
+                           const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
 
 // Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
 // into `inter`, then row DFT^- fused with the recomputed row input and the
 // per-frame FP64 moments of Im(conj(g) z) (partials [T][nblk][N_MONO]).
 hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw,
-                               float2* inter, hipStream_t s);
+                               float2* inter, int grid, hipStream_t s);
 hipError_t launch_row_pass_adj(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
                                const AxisTab* cols, const float2* tw, const float2* aberr,
                                const float2* inter, double* partials, hipStream_t s);

@@ -1,0 +1,74 @@
+// Host-side plan object shared by the C ABI (abi.cpp) and the streaming
+// engine (stream.cpp).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/ssoct.h"
+#include "internal.hpp"
+
+namespace ssoct {
+
+// Workspace layout: H stack, one chunk of row-transformed frames, and with
+// SSOCT_BACKWARD a second stack plus the FP64 reduction partials.
+struct WsLayout {
+  size_t H, inter, B2, mono, loss, total;
+};
+WsLayout ws_layout(int T, int N, uint32_t flags, int F);
+int frames_per_chunk(int T, int N);
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* where);
+
+#define SSOCT_HIP(call)                                \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return ssoct::hip_fail(e_, #call); \
+  } while (0)
+
+}  // namespace ssoct
+
+struct ssoct_plan {
+  int T = 0, N = 0, device = 0, cu = 0;
+  int F = 0;                   // frames per chunk the workspace is sized for
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  ssoct::DepthLayout dl{};
+  // launch shapes (ssoct_plan_tune / ssoct_plan_set_tuning)
+  int F_run = 0;               // frames per chunk in use (1 .. F)
+  int col_grid = 0;            // persistent column workgroups (0 = default)
+  int depth_grid = 0;          // persistent depth workgroups (0 = default)
+  // device tables
+  ssoct::AxisTab* rows = nullptr;
+  ssoct::AxisTab* cols = nullptr;
+  float2* tw = nullptr;
+  float2* outfac = nullptr;
+  float2* aberr = nullptr;
+  double* params = nullptr;    // ParamLayout + alpha/z [T] + zmat [15 x 15]
+  float* a_f32 = nullptr;
+  uint4* a_f16 = nullptr;
+  uint4* a_bf16 = nullptr;
+  double zmat[15][ssoct::N_MONO];
+  std::vector<double> cache;   // parameter set the tables were last built from
+  bool have_aberr = false;
+  int sigma = 0;               // FP16 operand scale exponent for the current tables
+  // profiling record
+  static constexpr int MAXREC = 256;
+  std::vector<hipEvent_t> ev;  // [MAXREC][4] with SSOCT_PROFILE
+  int rec = 0;
+  bool streaming = false;      // a stream object uses the plan's tables
+};
+
+namespace ssoct {
+
+int check_plan(const ssoct_plan* p);
+int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, const double* disp,
+                  const double* zern, bool for_backward);
+int depth_prec(uint32_t flags);
+// Enqueue one forward render on `stream` (tables must be current): Fresnel
+// stage into the workspace, depth transform into vol.  `ev` (4 events or
+// null) brackets the stages for the profiling record.
+int render_core(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
+                hipEvent_t* ev);
+
+}  // namespace ssoct

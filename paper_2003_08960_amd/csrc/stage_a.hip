@@ -380,18 +380,18 @@ static hipError_t row_pass_n(int F, int t0, const uint16_t* frames, const AxisTa
   return hipGetLastError();
 }
 
-static int col_grid(int ntiles) {
-  // persistent: about two resident workgroups per CU of the 256 on MI355X
-  const int g = 512;
+// persistent column workgroups: `req` (from the tuner) or 512 (two per CU of the 256 on MI355X)
+static int col_grid(int ntiles, int req) {
+  const int g = req > 0 ? req : 512;
   return ntiles < g ? ntiles : g;
 }
 
 template <int N>
 static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                             int fmt, int sigma, hipStream_t s) {
+                             int fmt, int sigma, int req_grid, hipStream_t s) {
   using C = ColCfg<N>;
   const int ntiles = F * (N / C::C);
-  dim3 grid(col_grid(ntiles)), block(C::THREADS);
+  dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
   const float scale = ldexpf(1.0f, -sigma);
   char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
   const bool eq6 = outfac != nullptr;
@@ -406,10 +406,11 @@ static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* t
 }
 
 template <int N>
-static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* tw, float2* inter, hipStream_t s) {
+static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* tw, float2* inter, int req_grid,
+                                 hipStream_t s) {
   using C = ColCfg<N>;
   const int ntiles = F * (N / C::C);
-  dim3 grid(col_grid(ntiles)), block(C::THREADS);
+  dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
   const float2* src = B + (size_t)t0 * N * N;
   hipLaunchKernelGGL((k_col_pass<N, -1, HF_F32, false>), grid, block, 0, s, src, tw, (const float2*)nullptr,
                      (void*)inter, 1.0f, ntiles);
@@ -450,14 +451,15 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
 }
 
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                           int fmt, int sigma, hipStream_t s) {
-#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, s)
+                           int fmt, int sigma, int grid, hipStream_t s) {
+#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, grid, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
 
-hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw, float2* inter, hipStream_t s) {
-#define CALL(n) col_pass_adj_n<n>(F, t0, B, tw, inter, s)
+hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw, float2* inter, int grid,
+                               hipStream_t s) {
+#define CALL(n) col_pass_adj_n<n>(F, t0, B, tw, inter, grid, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }

@@ -20,6 +20,8 @@ EUNSUPPORTED = -2
 EHIP = -3
 ENOMEM = -4
 EALIAS = -5
+EDROPPED = -6
+EAGAIN = -7
 
 PREC_FP32 = 0
 PREC_FP16 = 1
@@ -35,10 +37,14 @@ PROFILE = 256
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",
     "ssoct_plan_set_stream", "ssoct_plan_destroy", "ssoct_render", "ssoct_cuts", "ssoct_backward",
-    "ssoct_backward_sharpness", "ssoct_profile_read",
+    "ssoct_backward_sharpness", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
+    "ssoct_plan_set_tuning", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
+    "ssoct_stream_submit", "ssoct_stream_pop", "ssoct_stream_slot_volume", "ssoct_stream_stats",
+    "ssoct_stream_destroy",
 )
 
-_NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EHIP: "EHIP", ENOMEM: "ENOMEM", EALIAS: "EALIAS"}
+_NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EHIP: "EHIP", ENOMEM: "ENOMEM", EALIAS: "EALIAS",
+          EDROPPED: "EDROPPED", EAGAIN: "EAGAIN"}
 
 
 class SsoctError(RuntimeError):
@@ -81,6 +87,32 @@ def _declare(lib):
                                              c_size_t, c_void_p]
     lib.ssoct_profile_read.restype = c_int
     lib.ssoct_profile_read.argtypes = [c_void_p, _fptr]
+    _iptr = ctypes.POINTER(c_int)
+    lib.ssoct_plan_tune.restype = c_int
+    lib.ssoct_plan_tune.argtypes = [c_void_p, c_void_p, _dptr, c_double, c_double, _dptr, _dptr, c_void_p, c_size_t,
+                                    c_void_p, _iptr]
+    lib.ssoct_plan_get_tuning.restype = c_int
+    lib.ssoct_plan_get_tuning.argtypes = [c_void_p, _iptr]
+    lib.ssoct_plan_set_tuning.restype = c_int
+    lib.ssoct_plan_set_tuning.argtypes = [c_void_p, _iptr]
+    lib.ssoct_stream_create.restype = c_int
+    lib.ssoct_stream_create.argtypes = [ctypes.POINTER(c_void_p), c_void_p, _dptr, c_double, c_double, _dptr, _dptr,
+                                        c_int, c_int, c_int, c_int]
+    lib.ssoct_stream_push_frames.restype = c_int
+    lib.ssoct_stream_push_frames.argtypes = [c_void_p, c_void_p, c_int, ctypes.c_uint64]
+    lib.ssoct_stream_acquire.restype = c_int
+    lib.ssoct_stream_acquire.argtypes = [c_void_p, _iptr, ctypes.POINTER(c_void_p)]
+    lib.ssoct_stream_submit.restype = c_int
+    lib.ssoct_stream_submit.argtypes = [c_void_p, c_int, ctypes.c_uint64]
+    lib.ssoct_stream_pop.restype = c_int
+    lib.ssoct_stream_pop.argtypes = [c_void_p, c_int, ctypes.POINTER(ctypes.c_uint64), _iptr, c_void_p, c_void_p,
+                                     c_void_p, _dptr]
+    lib.ssoct_stream_slot_volume.restype = c_int
+    lib.ssoct_stream_slot_volume.argtypes = [c_void_p, c_int, ctypes.POINTER(c_void_p)]
+    lib.ssoct_stream_stats.restype = c_int
+    lib.ssoct_stream_stats.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ssoct_stream_destroy.restype = c_int
+    lib.ssoct_stream_destroy.argtypes = [c_void_p]
     return lib
 
 

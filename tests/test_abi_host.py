@@ -90,3 +90,25 @@ def test_binding_raises_with_message(lib):
         native.check(native.EINVAL)
     assert "EINVAL" in str(e.value)
     assert native.check(native.WARN_UNDERSAMPLED) == native.WARN_UNDERSAMPLED
+
+
+def test_stream_and_tuning_entry_points_reject_null(lib):
+    from paper_2003_08960_amd import native
+    lam = (ctypes.c_double * 4)(1e-6, 1e-6, 1e-6, 1e-6)
+    h = ctypes.c_void_p(99)
+    assert lib.ssoct_stream_create(ctypes.byref(h), None, lam, 1e-5, 0.1, None, None, 2, 0, 0, 0) == native.EINVAL
+    assert not h.value
+    assert lib.ssoct_stream_create(None, None, lam, 1e-5, 0.1, None, None, 2, 0, 0, 0) == native.EINVAL
+    assert lib.ssoct_stream_push_frames(None, None, 1, 0) == native.EINVAL
+    slot = ctypes.c_int()
+    ptr = ctypes.c_void_p()
+    assert lib.ssoct_stream_acquire(None, ctypes.byref(slot), ctypes.byref(ptr)) == native.EINVAL
+    assert lib.ssoct_stream_submit(None, 0, 0) == native.EINVAL
+    assert lib.ssoct_stream_pop(None, 1, None, None, None, None, None, None) == native.EINVAL
+    c = (ctypes.c_uint64 * 4)()
+    assert lib.ssoct_stream_stats(None, c) == native.EINVAL
+    assert lib.ssoct_stream_destroy(None) == native.OK
+    t = (ctypes.c_int * 3)()
+    assert lib.ssoct_plan_get_tuning(None, t) == native.EINVAL
+    assert lib.ssoct_plan_set_tuning(None, t) == native.EINVAL
+    assert lib.ssoct_plan_tune(None, None, lam, 1e-5, 0.1, None, None, None, 0, None, t) == native.EINVAL
