@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Gvoxel/s per volume, FP32 vs split-prec MFMA depth-DFT at rel-L2≤1e-4; %HBM"
 HBM_PEAK = 8.0e12                       # B/s, MI355X HBM3E
 MFMA_PEAK = {"fp32": 157.3e12, "fp16": 2.5e15, "bf16": 2.5e15}
-FRESNEL_BYTES_PER_VOXEL = 10            # u16 frame in + H out
+FRESNEL_BYTES_PER_VOXEL = 10            # u16 frame in + H out (stage A as a whole)
+ROW_BYTES_PER_VOXEL = 10                # row pass: u16 frame in + complex64 intermediate out
+COL_BYTES_PER_VOXEL = 16                # column pass: intermediate in + H out (8 B in every format)
 DEPTH_BYTES_PER_VOXEL = 16              # H in + complex64 volume out
 PATH_BYTES_PER_VOXEL = 26
 SPLIT_BAR = 1e-4
@@ -54,7 +56,8 @@ def depth_flops(T: int, N: int, form: str) -> float:
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_08960_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    # device code only: the .hip kernels and the headers they include
+    for name in sorted(n for n in os.listdir(csrc) if n.endswith(".hip") or n in ("fft_engine.hpp", "internal.hpp")):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -111,6 +114,195 @@ def cpu_baseline(sw, n_frames=32, n_cols=65536):
     }
 
 
+def roofline(rec, form, T, N):
+    """Per-kernel achieved rates from the live HIP-event times of one step, and
+    the roofline object of the kernel that takes the most time per step."""
+    voxels = T * N * N
+    st = rec["stage_ms"]
+    sp = rec["fresnel_split_ms"]
+    nch = -(-T // rec["tuning"]["frames_per_chunk"])
+    prec = form.split("_")[0]
+    ks = {
+        # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
+        "k_depth": (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
+        "k_row_pass": (sp["row_pass"], nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
+        "k_col_pass": (sp["col_pass"], nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
+    }
+    kernels = {}
+    for name, (ms, n, byts, flops) in ks.items():
+        if ms is None or ms <= 0:
+            continue
+        t = ms * 1e-3 / n                              # average launch duration
+        k = {"ms_per_step": ms, "launches": n, "avg_launch_us": t * 1e6,
+             "bytes_per_launch": byts / n, "achieved_gb_s": byts / n / t / 1e9,
+             "hbm_frac": byts / n / t / HBM_PEAK}
+        if flops:
+            k["flops_per_launch"] = flops / n
+            k["achieved_tflop_s"] = flops / n / t / 1e12
+            k["mfma_frac"] = flops / n / t / MFMA_PEAK[prec]
+        kernels[name] = k
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    k = kernels[dom]
+    if dom == "k_depth" and k["flops_per_launch"] / MFMA_PEAK[prec] >= k["bytes_per_launch"] / HBM_PEAK:
+        roof = {"bound": "mfma", "achieved": k["achieved_tflop_s"], "peak": MFMA_PEAK[prec] / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": k["achieved_gb_s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic_record(f"{dom}_{form}" if dom != "k_row_pass" else dom)
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = k["avg_launch_us"]
+    roof["launches_per_step"] = k["launches"]
+    return roof, kernels
+
+
+def pctl(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
+
+
+def bench_stream(sw, form, n_vol=16, slots=3, fps=512.0, chunk=16, paced=True):
+    """Consecutive volumes through the streaming engine (one graph replay per
+    volume, or per frame chunk when host-fed): sustained Gvoxel/s with the
+    frames already in device slots, host-fed from pinned memory, and host-fed
+    at a camera rate of `fps` with per-volume latency after the last frame."""
+    import torch
+
+    from paper_2003_08960_amd import native
+    from paper_2003_08960_amd.api import Plan, Stream
+    T, N, _ = sw.frames.shape
+    voxels = T * N * N
+    plan = Plan(T, N, precision=form)
+    frames_dev = torch.from_numpy(sw.frames).cuda()
+    ws_vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
+    tuning = plan.tune(frames_dev, sw.lam, sw.pitch, sw.z, out=ws_vol)
+    del ws_vol
+    torch.cuda.empty_cache()
+    out = {"form": form, "volumes": n_vol, "slots": slots, "tuning": tuning}
+
+    st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=slots)
+    # device-resident: every slot holds the sweep; each volume is one graph launch
+    for _ in range(slots):
+        slot, buf = st.acquire()
+        buf.copy_(frames_dev)
+        torch.cuda.synchronize()
+        st.submit(slot, 0)
+    while st.pop(wait=True, cuts=False) is not None:
+        pass
+    lat = []
+    t0 = time.perf_counter()
+    done = 0
+    for v in range(n_vol):
+        got = st.acquire()
+        while got is None:
+            lat.append(st.pop(wait=True, cuts=False)["latency_ms"])
+            done += 1
+            got = st.acquire()
+        st.submit(got[0], v)
+    while done < n_vol:
+        lat.append(st.pop(wait=True, cuts=False)["latency_ms"])
+        done += 1
+    el = time.perf_counter() - t0
+    out["device_resident"] = {"gvoxel_s": n_vol * voxels / el / 1e9, "ms_per_volume": el * 1e3 / n_vol,
+                              "latency_ms_p50": pctl(lat, 50), "latency_ms_p99": pctl(lat, 99)}
+    log(f"stream {form} device-resident: {out['device_resident']['gvoxel_s']:.1f} Gvoxel/s")
+
+    # host-fed, unpaced: the same sweep pushed from pinned memory n_vol times
+    pinned = torch.from_numpy(sw.frames).pin_memory()
+    lat = []
+    seq = 0
+    t0 = time.perf_counter()
+    for v in range(n_vol):
+        while st.stats()["in_flight"] >= slots:
+            lat.append(st.pop(wait=True, cuts=False)["latency_ms"])
+        rc = st.push_frames(pinned, seq)
+        assert rc == native.OK, rc
+        seq += T
+    while True:
+        r = st.pop(wait=True, cuts=False)
+        if r is None:
+            break
+        lat.append(r["latency_ms"])
+    el = time.perf_counter() - t0
+    out["host_fed"] = {"gvoxel_s": n_vol * voxels / el / 1e9, "ms_per_volume": el * 1e3 / n_vol,
+                       "h2d_gb_s": n_vol * T * N * N * 2 / el / 1e9,
+                       "latency_ms_p50": pctl(lat, 50), "latency_ms_p99": pctl(lat, 99)}
+    log(f"stream {form} host-fed: {out['host_fed']['gvoxel_s']:.1f} Gvoxel/s")
+
+    if paced:
+        # host-fed at the camera rate: chunks of `chunk` frames released on the frame clock
+        lat = []
+        t_start = time.perf_counter()
+        n_chunks = n_vol * T // chunk
+        for j in range(n_chunks):
+            t_due = t_start + j * chunk / fps
+            while True:
+                r = st.pop(wait=False, cuts=True)
+                if r is None:
+                    break
+                lat.append(r["latency_ms"])
+            dt = t_due - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            pos = (j * chunk) % T
+            rc = st.push_frames(pinned[pos:pos + chunk], seq)
+            assert rc == native.OK, rc
+            seq += chunk
+        while True:
+            r = st.pop(wait=True, cuts=True)
+            if r is None:
+                break
+            lat.append(r["latency_ms"])
+        el = time.perf_counter() - t_start
+        s = st.stats()
+        out["paced"] = {"fps": fps, "chunk_frames": chunk, "gvoxel_s": n_vol * voxels / el / 1e9,
+                        "latency_ms_p50": pctl(lat, 50), "latency_ms_p99": pctl(lat, 99),
+                        "latency_ms_max": max(lat) if lat else None, "dropped_frames": s["dropped_frames"]}
+        log(f"stream {form} paced {fps:.0f} fps: latency p50 {out['paced']['latency_ms_p50']:.2f} ms, "
+            f"p99 {out['paced']['latency_ms_p99']:.2f} ms")
+    st.close()
+    del plan, frames_dev, pinned
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_backward(steps=10, warmup=3):
+    """Loss sum |V|^4 and its gradient (z, 15 Zernike coefficients, T dispersion
+    phases) on the aberrated T=128, N=512 workload: fused recompute-forward +
+    adjoint, against the FP32 forward render alone."""
+    import torch
+
+    from paper_2003_08960_amd import synth
+    from paper_2003_08960_amd.api import Plan
+    sw = synth.make_config("diff")
+    T, N, _ = sw.frames.shape
+    fr = torch.from_numpy(sw.frames).cuda()
+    disp = np.zeros(T)
+    zern = np.zeros(15)
+    plan = Plan(T, N, backward=True)
+    vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_fwd = timed(lambda: plan.render(fr, sw.lam, sw.pitch, sw.z, disp, zern, out=vol))
+    ms_bwd = timed(lambda: plan.backward_sharpness(fr, sw.lam, sw.pitch, sw.z, disp, zern))
+    del plan, vol, fr
+    torch.cuda.empty_cache()
+    rec = {"workload": f"aberrated sweep T={T}, N={N}: loss sum |V|^4, gradient w.r.t. z, 15 Zernike "
+                       f"coefficients and {T} dispersion phases (FP32, forward recomputed)",
+           "ms_forward_render": ms_fwd, "ms_loss_and_gradient": ms_bwd, "ratio": ms_bwd / ms_fwd,
+           "gvoxel_s_loss_and_gradient": T * N * N / (ms_bwd * 1e-3) / 1e9}
+    log(f"backward: forward {ms_fwd:.3f} ms, loss+gradient {ms_bwd:.3f} ms ({ms_bwd / ms_fwd:.2f}x)")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +311,12 @@ def main():
     ap.add_argument("--forms", default="fp32,fp16_split,bf16_split,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming form")
+    ap.add_argument("--no-paced", action="store_true", help="skip the 512 frames/s paced stream (about 8 s)")
+    ap.add_argument("--no-backward", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the launch-shape tuner before timing each form (default: the plan's defaults; "
+                         "the streaming form is always tuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one untimed 1 GiB device-to-device copy first: the reference kernel that "
                          "scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings to bytes")
@@ -161,6 +359,7 @@ def main():
     for form in [f for f in args.forms.split(",") if f]:
         plan = Plan(T, N, precision=form, profile=True)
         vol = torch.empty((T, N, N), dtype=torch.complex64, device=dev)
+        tuning = plan.tune(frames, sw.lam, sw.pitch, sw.z, out=vol) if args.tune else plan.get_tuning()
         for _ in range(args.warmup):
             plan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
             plan.cuts(vol, x0, y0, q0)
@@ -175,16 +374,33 @@ def main():
         t1 = time.perf_counter()
         stage = plan.profile_read()
         ms = (t1 - t0) * 1e3 / args.steps
+        del plan
+        torch.cuda.empty_cache()
+        # untimed pass with an event after every Fresnel-stage launch: per-pass split of that stage
+        kplan = Plan(T, N, precision=form, profile="kernels")
+        kplan.set_tuning(tuning)
+        for _ in range(3):
+            kplan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
+        kplan.profile_read()
+        for _ in range(5):
+            kplan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
+        kst = kplan.profile_read()
+        del kplan
+        torch.cuda.empty_cache()
         rec = {"ms_per_step": ms, "gvoxel_s": voxels / (ms * 1e-3) / 1e9,
                "stage_ms": {"tables": stage[0], "fresnel": stage[1], "depth": stage[2]},
-               "hbm_frac_path": PATH_BYTES_PER_VOXEL * voxels / (ms * 1e-3) / HBM_PEAK}
+               "fresnel_split_ms": {"row_pass": kst[4], "col_pass": kst[5], "fresnel": kst[1],
+                                    "note": "separate untimed pass with an event after every launch"},
+               "hbm_frac_path": PATH_BYTES_PER_VOXEL * voxels / (ms * 1e-3) / HBM_PEAK,
+               "tuning": {"frames_per_chunk": tuning[0], "col_workgroups": tuning[1],
+                          "depth_workgroups": tuning[2]}}
         if ref_cols is not None:
             got = np.stack([vol[:, u, v].cpu().numpy() for u, v in pix], axis=1)
             rec["rel_l2_sampled"] = float(np.linalg.norm(got - ref_cols) / np.linalg.norm(ref_cols))
         forms[form] = rec
         log(f"{form}: {ms:.3f} ms/step, {rec['gvoxel_s']:.1f} Gvoxel/s, stages {stage[1]:.3f} / {stage[2]:.3f} ms"
             + (f", rel-L2 {rec['rel_l2_sampled']:.2e}" if "rel_l2_sampled" in rec else ""))
-        del plan, vol
+        del vol
         torch.cuda.empty_cache()
 
     def ok(f):
@@ -196,26 +412,7 @@ def main():
     hr = forms[head]
     prec = head.split("_")[0]
 
-    # roofline of the dominant kernel of the headline form, from the live HIP-event stage times
-    st = hr["stage_ms"]
-    if st["depth"] >= st["fresnel"]:
-        flops = depth_flops(T, N, head)
-        byts = DEPTH_BYTES_PER_VOXEL * voxels
-        t = st["depth"] * 1e-3
-        if flops / MFMA_PEAK[prec] >= byts / HBM_PEAK:
-            roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": MFMA_PEAK[prec] / 1e12, "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-        roof["kernel"] = "k_depth (depth DFT, 1 launch per step)"
-        roof["traffic"] = traffic_record(f"k_depth_{head}")
-    else:
-        byts = FRESNEL_BYTES_PER_VOXEL * voxels
-        t = st["fresnel"] * 1e-3
-        roof = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "kernel": "k_row_pass + k_col_pass (Fresnel stage, all frame chunks)",
-                "traffic": traffic_record(f"fresnel_{head}")}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-
+    roof, kernels = roofline(hr, head, T, N)
     out = {
         "metric": METRIC,
         "value": hr["gvoxel_s"],
@@ -234,10 +431,17 @@ def main():
                                "one rectangular depth gate of all frames, complex64 volume + 3 cuts",
                    "T": T, "N": N, "form": head, "pitch_m": sw.pitch, "z_m": sw.z},
         "roofline": roof,
+        "kernels": kernels,
+        "stage_a_hbm_frac": FRESNEL_BYTES_PER_VOXEL * voxels / (hr["stage_ms"]["fresnel"] * 1e-3) / HBM_PEAK,
         "hbm_frac_whole_path": hr["hbm_frac_path"],
         "forms": forms,
         "paper_context_gvoxel_s": PAPER_GVOXEL_S,
     }
+    if not args.no_stream:
+        stream_form = "bf16_split" if "bf16_split" in forms else head
+        out["streaming"] = bench_stream(sw, stream_form, paced=not args.no_paced)
+    if not args.no_backward:
+        out["backward"] = bench_backward()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample (CPU)")
         out["cpu_baseline"] = cpu_baseline(sw)

@@ -73,6 +73,8 @@ extern "C" {
 #define SSOCT_CUT_POWER 64u       /* ssoct_cuts returns |V|^2 instead of |V| */
 #define SSOCT_BACKWARD 128u       /* workspace also sized for the gradient entry points */
 #define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
+#define SSOCT_PROFILE_KERNELS 512u /* with SSOCT_PROFILE: an event after every Fresnel-stage launch too
+                                      (each adds a few microseconds to the render) */
 
 typedef struct ssoct_plan ssoct_plan;
 
@@ -143,11 +145,15 @@ int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const dou
                              size_t workspace_bytes, double* grad_out);
 
 /* With SSOCT_PROFILE every ssoct_render records HIP events on the plan's
- * stream around its stages.  This call waits for the last recorded render
- * and returns the mean elapsed milliseconds over the renders recorded since
- * the previous call (at most the last 256): ms[0] tables, ms[1] Fresnel
- * stage (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth
- * transform, ms[3] the number of renders averaged.  Resets the record. */
+ * stream around its stages (and, with SSOCT_PROFILE_KERNELS, after every
+ * kernel launch of the Fresnel stage).  This call waits for the last recorded render and fills ms[6] with
+ * the mean elapsed milliseconds per render over the renders recorded since
+ * the previous call (at most the last 64): ms[0] tables, ms[1] Fresnel stage
+ * (rescale + chirp + 2-D DFT, all frame chunks), ms[2] depth transform (one
+ * launch), ms[3] the number of renders averaged, ms[4] all row-pass launches,
+ * ms[5] all column-pass launches (ms[4] and ms[5] are -1 without
+ * SSOCT_PROFILE_KERNELS or when a render had more than 64 frame chunks).
+ * Resets the record. */
 int ssoct_profile_read(ssoct_plan* plan, float* ms);
 
 /* ---------------------------------------------------------------- tuning
@@ -172,10 +178,16 @@ int ssoct_plan_set_tuning(ssoct_plan* plan, const int* tuning);
  * Continuous rendering of consecutive sweeps (one volume per T frames) with
  * a ring of `slots` volume slots.  Each slot owns device memory for one
  * sweep of frames, a workspace, the complex volume and the three cuts, a HIP
- * stream, and a HIP graph captured once at creation (render + cuts + copy of
- * the cuts to pinned host memory), so successive volumes overlap (the depth
- * transform of one with the Fresnel stage of the next) and each volume is
- * one graph launch.  Physical parameters (lambda, pitch, z, disp_phase,
+ * stream, and HIP graphs captured once at creation with the plan's launch
+ * shapes at that time: the whole volume (render + cuts + copy of the cuts to
+ * pinned host memory), the Fresnel stage of each chunk of frames, and the
+ * depth transform + cuts + copy.  Successive volumes overlap (the depth
+ * transform of one with the Fresnel stage of the next).  Host-fed frames
+ * start each chunk's Fresnel stage as soon as the chunk has landed, so a
+ * volume's latency after its last frame is about one chunk plus the depth
+ * transform; a device-filled slot is one graph launch.  The model is the
+ * buffered camera acquisition of the real-time system described after Eq. 7,
+ * which keeps every sweep whole for the depth transform.  Physical parameters (lambda, pitch, z, disp_phase,
  * zernike) and cut positions are fixed for the stream; the plan must not be
  * used concurrently by other calls while the stream exists.  A stream object
  * is safe to use from two threads (a producer pushing, a consumer popping). */

@@ -44,6 +44,7 @@ class Plan:
         flags |= native.CUT_POWER if cut_power else 0
         flags |= native.BACKWARD if backward else 0
         flags |= native.PROFILE if profile else 0
+        flags |= native.PROFILE_KERNELS if profile == "kernels" else 0
         self.flags = flags
         self.precision = precision
         self.write_abs = write_abs
@@ -137,8 +138,9 @@ class Plan:
         return out
 
     def profile_read(self):
-        """Mean stage times (ms) since the last read: (tables, fresnel stage, depth transform, count)."""
-        ms = (ctypes.c_float * 4)()
+        """Mean times (ms) per render since the last read: (tables, Fresnel stage, depth transform,
+        renders averaged, all row-pass launches, all column-pass launches)."""
+        ms = (ctypes.c_float * 6)()
         native.check(self.lib.ssoct_profile_read(self._h, ms))
         return tuple(ms)
 
@@ -156,9 +158,11 @@ class Plan:
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         return f"{arch}|T{self.T}|N{self.N}|flags{self.flags & ~native.PROFILE}"
 
-    def tune(self, frames, lam, pitch, z, disp_phase=None, zernike=None, cache_path: str | None = None):
+    def tune(self, frames, lam, pitch, z, disp_phase=None, zernike=None, cache_path: str | None = None,
+             out: torch.Tensor | None = None):
         """Pick launch shapes by timing candidates (ssoct_plan_tune); with `cache_path`, reuse or store
-        the choice in a JSON cache keyed by GPU architecture, T, N and plan flags."""
+        the choice in a JSON cache keyed by GPU architecture, T, N and plan flags.  `out` is an
+        optional volume buffer to render into while timing."""
         key = self.tuning_key()
         if cache_path:
             cached = _load_cache(cache_path).get(key)
@@ -166,7 +170,7 @@ class Plan:
                 self.set_tuning(cached)
                 return list(cached)
         _check_frames(frames, self.T, self.N)
-        out = self.render(frames, lam, pitch, z, disp_phase, zernike)
+        out = self.render(frames, lam, pitch, z, disp_phase, zernike, out=out)
         t = (ctypes.c_int * 3)()
         self._sync_stream()
         native.check(self.lib.ssoct_plan_tune(

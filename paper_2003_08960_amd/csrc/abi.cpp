@@ -120,6 +120,8 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->a_bf16);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->kev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -235,34 +237,50 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
 
 // Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
 // row DFT) into the chunk buffer, then column DFT into H.
-static int forward_stage_a(ssoct_plan* p, hipStream_t s, const uint16_t* frames, void* H, float2* inter, int fmt,
-                           int sigma) {
-  const int T = p->T, N = p->N, F = p->F_run;
-  const float2* ab = p->have_aberr ? p->aberr : nullptr;
-  for (int t0 = 0; t0 < T; t0 += F) {
-    const int Fc = T - t0 < F ? T - t0 : F;
-    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
-    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, fmt, sigma, p->col_grid, s));
-  }
-  return SSOCT_OK;
-}
-
 static int depth_grid_for(const ssoct_plan* p) {
   return p->depth_grid > 0 ? p->depth_grid : depth_grid(p->T, p->N * p->N, p->cu);
 }
 
-int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
-                hipEvent_t* ev) {
-  const int T = p->T, N = p->N;
+int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, int t0, int Fc) {
+  const int N = p->N;
+  const int fmt = h_format(depth_prec(p->flags));
+  float2* inter = reinterpret_cast<float2*>(ws + L.inter);
+  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
+  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, p->col_grid, s));
+  return SSOCT_OK;
+}
+
+int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void* vol) {
   const int prec = depth_prec(p->flags);
-  const int fmt = h_format(prec);
-  void* H = ws + L.H;
-  if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
-  if (int rc = forward_stage_a(p, s, frames, H, reinterpret_cast<float2*>(ws + L.inter), fmt, p->sigma)) return rc;
-  if (ev) SSOCT_HIP(hipEventRecord(ev[2], s));
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
-  SSOCT_HIP(launch_depth(T, N * N, prec, +1, epi, H, amat_for(p, prec), vol, p->sigma, 0, nullptr, depth_grid_for(p),
-                         s));
+  SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
+                         depth_grid_for(p), s));
+  return SSOCT_OK;
+}
+
+int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
+                hipEvent_t* ev, hipEvent_t* kev) {
+  const int T = p->T, N = p->N, F = p->F_run;
+  if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
+  if (kev) {  // the two passes launched one by one with an event after each
+    const int fmt = h_format(depth_prec(p->flags));
+    float2* inter = reinterpret_cast<float2*>(ws + L.inter);
+    const float2* ab = p->have_aberr ? p->aberr : nullptr;
+    for (int t0 = 0, c = 0; t0 < T; t0 += F, ++c) {
+      const int Fc = T - t0 < F ? T - t0 : F;
+      SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
+      SSOCT_HIP(hipEventRecord(kev[2 * c], s));
+      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, p->col_grid, s));
+      SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
+    }
+  } else {
+    for (int t0 = 0; t0 < T; t0 += F) {
+      if (int rc = render_chunk(p, s, frames, ws, L, t0, T - t0 < F ? T - t0 : F)) return rc;
+    }
+  }
+  if (ev) SSOCT_HIP(hipEventRecord(ev[2], s));
+  if (int rc = render_depth(p, s, ws, L, vol)) return rc;
   if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
   return SSOCT_OK;
 }
@@ -350,6 +368,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess) e = hipMalloc(&p->a_bf16, na16 * sizeof(uint4));
   if (e == hipSuccess && (flags & SSOCT_PROFILE)) {
     p->ev.assign((size_t)ssoct_plan::MAXREC * 4, nullptr);
+    p->rec_nch.assign(ssoct_plan::MAXREC, 0);
     for (auto& ev : p->ev)
       if (e == hipSuccess) e = hipEventCreate(&ev);
   }
@@ -385,11 +404,24 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
   if (int rc = check_render_args(p, frames, workspace, workspace_bytes, vol, &L)) return rc;
   SSOCT_HIP(hipSetDevice(p->device));
   const bool prof = (p->flags & SSOCT_PROFILE) != 0;
-  hipEvent_t* ev = prof ? &p->ev[(size_t)(p->rec % ssoct_plan::MAXREC) * 4] : nullptr;
-  if (prof) SSOCT_HIP(hipEventRecord(ev[0], p->stream));
+  const int slot = p->rec % ssoct_plan::MAXREC;
+  hipEvent_t* ev = prof ? &p->ev[(size_t)slot * 4] : nullptr;
+  hipEvent_t* kev = nullptr;
+  if (prof) {
+    const int nch = (p->T + p->F_run - 1) / p->F_run;
+    if ((p->flags & SSOCT_PROFILE_KERNELS) && nch <= ssoct_plan::KMAX) {
+      if (p->kev.empty()) {
+        p->kev.assign((size_t)ssoct_plan::MAXREC * 2 * ssoct_plan::KMAX, nullptr);
+        for (auto& e : p->kev) SSOCT_HIP(hipEventCreate(&e));
+      }
+      kev = &p->kev[(size_t)slot * 2 * ssoct_plan::KMAX];
+    }
+    p->rec_nch[slot] = kev ? nch : 0;
+    SSOCT_HIP(hipEventRecord(ev[0], p->stream));
+  }
   const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
   if (status < 0) return status;
-  if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev)) return rc;
+  if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev, kev)) return rc;
   if (prof) ++p->rec;
   return status;
 }
@@ -449,8 +481,14 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   void* H = ws + L.H;
   float2* gam = reinterpret_cast<float2*>(ws + L.B2);
   double* loss = reinterpret_cast<double*>(ws + L.loss);
-  if (int rc = forward_stage_a(p, p->stream, frames, H, reinterpret_cast<float2*>(ws + L.inter), HF_F32, 0))
-    return rc;
+  // Fresnel stage in FP32 whatever the plan's depth precision: the loss and its adjoint run in FP32
+  float2* inter = reinterpret_cast<float2*>(ws + L.inter);
+  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  for (int t0 = 0; t0 < T; t0 += p->F_run) {
+    const int Fc = T - t0 < p->F_run ? T - t0 : p->F_run;
+    SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));
+    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, HF_F32, 0, p->col_grid, p->stream));
+  }
   // |V| <= T N^2 65535: scale by 2^-e so that 4 |V^|^3 stays finite in FP32
   const double bound = (double)T * N * N * 65535.0;
   int e = (int)std::ceil(std::log2(bound)) - 40;
@@ -469,7 +507,8 @@ int ssoct_profile_read(ssoct_plan* p, float* ms) {
   const int n = p->rec < ssoct_plan::MAXREC ? p->rec : ssoct_plan::MAXREC;
   const int last = (p->rec - 1) % ssoct_plan::MAXREC;
   SSOCT_HIP(hipEventSynchronize(p->ev[(size_t)last * 4 + 3]));
-  double sum[3] = {0, 0, 0};
+  double sum[5] = {0, 0, 0, 0, 0};
+  int nk = 0;
   for (int r = 0; r < n; ++r) {
     const int slot = (p->rec - 1 - r) % ssoct_plan::MAXREC;
     hipEvent_t* e = &p->ev[(size_t)slot * 4];
@@ -478,9 +517,23 @@ int ssoct_profile_read(ssoct_plan* p, float* ms) {
       SSOCT_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
       sum[i] += t;
     }
+    const int nch = p->rec_nch[slot];
+    if (nch > 0) {
+      hipEvent_t* k = &p->kev[(size_t)slot * 2 * ssoct_plan::KMAX];
+      for (int c = 0; c < nch; ++c) {
+        float tr = 0.f, tc = 0.f;
+        SSOCT_HIP(hipEventElapsedTime(&tr, c == 0 ? e[1] : k[2 * c - 1], k[2 * c]));
+        SSOCT_HIP(hipEventElapsedTime(&tc, k[2 * c], k[2 * c + 1]));
+        sum[3] += tr;
+        sum[4] += tc;
+      }
+      ++nk;
+    }
   }
   for (int i = 0; i < 3; ++i) ms[i] = (float)(sum[i] / n);
   ms[3] = (float)n;
+  ms[4] = nk == n ? (float)(sum[3] / n) : -1.0f;
+  ms[5] = nk == n ? (float)(sum[4] / n) : -1.0f;
   p->rec = 0;
   return SSOCT_OK;
 }

@@ -52,9 +52,14 @@ struct ssoct_plan {
   std::vector<double> cache;   // parameter set the tables were last built from
   bool have_aberr = false;
   int sigma = 0;               // FP16 operand scale exponent for the current tables
-  // profiling record
-  static constexpr int MAXREC = 256;
-  std::vector<hipEvent_t> ev;  // [MAXREC][4] with SSOCT_PROFILE
+  // profiling record (SSOCT_PROFILE): per render, events at start, after the
+  // tables, after the Fresnel stage and after the depth transform, plus one
+  // after every row-pass and column-pass launch (kev, up to KMAX chunks)
+  static constexpr int MAXREC = 64;
+  static constexpr int KMAX = 64;
+  std::vector<hipEvent_t> ev;   // [MAXREC][4]
+  std::vector<hipEvent_t> kev;  // [MAXREC][2 KMAX], created on first use
+  std::vector<int> rec_nch;     // chunks of each record (0: no per-kernel events)
   int rec = 0;
   bool streaming = false;      // a stream object uses the plan's tables
 };
@@ -67,8 +72,15 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
 int depth_prec(uint32_t flags);
 // Enqueue one forward render on `stream` (tables must be current): Fresnel
 // stage into the workspace, depth transform into vol.  `ev` (4 events or
-// null) brackets the stages for the profiling record.
+// null) brackets the stages for the profiling record; `kev` (2 events per
+// chunk, or null) is recorded after each row-pass and column-pass launch.
 int render_core(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
-                hipEvent_t* ev);
+                hipEvent_t* ev, hipEvent_t* kev = nullptr);
+// The two halves of render_core: the Fresnel stage of frames [t0, t0 + Fc)
+// (Fc <= the plan's frames per chunk), and the depth transform of the whole
+// H stack into vol.
+int render_chunk(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, int t0,
+                 int Fc);
+int render_depth(ssoct_plan* p, hipStream_t stream, char* ws, const WsLayout& L, void* vol);
 
 }  // namespace ssoct

@@ -1,13 +1,16 @@
 // Streaming renderer of consecutive sweeps (ssoct_stream_*).
 //
-// The paper buffers the acquisition "to avoid any image drop" so that the
-// temporal demodulation (Eq. 7) only ever sees consecutive frames of one
-// sweep.  Here a ring of volume slots plays that role on the GPU: frames are
+// The real-time system described after Eq. 7 buffers the camera stream so
+// that no frame is lost and the depth transform (Eq. 7) only ever sees the
+// consecutive frames of one sweep.  Here a ring of volume slots plays that role on the GPU: frames are
 // copied into a slot in sweep order (sequence numbers are checked; a gap or a
 // full ring discards the incomplete sweep instead of mixing sweeps), and a
-// complete slot is rendered by one launch of a HIP graph captured at stream
-// creation (render + cuts + copy of the cuts to pinned host memory) on the
-// slot's own stream, so consecutive volumes overlap on the GPU.
+// slot is rendered by HIP graphs captured at stream creation, on the slot's
+// own stream, so consecutive volumes overlap on the GPU.  Host-fed frames
+// start the Fresnel stage of each chunk of frames as soon as that chunk has
+// landed (one small graph per chunk), and the last frame of a sweep launches
+// the depth transform + cuts + copy of the cuts to pinned host memory; a
+// device-filled slot replays one graph of the whole volume.
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -15,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -37,11 +41,15 @@ struct Slot {
   float* cuts = nullptr;       // device cuts xy | xz | yz
   float* hcuts = nullptr;      // pinned host copy of the cuts
   hipStream_t s = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec = nullptr;          // whole volume: Fresnel + depth + cuts + D2H
+  std::vector<hipGraphExec_t> chunk;      // Fresnel stage of one chunk of frames
+  hipGraphExec_t tail = nullptr;          // depth + cuts + D2H
   hipEvent_t landed = nullptr;  // host-fed frames have arrived
+  hipEvent_t idle = nullptr;    // earlier work of the slot is over (before its frames are overwritten)
   hipEvent_t done = nullptr;    // volume finished
   int state = FREE;
   int filled = 0;
+  int chunks_run = 0;
   uint64_t vseq = 0;
   int64_t t_submit = 0;
   std::atomic<int64_t> t_done{0};
@@ -55,6 +63,7 @@ struct ssoct_stream {
   ssoct_plan* plan = nullptr;
   int nslot = 0;
   int x0 = 0, y0 = 0, q0 = 0;
+  int F = 0;                   // frames per Fresnel chunk the graphs were captured with
   hipStream_t copy = nullptr;
   std::unique_ptr<Slot[]> slots;
   std::mutex m;
@@ -74,7 +83,11 @@ void stream_free(ssoct_stream* st) {
       Slot& s = st->slots[k];
       if (s.s) (void)hipStreamSynchronize(s.s);
       if (s.exec) (void)hipGraphExecDestroy(s.exec);
+      for (hipGraphExec_t g : s.chunk)
+        if (g) (void)hipGraphExecDestroy(g);
+      if (s.tail) (void)hipGraphExecDestroy(s.tail);
       if (s.landed) (void)hipEventDestroy(s.landed);
+      if (s.idle) (void)hipEventDestroy(s.idle);
       if (s.done) (void)hipEventDestroy(s.done);
       if (s.s) (void)hipStreamDestroy(s.s);
       (void)hipFree(s.frames);
@@ -92,20 +105,47 @@ void stream_free(ssoct_stream* st) {
   delete st;
 }
 
-// enqueue the slot's graph (after its frames have landed) and stamp its completion
-int submit(ssoct_stream* st, int k, bool host_fed) {
+// after the slot's Fresnel work (or with it, for a whole-volume graph): the
+// rest of the volume, its completion stamp and event
+int finish(ssoct_stream* st, int k, hipGraphExec_t g) {
   Slot& s = st->slots[k];
-  if (host_fed) {
-    SSOCT_HIP(hipEventRecord(s.landed, st->copy));
-    SSOCT_HIP(hipStreamWaitEvent(s.s, s.landed, 0));
-  }
   s.t_done.store(0);
   s.t_submit = now_ns();
-  SSOCT_HIP(hipGraphLaunch(s.exec, s.s));
+  SSOCT_HIP(hipGraphLaunch(g, s.s));
   SSOCT_HIP(hipLaunchHostFunc(s.s, stamp_done, &s));
   SSOCT_HIP(hipEventRecord(s.done, s.s));
   s.state = INFLIGHT;
   st->inflight.push_back(k);
+  return SSOCT_OK;
+}
+
+// launch the Fresnel graphs of every chunk of slot k whose frames have all been
+// queued on the copy stream (the slot stream waits for those copies)
+int run_landed_chunks(ssoct_stream* st, int k) {
+  Slot& s = st->slots[k];
+  const int T = st->plan->T, F = st->F;
+  const int ready = s.filled == T ? (int)s.chunk.size() : s.filled / F;
+  if (ready <= s.chunks_run) return SSOCT_OK;
+  SSOCT_HIP(hipEventRecord(s.landed, st->copy));
+  SSOCT_HIP(hipStreamWaitEvent(s.s, s.landed, 0));
+  for (; s.chunks_run < ready; ++s.chunks_run) SSOCT_HIP(hipGraphLaunch(s.chunk[s.chunks_run], s.s));
+  return SSOCT_OK;
+}
+
+// capture what `enqueue` puts on stream s into an executable graph
+template <class Fn>
+int capture(hipStream_t s, hipGraphExec_t* out, Fn enqueue) {
+  hipGraph_t g = nullptr;
+  SSOCT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue();
+  const hipError_t ee = hipStreamEndCapture(s, &g);
+  if (rc != SSOCT_OK || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != SSOCT_OK ? rc : hip_fail(ee, "hipStreamEndCapture");
+  }
+  const hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
   return SSOCT_OK;
 }
 
@@ -147,8 +187,13 @@ int ssoct_stream_create(ssoct_stream** out, ssoct_plan* p, const double* lambda,
   const int T = p->T, N = p->N;
   const WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
   const size_t ncut = (size_t)N * N + 2 * (size_t)T * N;
+  const int F = p->F_run;
+  const int nch = (T + F - 1) / F;
+  st->F = F;
+  const bool power = (p->flags & SSOCT_CUT_POWER) != 0;
   hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
-  for (int k = 0; k < slots && e == hipSuccess; ++k) {
+  int rc = SSOCT_OK;
+  for (int k = 0; k < slots && e == hipSuccess && rc == SSOCT_OK; ++k) {
     Slot& s = st->slots[k];
     e = hipMalloc(&s.frames, (size_t)T * N * N * sizeof(uint16_t));
     if (e == hipSuccess) e = hipMalloc(&s.ws, L.total);
@@ -157,38 +202,38 @@ int ssoct_stream_create(ssoct_stream** out, ssoct_plan* p, const double* lambda,
     if (e == hipSuccess) e = hipHostMalloc(&s.hcuts, ncut * sizeof(float), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.landed, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.idle, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(s.frames, 0, (size_t)T * N * N * sizeof(uint16_t), s.s);
     if (e != hipSuccess) break;
-    // capture: render + cuts + cuts to pinned host memory
-    hipGraph_t g = nullptr;
-    e = hipStreamBeginCapture(s.s, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) break;
-    int rc = render_core(p, s.s, s.frames, s.ws, L, s.vol, nullptr);
-    if (rc == SSOCT_OK) {
-      const hipError_t le = launch_cuts(T, N, s.vol, x0, y0, q0, (p->flags & SSOCT_CUT_POWER) ? 1 : 0, s.cuts,
-                                        s.cuts + (size_t)N * N, s.cuts + (size_t)N * N + (size_t)T * N, s.s);
-      if (le != hipSuccess) rc = hip_fail(le, "launch_cuts");
+    auto tail = [&]() -> int {
+      if (int r = render_depth(p, s.s, s.ws, L, s.vol)) return r;
+      float* c = s.cuts;
+      SSOCT_HIP(launch_cuts(T, N, s.vol, x0, y0, q0, power ? 1 : 0, c, c + (size_t)N * N,
+                            c + (size_t)N * N + (size_t)T * N, s.s));
+      SSOCT_HIP(hipMemcpyAsync(s.hcuts, c, ncut * sizeof(float), hipMemcpyDeviceToHost, s.s));
+      return SSOCT_OK;
+    };
+    rc = capture(s.s, &s.exec, [&]() -> int {
+      for (int t0 = 0; t0 < T; t0 += F)
+        if (int r = render_chunk(p, s.s, s.frames, s.ws, L, t0, T - t0 < F ? T - t0 : F)) return r;
+      return tail();
+    });
+    if (rc == SSOCT_OK) rc = capture(s.s, &s.tail, tail);
+    s.chunk.assign(nch, nullptr);
+    for (int c = 0; c < nch && rc == SSOCT_OK; ++c) {
+      const int t0 = c * F;
+      rc = capture(s.s, &s.chunk[c],
+                   [&]() { return render_chunk(p, s.s, s.frames, s.ws, L, t0, T - t0 < F ? T - t0 : F); });
     }
-    if (rc == SSOCT_OK) {
-      const hipError_t ce = hipMemcpyAsync(s.hcuts, s.cuts, ncut * sizeof(float), hipMemcpyDeviceToHost, s.s);
-      if (ce != hipSuccess) rc = hip_fail(ce, "hipMemcpyAsync");
-    }
-    const hipError_t ee = hipStreamEndCapture(s.s, &g);
-    if (rc != SSOCT_OK || ee != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      stream_free(st);
-      return rc != SSOCT_OK ? rc : hip_fail(ee, "hipStreamEndCapture");
-    }
-    e = hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && rc == SSOCT_OK) {
     for (int k = 0; k < slots && e == hipSuccess; ++k) e = hipStreamSynchronize(st->slots[k].s);
   }
-  if (e != hipSuccess) {
-    const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device or pinned allocation failed")
-                                              : hip_fail(e, "ssoct_stream_create");
+  if (e != hipSuccess || rc != SSOCT_OK) {
+    if (rc == SSOCT_OK)
+      rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device or pinned allocation failed")
+                                      : hip_fail(e, "ssoct_stream_create");
     stream_free(st);
     return rc;
   }
@@ -234,12 +279,18 @@ int ssoct_stream_push_frames(ssoct_stream* st, const uint16_t* host, int nframes
         continue;
       }
       Slot& s = st->slots[k];
+      // the copies into this slot wait for whatever its stream still runs
+      // (Fresnel chunks of a discarded sweep read the frames buffer)
+      SSOCT_HIP(hipEventRecord(s.idle, s.s));
+      SSOCT_HIP(hipStreamWaitEvent(st->copy, s.idle, 0));
       s.state = FILLING;
       s.filled = 0;
+      s.chunks_run = 0;
       s.vseq = seq / (uint64_t)T;
       st->filling = k;
     }
-    Slot& s = st->slots[st->filling];
+    const int k = st->filling;
+    Slot& s = st->slots[k];
     const int run = (nframes - i) < (T - pos) ? (nframes - i) : (T - pos);
     SSOCT_HIP(hipMemcpyAsync(s.frames + (size_t)pos * fpx, host + (size_t)i * fpx, (size_t)run * fpx * 2,
                              hipMemcpyHostToDevice, st->copy));
@@ -247,10 +298,10 @@ int ssoct_stream_push_frames(ssoct_stream* st, const uint16_t* host, int nframes
     st->expect = seq + (uint64_t)run;
     st->have_expect = true;
     i += run;
+    if (int r = run_landed_chunks(st, k)) return r;
     if (pos + run == T) {
-      const int k = st->filling;
       st->filling = -1;
-      if (int r = submit(st, k, true)) return r;
+      if (int r = finish(st, k, s.tail)) return r;
     }
   }
   return rc;
@@ -274,7 +325,7 @@ int ssoct_stream_submit(ssoct_stream* st, int slot, uint64_t volume_seq) {
   if (slot < 0 || slot >= st->nslot || st->slots[slot].state != ACQUIRED)
     return fail(SSOCT_EINVAL, "slot was not acquired");
   st->slots[slot].vseq = volume_seq;
-  return submit(st, slot, false);
+  return finish(st, slot, st->slots[slot].exec);
 }
 
 int ssoct_stream_pop(ssoct_stream* st, int wait, uint64_t* volume_seq, int* slot, float* cut_xy, float* cut_xz,

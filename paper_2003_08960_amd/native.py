@@ -33,6 +33,7 @@ WRITE_ABS = 32
 CUT_POWER = 64
 BACKWARD = 128
 PROFILE = 256
+PROFILE_KERNELS = 512
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",

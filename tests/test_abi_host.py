@@ -78,7 +78,7 @@ def test_null_plan_is_rejected(lib):
     assert lib.ssoct_cuts(None, None, 0, 0, 0, None, None, None) == native.EINVAL
     assert lib.ssoct_backward(None, None, lam, 1e-5, 0.1, None, None, None, None, 0, None) == native.EINVAL
     assert lib.ssoct_backward_sharpness(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL
-    ms = (ctypes.c_float * 4)()
+    ms = (ctypes.c_float * 6)()
     assert lib.ssoct_profile_read(None, ms) == native.EINVAL
     assert lib.ssoct_plan_destroy(None) == native.OK
     assert b"NULL" in lib.ssoct_last_error() or b"null" in lib.ssoct_last_error()

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from oracle import ssoct_oracle as O
-from paper_2003_08960_amd import synth
+from paper_2003_08960_amd import native, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -196,3 +196,26 @@ def _mid_ref(mid):
     if "v" not in _MID_REF:
         _MID_REF["v"] = O.render(mid.frames, mid.lam, mid.pitch, mid.z)
     return _MID_REF["v"]
+
+
+def test_profile_record_splits_the_fresnel_stage(gpu_lib):
+    from paper_2003_08960_amd.api import Plan
+    print("\n[gpu] profile record", flush=True)
+    sw = synth.make_config("tiny")
+    T, N = sw.frames.shape[:2]
+    fr = torch.from_numpy(sw.frames).cuda()
+    for F in (T, 5):
+        plan = Plan(T, N, profile="kernels")
+        plan.set_tuning([F, 0, 0])
+        for _ in range(3):
+            plan.render(fr, sw.lam, sw.pitch, sw.z)
+        st = plan.profile_read()
+        assert st[3] == 3
+        assert st[4] > 0 and st[5] > 0 and st[2] > 0
+        assert st[4] + st[5] <= st[1] * 1.05 + 1e-3
+        with pytest.raises(native.SsoctError):
+            plan.profile_read()                      # the record was reset
+    plan = Plan(T, N, profile=True)                  # stage events only
+    plan.render(fr, sw.lam, sw.pitch, sw.z)
+    st = plan.profile_read()
+    assert st[1] > 0 and st[4] == -1 and st[5] == -1

@@ -166,3 +166,34 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
     assert plan2.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache) == choice   # from the cache
     with pytest.raises(native.SsoctError):
         plan.set_tuning([0, 0, 0])
+
+
+def test_chunkwise_fresnel_with_ragged_chunks_and_discarded_sweep(gpu_lib, sweeps):
+    """Frames per chunk 5 (T = 32: six full chunks and a ragged one): the chunk
+    graphs of a sweep that is then discarded must not disturb the next sweep
+    rendered in the same slot."""
+    from paper_2003_08960_amd.api import Plan, Stream
+    print("\n[gpu] stream chunk-wise, F=5", flush=True)
+    plan = Plan(T, N)
+    plan.set_tuning([5, 0, 0])
+    refs = [eager(plan, s) for s in sweeps[:3]]
+    sw = sweeps[0]
+    st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=1)
+    f = [np.ascontiguousarray(s.frames) for s in sweeps[:3]]
+    assert st.push_frames(f[0][:23], 0) == native.OK           # chunks 0-3 start, the sweep is cut short
+    assert st.push_frames(f[0][24:], 24) == native.EDROPPED
+    assert st.push_frames(f[1][:7], T) == native.OK
+    assert st.push_frames(f[1][7:19], T + 7) == native.OK
+    assert st.push_frames(f[1][19:], T + 19) == native.OK
+    r = st.pop(wait=True)
+    assert r["seq"] == 1
+    assert torch.equal(st.slot_volume(r["slot"]), refs[1][0])
+    assert np.array_equal(r["cut_xy"], refs[1][1][0])
+    for j in range(0, T, 3):                                    # sweep 2 three frames at a time
+        assert st.push_frames(f[2][j:j + 3], 2 * T + j) == native.OK
+    r = st.pop(wait=True)
+    assert r["seq"] == 2
+    assert torch.equal(st.slot_volume(r["slot"]), refs[2][0])
+    s = st.stats()
+    assert s["dropped_sweeps"] == 1 and s["done"] == 2
+    st.close()
