@@ -49,6 +49,9 @@ def depth_products(form: str) -> int:
 
 
 def depth_flops(T: int, N: int, form: str) -> float:
+    if form.endswith("_fft"):
+        # nominal radix-FFT count: 5 T log2 T real flops per pixel
+        return 5.0 * T * np.log2(T) * N * N
     # real form of the complex DFT matrix: 4 T^2 real flops per pixel per product
     return 4.0 * T * T * N * N * depth_products(form)
 
@@ -75,6 +78,15 @@ def traffic_record(kernel: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def traffic_key(kernel: str, form: str) -> str:
+    """Name of a kernel variant in profiles/traffic.json."""
+    if kernel == "k_row_pass":
+        return kernel
+    if kernel == "k_col_pass":
+        return f"k_col_pass_{form.split('_')[0]}"      # the column pass differs by H format only
+    return f"{kernel}_{form}"
 
 
 def sampled_pixels(sw, n_random=6, seed=5):
@@ -122,9 +134,10 @@ def roofline(rec, form, T, N):
     sp = rec["fresnel_split_ms"]
     nch = -(-T // rec["tuning"]["frames_per_chunk"])
     prec = form.split("_")[0]
+    dname = "k_depth_fft" if form.endswith("_fft") else "k_depth"
     ks = {
         # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
-        "k_depth": (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
+        dname: (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
         "k_row_pass": (sp["row_pass"], nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
         "k_col_pass": (sp["col_pass"], nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
     }
@@ -144,12 +157,13 @@ def roofline(rec, form, T, N):
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     k = kernels[dom]
     if dom == "k_depth" and k["flops_per_launch"] / MFMA_PEAK[prec] >= k["bytes_per_launch"] / HBM_PEAK:
+        # a dense depth product in FP32 is bound by the MFMA rate, not by its 16 B/voxel
         roof = {"bound": "mfma", "achieved": k["achieved_tflop_s"], "peak": MFMA_PEAK[prec] / 1e12,
                 "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": k["achieved_gb_s"], "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_record(f"{dom}_{form}" if dom != "k_row_pass" else dom)
+    roof["traffic"] = traffic_record(traffic_key(dom, form))
     roof["kernel"] = dom
     roof["avg_launch_us"] = k["avg_launch_us"]
     roof["launches_per_step"] = k["launches"]
@@ -308,7 +322,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp32,fp16_split,bf16_split,fp16,bf16")
+    ap.add_argument("--forms", default="fp32,fp32_fft,fp16_split,bf16_split,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming form")
@@ -424,8 +438,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32" if head == "fp32" else f"{prec}{'-split' if head.endswith('_split') else ''} depth DFT, f32 acc; "
-                  "f32 Fresnel stage"),
+        "dtype": ("f32" if head in ("fp32", "fp32_fft") else
+                  f"{prec}{'-split' if head.endswith('_split') else ''} depth DFT, f32 acc; f32 Fresnel stage"),
         "data": "synthetic",
         "config": {"workload": f"paper-shaped sweep: T={T} uint16 frames of {N}x{N}, 200 scatterers + speckle, "
                                "one rectangular depth gate of all frames, complex64 volume + 3 cuts",

@@ -75,6 +75,8 @@ extern "C" {
 #define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
 #define SSOCT_PROFILE_KERNELS 512u /* with SSOCT_PROFILE: an event after every Fresnel-stage launch too
                                       (each adds a few microseconds to the render) */
+#define SSOCT_DEPTH_FFT 1024u     /* FP32 depth transform as a radix FFT along the sweep (T in {16..256},
+                                      powers of two) instead of the dense DFT-matrix product */
 
 typedef struct ssoct_plan ssoct_plan;
 

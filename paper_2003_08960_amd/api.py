@@ -10,6 +10,7 @@ from . import native
 
 PRECISIONS = {
     "fp32": native.PREC_FP32,
+    "fp32_fft": native.PREC_FP32 | native.DEPTH_FFT,
     "fp16": native.PREC_FP16,
     "bf16": native.PREC_BF16,
     "fp16_split": native.PREC_FP16 | native.SPLIT,

@@ -118,6 +118,7 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->a_f32);
   (void)hipFree(p->a_f16);
   (void)hipFree(p->a_bf16);
+  (void)hipFree(p->dtw);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->kev)
@@ -254,6 +255,11 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
 int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void* vol) {
   const int prec = depth_prec(p->flags);
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
+  if (p->flags & SSOCT_DEPTH_FFT) {
+    SSOCT_HIP(launch_depth_fft(p->T, p->N * p->N, +1, epi, reinterpret_cast<const float2*>(ws + L.H), p->dtw, vol,
+                               s));
+    return SSOCT_OK;
+  }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
                          depth_grid_for(p), s));
   return SSOCT_OK;
@@ -341,6 +347,10 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if ((flags & SSOCT_PREC_MASK) == 3u) return fail(SSOCT_EINVAL, "unknown precision");
   if ((flags & SSOCT_SPLIT) && (flags & SSOCT_PREC_MASK) == SSOCT_PREC_FP32)
     return fail(SSOCT_EINVAL, "SSOCT_SPLIT needs SSOCT_PREC_FP16 or SSOCT_PREC_BF16");
+  if ((flags & SSOCT_DEPTH_FFT) && (flags & (SSOCT_PREC_MASK | SSOCT_SPLIT)))
+    return fail(SSOCT_EINVAL, "SSOCT_DEPTH_FFT is an FP32 form");
+  if ((flags & SSOCT_DEPTH_FFT) && !depth_fft_supported(T))
+    return fail(SSOCT_EUNSUPPORTED, "SSOCT_DEPTH_FFT needs T in {16, 32, 64, 128, 256}");
   ssoct_plan* p = new (std::nothrow) ssoct_plan();
   if (!p) return fail(SSOCT_ENOMEM, "host allocation failed");
   p->T = T;
@@ -374,6 +384,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
+  if (e == hipSuccess && (flags & SSOCT_DEPTH_FFT)) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
+  if (e == hipSuccess && (flags & SSOCT_DEPTH_FFT)) e = launch_depth_twiddles(T, p->dtw, stream);
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");

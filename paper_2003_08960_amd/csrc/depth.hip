@@ -19,7 +19,12 @@
 // Operand precisions: FP32 (v_mfma_f32_32x32x2_f32), FP16/BF16 hi only, and
 // FP16/BF16 split hi*hi + hi*lo + lo*hi (v_mfma_f32_32x32x16_{f16,bf16}),
 // always with FP32 accumulation.
+#include "access.hpp"
 #include "internal.hpp"
+
+#ifndef SSOCT_DEPTH_NT
+#define SSOCT_DEPTH_NT 0         // non-temporal loads of H and stores of the volume
+#endif
 
 namespace ssoct {
 
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
       const int r = r0 + i * ROWS_PER_PASS;
       const int t = ch * KC + r;
       pf[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (r < KC && t < T) pf[i] = *reinterpret_cast<const uint4*>(in + (size_t)t * P + p0 + 2 * cq);
+      if (r < KC && t < T) pf[i] = ld_once<SSOCT_DEPTH_NT>(reinterpret_cast<const uint4*>(in + (size_t)t * P + p0 + 2 * cq));
     }
   };
 
@@ -208,9 +213,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
         const float2 V = o == 0 ? v1 : v2;
         const size_t idx = (size_t)q * P + p;
         if constexpr (EPI == EPI_STORE) {
-          reinterpret_cast<float2*>(out)[idx] = V;
+          st_once<SSOCT_DEPTH_NT>(reinterpret_cast<float2*>(out) + idx, V);
         } else if constexpr (EPI == EPI_ABS) {
-          reinterpret_cast<float*>(out)[idx] = sqrtf(V.x * V.x + V.y * V.y);
+          st_once<SSOCT_DEPTH_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(V.x * V.x + V.y * V.y));
         } else {
           const double a2 = (double)V.x * V.x + (double)V.y * V.y;
           loss += a2 * a2;

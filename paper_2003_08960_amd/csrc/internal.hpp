@@ -107,6 +107,13 @@ hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in
                         hipStream_t s);
 int depth_grid(int T, int P, int cu_count);
 
+// Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).
+// epi: EPI_STORE (complex64) or EPI_ABS (forward only).  wt: exp(-2 pi i k/T).
+bool depth_fft_supported(int T);
+hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
+                            hipStream_t s);
+hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
+
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,
                        float* cut_xy, float* cut_xz, float* cut_yz, hipStream_t s);
 

@@ -48,6 +48,7 @@ struct ssoct_plan {
   float* a_f32 = nullptr;
   uint4* a_f16 = nullptr;
   uint4* a_bf16 = nullptr;
+  float2* dtw = nullptr;       // exp(-2 pi i k / T), SSOCT_DEPTH_FFT
   double zmat[15][ssoct::N_MONO];
   std::vector<double> cache;   // parameter set the tables were last built from
   bool have_aberr = false;

@@ -13,6 +13,7 @@
 // one, and a column workgroup loads its next column tile while it transforms
 // the current one.  The per-frame column table of Eq. 5/6 is staged in LDS
 // once per row workgroup.
+#include "access.hpp"
 #include "fft_engine.hpp"
 #include "internal.hpp"
 
@@ -30,6 +31,15 @@ namespace ssoct {
 #endif
 #ifndef SSOCT_COL_PREFETCH
 #define SSOCT_COL_PREFETCH 0     // load the next column tile while transforming the current one
+#endif
+#ifndef SSOCT_ROW_NT
+#define SSOCT_ROW_NT 0           // row pass: non-temporal stores of the intermediate
+#endif
+#ifndef SSOCT_COL_NT
+#define SSOCT_COL_NT 1           // column pass: non-temporal stores of H (and of the adjoint's intermediate)
+#endif
+#ifndef SSOCT_COL_NT_LD
+#define SSOCT_COL_NT_LD 1        // column pass: non-temporal loads of the intermediate
 #endif
 #ifndef SSOCT_ROW_WAVES_PER_EU
 #define SSOCT_ROW_WAVES_PER_EU 0  // > 0: ask the compiler to fit this many row-pass waves per SIMD
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
       const int vv = j + out_offset<N>(e);
       float2 val = v[e];
       if constexpr (EQ6) val = cmul(val, outfac[vv]);
-      dst[vv] = val;
+      st_once<SSOCT_ROW_NT>(dst + vv, val);
     }
   }
 }
@@ -210,12 +220,12 @@ __device__ __forceinline__ uint32_t split_pack(float x) {
 template <int FMT>
 __device__ __forceinline__ void store_h(void* __restrict__ H, size_t idx, float2 val, float scale) {
   if constexpr (FMT == HF_F32) {
-    reinterpret_cast<float2*>(H)[idx] = val;
+    st_once<SSOCT_COL_NT>(reinterpret_cast<float2*>(H) + idx, val);
   } else {
     uint2 w;
     w.x = split_pack<FMT>(val.x * scale);
     w.y = split_pack<FMT>(val.y * scale);
-    reinterpret_cast<uint2*>(H)[idx] = w;
+    st_once<SSOCT_COL_NT>(reinterpret_cast<uint2*>(H) + idx, w);
   }
 }
 
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
     const int f = tile / NCB, col = (tile % NCB) * C + c;
     const float2* s = src + (size_t)f * N * N + col;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) pf[k] = s[(size_t)(j + k * G) * N];
+    for (int k = 0; k < 16; ++k) pf[k] = ld_once<SSOCT_COL_NT_LD>(s + (size_t)(j + k * G) * N);
   };
   int tile = blockIdx.x;
   if (SSOCT_COL_PREFETCH && tile < ntiles) issue(tile);

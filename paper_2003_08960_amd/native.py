@@ -34,6 +34,7 @@ CUT_POWER = 64
 BACKWARD = 128
 PROFILE = 256
 PROFILE_KERNELS = 512
+DEPTH_FFT = 1024
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",

@@ -69,6 +69,12 @@ def test_plan_create_rejects_bad_sizes(lib):
     assert lib.ssoct_plan_create(ctypes.byref(h), 8, 64, native.PREC_FP32 | native.SPLIT, None) == native.EINVAL
     assert lib.ssoct_plan_create(ctypes.byref(h), 8, 64, 3, None) == native.EINVAL
     assert lib.ssoct_plan_create(None, 8, 64, 0, None) == native.EINVAL
+    fft = native.DEPTH_FFT
+    assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, fft | native.PREC_BF16 | native.SPLIT, None) == native.EINVAL
+    assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, fft | native.PREC_FP16, None) == native.EINVAL
+    for T in (8, 100, 512):
+        assert lib.ssoct_plan_create(ctypes.byref(h), T, 64, fft, None) == native.EUNSUPPORTED
+    assert not h.value
 
 
 def test_null_plan_is_rejected(lib):

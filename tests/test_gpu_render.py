@@ -177,8 +177,8 @@ def test_bad_arguments_raise(gpu_lib, tiny):
 
 # ---------------------------------------------------------------- mid workload (T=128, N=512)
 
-@pytest.mark.parametrize("precision,bar", [("fp32", FP32_BAR), ("fp16_split", SPLIT_BAR), ("bf16_split", SPLIT_BAR),
-                                           ("fp16", PLAIN_SANITY), ("bf16", PLAIN_SANITY)])
+@pytest.mark.parametrize("precision,bar", [("fp32", FP32_BAR), ("fp32_fft", FP32_BAR), ("fp16_split", SPLIT_BAR),
+                                           ("bf16_split", SPLIT_BAR), ("fp16", PLAIN_SANITY), ("bf16", PLAIN_SANITY)])
 def test_mid_precisions(gpu_lib, mid, precision, bar):
     _, _, V = gpu_render(mid.frames, mid.lam, mid.pitch, mid.z, precision=precision)
     ref = _mid_ref(mid)
@@ -219,3 +219,41 @@ def test_profile_record_splits_the_fresnel_stage(gpu_lib):
     plan.render(fr, sw.lam, sw.pitch, sw.z)
     st = plan.profile_read()
     assert st[1] > 0 and st[4] == -1 and st[5] == -1
+
+
+# ---------------------------------------------------------------- radix-FFT depth transform
+
+@pytest.mark.parametrize("T,N", [(16, 64), (32, 32), (64, 16), (128, 32), (256, 16), (256, 64)])
+def test_fft_depth_every_supported_length(gpu_lib, T, N):
+    """Every T the FFT form takes, with P = N^2 pixels a multiple of the pixel tile or not (N = 16: P = 256)."""
+    frames, lam = random_case(T, N, seed=3 * T + N)
+    _, _, V = gpu_render(frames, lam, 20e-6, 0.05, precision="fp32_fft")
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"T={T} N={N} rel-L2 {err:.3e}")
+    assert err <= FP32_BAR
+
+
+def test_fft_depth_matches_dense_form_and_options(gpu_lib, tiny):
+    """Dispersion and aberration, |V| output and cuts through the FFT form."""
+    from paper_2003_08960_amd.api import Plan
+    T = tiny.frames.shape[0]
+    rng = np.random.default_rng(11)
+    disp = rng.normal(0, 1.0, T)
+    zern = rng.normal(0, 0.3, 15)
+    _, _, V = gpu_render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, precision="fp32_fft", disp=disp, zern=zern)
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+    assert rel_l2(V.cpu().numpy(), ref) <= FP32_BAR
+    N = tiny.frames.shape[1]
+    plan = Plan(T, N, precision="fp32_fft", write_abs=True)
+    fr = torch.from_numpy(tiny.frames).cuda()
+    M = plan.render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern).cpu().numpy()
+    assert rel_l2(M, np.abs(ref)) <= FP32_BAR
+
+
+def test_fft_depth_rejections(gpu_lib):
+    from paper_2003_08960_amd.api import Plan
+    for T in (100, 512, 8):
+        with pytest.raises(native.SsoctError) as e:
+            Plan(T, 32, precision="fp32_fft")
+        assert e.value.code == native.EUNSUPPORTED
