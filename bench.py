@@ -135,11 +135,14 @@ def roofline(rec, form, T, N):
     nch = -(-T // rec["tuning"]["frames_per_chunk"])
     prec = form.split("_")[0]
     dname = "k_depth_fft" if form.endswith("_fft") else "k_depth"
+    # The per-launch events of the split pass add a gap after every launch; the
+    # split is rescaled to the event-free Fresnel-stage time of the timed steps.
+    scale = st["fresnel"] / (sp["row_pass"] + sp["col_pass"]) if sp["row_pass"] > 0 and sp["col_pass"] > 0 else 0.0
     ks = {
         # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
         dname: (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
-        "k_row_pass": (sp["row_pass"], nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
-        "k_col_pass": (sp["col_pass"], nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
+        "k_row_pass": (sp["row_pass"] * scale, nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
+        "k_col_pass": (sp["col_pass"] * scale, nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
     }
     kernels = {}
     for name, (ms, n, byts, flops) in ks.items():
