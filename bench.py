@@ -410,7 +410,7 @@ def main():
                                     "note": "separate untimed pass with an event after every launch"},
                "hbm_frac_path": PATH_BYTES_PER_VOXEL * voxels / (ms * 1e-3) / HBM_PEAK,
                "tuning": {"frames_per_chunk": tuning[0], "col_workgroups": tuning[1],
-                          "depth_workgroups": tuning[2]}}
+                          "depth_workgroups": tuning[2], "order": tuning[3]}}
         if ref_cols is not None:
             got = np.stack([vol[:, u, v].cpu().numpy() for u, v in pix], axis=1)
             rec["rel_l2_sampled"] = float(np.linalg.norm(got - ref_cols) / np.linalg.norm(ref_cols))

@@ -159,15 +159,22 @@ int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const dou
 int ssoct_profile_read(ssoct_plan* plan, float* ms);
 
 /* ---------------------------------------------------------------- tuning
- * Launch-shape parameters of a plan: tuning[0] frames per chunk of the
- * Fresnel stage (1 .. the chunk the workspace was sized for), tuning[1]
- * persistent column-pass workgroups (0 = default), tuning[2] persistent
- * depth-transform workgroups (0 = default).  They change speed only, never
- * results. */
+ * Launch-shape parameters of a plan, int tuning[4]: tuning[0] frames per
+ * chunk of the Fresnel stage (1 .. the chunk the workspace was sized for),
+ * tuning[1] persistent column-pass workgroups (0 = default), tuning[2]
+ * persistent depth-transform workgroups (0 = default), tuning[3] evaluation
+ * order of the SSOCT_DEPTH_FFT form (0 = default: Fresnel transform of every
+ * frame, then the depth transform; 1 = depth transform of the rescaled real
+ * frames first, then one Fresnel transform per bin, which by linearity is the
+ * same map when the chirp and the per-frame factor do not depend on the
+ * frame: no SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS; otherwise
+ * the frame order is used).  tuning[0..2] change speed only, never results;
+ * tuning[3] changes the rounding order only. */
 
-/* Time candidate launch shapes on the given inputs (HIP events on the plan's
- * stream; synchronises the stream), keep the fastest in the plan and write it
- * to tuning[3].  Arguments as for ssoct_render; vol is overwritten. */
+/* Time candidate launch shapes (and, where allowed, both evaluation orders)
+ * on the given inputs (HIP events on the plan's stream; synchronises the
+ * stream), keep the fastest in the plan and write it to tuning[4].
+ * Arguments as for ssoct_render; vol is overwritten. */
 int ssoct_plan_tune(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                     const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                     void* vol, int* tuning);

@@ -147,12 +147,19 @@ class Plan:
 
     # -- launch shapes ---------------------------------------------------------------------------
     def get_tuning(self):
-        t = (ctypes.c_int * 3)()
+        """[frames per chunk, column workgroups, depth workgroups, evaluation order]."""
+        t = (ctypes.c_int * 4)()
         native.check(self.lib.ssoct_plan_get_tuning(self._h, t))
         return [int(x) for x in t]
 
     def set_tuning(self, tuning):
-        t = (ctypes.c_int * 3)(*[int(x) for x in tuning])
+        """Set launch shapes; a 3-entry list keeps the current evaluation order."""
+        vals = [int(x) for x in tuning]
+        if len(vals) == 3:
+            vals.append(self.get_tuning()[3])
+        if len(vals) != 4:
+            raise ValueError("tuning has 3 or 4 entries")
+        t = (ctypes.c_int * 4)(*vals)
         native.check(self.lib.ssoct_plan_set_tuning(self._h, t))
 
     def tuning_key(self) -> str:
@@ -172,7 +179,7 @@ class Plan:
                 return list(cached)
         _check_frames(frames, self.T, self.N)
         out = self.render(frames, lam, pitch, z, disp_phase, zernike, out=out)
-        t = (ctypes.c_int * 3)()
+        t = (ctypes.c_int * 4)()
         self._sync_stream()
         native.check(self.lib.ssoct_plan_tune(
             self._h, ctypes.c_void_p(_ptr(frames)), native.host_doubles(lam, self.T), float(pitch), float(z),

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "plan.hpp"
@@ -226,6 +227,10 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
   SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern ? p->aberr : nullptr, p->stream));
   p->have_aberr = zern != nullptr;
+  // depth-first order: the chirp and the per-frame row factor must not depend on the frame
+  bool no_disp = true;
+  for (int t = 0; disp && t < T; ++t) no_disp = no_disp && disp[t] == 0.0;
+  p->df_allowed = (p->flags & SSOCT_DEPTH_FFT) && !exact && !(p->flags & SSOCT_WRITE_ABS) && no_disp;
   // FP16 operands: |H| <= N^2 * 65535 * amplitude, kept below 2^15 by an exact power-of-two scale
   p->sigma = 0;
   if (h_format(depth_prec(p->flags)) == HF_F16) {
@@ -265,8 +270,53 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
   return SSOCT_OK;
 }
 
+int fresnel_chunks(const ssoct_plan* p) {
+  if (p->depth_first()) {
+    const int fh = p->F_run / 2 > 0 ? p->F_run / 2 : 1;
+    return (p->T / 2 + fh) / fh;   // ceil((T/2 + 1) / fh)
+  }
+  return (p->T + p->F_run - 1) / p->F_run;
+}
+
+// Depth-first order (frame-independent chirp and row factor): the depth
+// DFT of the rescaled real frames, G_q for q = 0..T/2 (stage 1), then the
+// Fresnel transforms of the bins, chunk by chunk: V[q] = DFT2(fac G_q) and
+// V[T - q] = DFT2(fac conj(G_q)) for 0 < q < T/2.  Events: ev[1] start,
+// ev[2] after stage 1, ev[3] at the end; kev after each row and column step.
+static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L,
+                              void* vol, hipEvent_t* ev, hipEvent_t* kev) {
+  const int T = p->T, N = p->N;
+  const size_t P = (size_t)N * N;
+  float2* G = reinterpret_cast<float2*>(ws + L.H);
+  float2* inter = reinterpret_cast<float2*>(ws + L.inter);
+  float2* V = static_cast<float2*>(vol);
+  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  const int nb = T / 2 + 1;                     // bins of G
+  const int nconj = (T + 1) / 2;                // bins q < nconj have a partner T - q (q >= 1)
+  const int fh = p->F_run / 2 > 0 ? p->F_run / 2 : 1;   // bins per chunk: 2 fh transforms fit the chunk buffer
+  if (2 * fh > p->F) return fail(SSOCT_EUNSUPPORTED, "chunk buffer too small for the depth-first order");
+  if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
+  SSOCT_HIP(launch_rescale_dft(T, N, frames, p->rows, p->cols, p->params, p->dtw, G, s));
+  if (ev) SSOCT_HIP(hipEventRecord(ev[2], s));
+  for (int qa = 0, c = 0; qa < nb; qa += fh, ++c) {
+    const int n = nb - qa < fh ? nb - qa : fh;
+    SSOCT_HIP(launch_row_pass_g(N, n, qa, T, G, p->rows, p->cols, p->tw, ab, p->outfac, inter, fh, s));
+    if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c], s));
+    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, p->col_grid, s));
+    const int ca = qa > 1 ? qa : 1;
+    const int cb = qa + n < nconj ? qa + n : nconj;
+    if (cb > ca)
+      SSOCT_HIP(launch_col_pass_v(N, cb - ca, inter + (size_t)(fh + ca - qa) * P, p->tw, p->outfac,
+                                  V + (size_t)(T - ca) * P, -1, p->col_grid, s));
+    if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
+  }
+  if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
+  return SSOCT_OK;
+}
+
 int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
                 hipEvent_t* ev, hipEvent_t* kev) {
+  if (p->depth_first()) return render_depth_first(p, s, frames, ws, L, vol, ev, kev);
   const int T = p->T, N = p->N, F = p->F_run;
   if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
   if (kev) {  // the two passes launched one by one with an event after each
@@ -379,6 +429,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess && (flags & SSOCT_PROFILE)) {
     p->ev.assign((size_t)ssoct_plan::MAXREC * 4, nullptr);
     p->rec_nch.assign(ssoct_plan::MAXREC, 0);
+    p->rec_df.assign(ssoct_plan::MAXREC, 0);
     for (auto& ev : p->ev)
       if (e == hipSuccess) e = hipEventCreate(&ev);
   }
@@ -419,8 +470,11 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
   const int slot = p->rec % ssoct_plan::MAXREC;
   hipEvent_t* ev = prof ? &p->ev[(size_t)slot * 4] : nullptr;
   hipEvent_t* kev = nullptr;
+  if (prof) SSOCT_HIP(hipEventRecord(ev[0], p->stream));
+  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
+  if (status < 0) return status;
   if (prof) {
-    const int nch = (p->T + p->F_run - 1) / p->F_run;
+    const int nch = fresnel_chunks(p);
     if ((p->flags & SSOCT_PROFILE_KERNELS) && nch <= ssoct_plan::KMAX) {
       if (p->kev.empty()) {
         p->kev.assign((size_t)ssoct_plan::MAXREC * 2 * ssoct_plan::KMAX, nullptr);
@@ -429,10 +483,8 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
       kev = &p->kev[(size_t)slot * 2 * ssoct_plan::KMAX];
     }
     p->rec_nch[slot] = kev ? nch : 0;
-    SSOCT_HIP(hipEventRecord(ev[0], p->stream));
+    p->rec_df[slot] = p->depth_first() ? 1 : 0;
   }
-  const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
-  if (status < 0) return status;
   if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev, kev)) return rc;
   if (prof) ++p->rec;
   return status;
@@ -524,17 +576,19 @@ int ssoct_profile_read(ssoct_plan* p, float* ms) {
   for (int r = 0; r < n; ++r) {
     const int slot = (p->rec - 1 - r) % ssoct_plan::MAXREC;
     hipEvent_t* e = &p->ev[(size_t)slot * 4];
+    const bool df = p->rec_df[slot] != 0;   // depth-first order: depth stage between e[1] and e[2]
     for (int i = 0; i < 3; ++i) {
       float t = 0.f;
       SSOCT_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
-      sum[i] += t;
+      sum[(df && i > 0) ? 3 - i : i] += t;
     }
     const int nch = p->rec_nch[slot];
     if (nch > 0) {
       hipEvent_t* k = &p->kev[(size_t)slot * 2 * ssoct_plan::KMAX];
+      hipEvent_t start = df ? e[2] : e[1];
       for (int c = 0; c < nch; ++c) {
         float tr = 0.f, tc = 0.f;
-        SSOCT_HIP(hipEventElapsedTime(&tr, c == 0 ? e[1] : k[2 * c - 1], k[2 * c]));
+        SSOCT_HIP(hipEventElapsedTime(&tr, c == 0 ? start : k[2 * c - 1], k[2 * c]));
         SSOCT_HIP(hipEventElapsedTime(&tc, k[2 * c], k[2 * c + 1]));
         sum[3] += tr;
         sum[4] += tc;
@@ -556,6 +610,7 @@ int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
   tuning[0] = p->F_run;
   tuning[1] = p->col_grid;
   tuning[2] = p->depth_grid;
+  tuning[3] = p->order;
   return SSOCT_OK;
 }
 
@@ -565,9 +620,12 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   if (tuning[0] < 1 || tuning[0] > p->F) return fail(SSOCT_EINVAL, "frames per chunk out of range");
   if (tuning[1] < 0 || tuning[1] > 65536 || tuning[2] < 0 || tuning[2] > 4096)
     return fail(SSOCT_EINVAL, "workgroup count out of range");
+  if (tuning[3] != 0 && tuning[3] != 1) return fail(SSOCT_EINVAL, "order must be 0 or 1");
+  if (p->streaming && tuning[3] != p->order) return fail(SSOCT_EINVAL, "the order is fixed while a stream uses the plan");
   p->F_run = tuning[0];
   p->col_grid = tuning[1];
   p->depth_grid = tuning[2];
+  p->order = tuning[3];
   return SSOCT_OK;
 }
 
@@ -589,6 +647,7 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
       float a = 0, b = 0;
       SSOCT_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
       SSOCT_HIP(hipEventElapsedTime(&b, ev[2], ev[3]));
+      if (p->depth_first()) std::swap(a, b);   // that order runs the depth stage first
       if (rep > 0) {  // first run warms caches and code
         best_a = a < best_a ? a : best_a;
         best_b = b < best_b ? b : best_b;
@@ -625,6 +684,16 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
     if (rc == SSOCT_OK && b < best) best = b, bestD = Ds[di];
   }
   p->depth_grid = bestD;
+  // evaluation order (FFT form without frame-dependent factors): whole render, both orders
+  if (rc == SSOCT_OK && p->df_allowed) {
+    float tot[2] = {1e30f, 1e30f};
+    for (int o = 0; o < 2 && rc == SSOCT_OK; ++o) {
+      p->order = o;
+      rc = measure(&a, &b);
+      tot[o] = a + b;
+    }
+    p->order = tot[1] < tot[0] ? 1 : 0;
+  }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc != SSOCT_OK) return rc;
   if (tuning) ssoct_plan_get_tuning(p, tuning);

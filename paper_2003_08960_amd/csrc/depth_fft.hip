@@ -64,6 +64,199 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
   }
 }
 
+// Depth-first order, stage 1: the depth DFT of the rescaled frames J_t (Eq. 5)
+// before any spatial transform.  J_t is real, so G_q = sum_t J_t wT^(q t) is
+// Hermitian in q and only bins q = 0..T/2 are written: G [T/2 + 1][N][N],
+// pixels at FFT positions (m, n) of the Fresnel passes (row and column tables
+// of frame t give the source position and weight of each position).
+template <int T2, int PX>
+__global__ __launch_bounds__(16 * PX) void k_rescale_dft(const uint16_t* __restrict__ frames,
+                                                          const AxisTab* __restrict__ rows,
+                                                          const AxisTab* __restrict__ cols,
+                                                          const float2* __restrict__ wt, float2* __restrict__ G,
+                                                          int N, int logN) {
+  constexpr int T = 16 * T2;
+  __shared__ float2 lds[T * PX];
+  const int px = threadIdx.x % PX, r = threadIdx.x / PX;
+  const size_t P = (size_t)N * N;
+  const int pix = blockIdx.x * PX + px;               // P is a multiple of PX (N >= 16, PX <= 256)
+  const int m = pix >> logN, n = pix & (N - 1);
+
+  float2 a[T2];
+#pragma unroll
+  for (int t2 = 0; t2 < T2; ++t2) {
+    const int t = r + 16 * t2;
+    const AxisTab rt = rows[(size_t)t * N + m];
+    const AxisTab ct = cols[(size_t)t * N + n];
+    const uint16_t* I = frames + (size_t)t * P;
+    const int y1 = rt.i0 + 1 < N ? rt.i0 + 1 : N - 1;
+    const int x1 = ct.i0 + 1 < N ? ct.i0 + 1 : N - 1;
+    const float a00 = I[(size_t)rt.i0 * N + ct.i0], a01 = I[(size_t)rt.i0 * N + x1];
+    const float a10 = I[(size_t)y1 * N + ct.i0], a11 = I[(size_t)y1 * N + x1];
+    const float ya = a00 + rt.f * (a10 - a00);        // lerp along y, then along x
+    const float yb = a01 + rt.f * (a11 - a01);
+    a[t2] = make_float2(ya + ct.f * (yb - ya), 0.f);
+  }
+  if constexpr (T2 > 1) dft_small<T2, -1>(a);
+#pragma unroll
+  for (int q2 = 0; q2 < T2; ++q2) lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], wt[(q2 * r) % T]);
+  __syncthreads();
+  if (r >= T2) return;
+  float2 b[16];
+#pragma unroll
+  for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+  dft16<-1>(b);
+#pragma unroll
+  for (int q1 = 0; q1 < 16; ++q1) {
+    const int q = r + T2 * q1;
+    if (2 * q <= T) st_once<SSOCT_DFFT_NT>(G + (size_t)q * P + pix, b[q1]);
+  }
+}
+
+// Source position of FFT position i at frame scale s, exactly as the axis
+// tables compute it: N/2 + c s in FP64 without contraction, floor, clamp.
+__device__ __forceinline__ void src_pos(int i, int N, double s, int& i0, float& f) {
+  const int half = N >> 1;
+  const int c = ((i + half) & (N - 1)) - half;
+  const double P = __dadd_rn(__dmul_rn((double)c, s), (double)half);
+  const double p0 = floor(P);
+  int k = (int)p0;
+  k = k < 0 ? 0 : (k > N - 1 ? N - 1 : k);
+  i0 = k;
+  f = (float)(P - p0);
+}
+
+// The same transform for N >= 64, where a tile of PX = 32 FFT positions lies
+// inside one row and one half of the centred order, so its source columns at
+// frame t are a window of at most PX + 2 samples (s_t <= 1) starting at the
+// first position's column.  The two source rows of that window are staged
+// in LDS for every frame with aligned dword loads, and the interpolation
+// reads LDS: one coalesced load per dword instead of four scattered 2-byte
+// gathers and two 16-byte table reads per sample.
+template <int T2>
+__global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restrict__ frames,
+                                                         const double* __restrict__ params,
+                                                         const float2* __restrict__ wt, float2* __restrict__ G,
+                                                         int N, int logN) {
+  constexpr int PX = 32;
+  constexpr int T = 16 * T2;
+  constexpr int WD = PX / 2 + 2;             // dwords per staged row window (36 samples >= PX + 3)
+  constexpr int STRIDE = ParamLayout::PER_FRAME;   // doubles per frame in the parameter block (s_t first)
+  constexpr int NE = (T * 2 * WD + 16 * PX - 1) / (16 * PX);
+  __shared__ float2 lds[T * PX];             // transposition buffer; the staged windows alias it
+  __shared__ double fs[T], fp[T];            // per frame: s_t and the source position of the tile's first column
+  __shared__ int fy0[T], fxa[T];             // per frame: source row y0 and the even start of the window
+  __shared__ float ffy[T];                   // per frame: y weight
+  static_assert(T * 2 * WD * 4 <= T * PX * 8, "staged windows must fit the transposition buffer");
+  uint32_t* foot = reinterpret_cast<uint32_t*>(lds);   // [T][2][WD]
+  const int px = threadIdx.x % PX, r = threadIdx.x / PX;
+  const size_t P = (size_t)N * N;
+  const int pix0 = blockIdx.x * PX;
+  const int m = pix0 >> logN, n0 = pix0 & (N - 1);
+  const int half = N >> 1;
+  const int c0 = ((n0 + half) & (N - 1)) - half;   // centred index of the first column (same half as the tile)
+
+  for (int t = threadIdx.x; t < T; t += 16 * PX) {
+    const double st = params[(size_t)STRIDE * t];
+    int y0, x0;
+    float fy, fx;
+    src_pos(m, N, st, y0, fy);
+    src_pos(n0, N, st, x0, fx);
+    fs[t] = st;
+    fp[t] = __dadd_rn(__dmul_rn((double)c0, st), (double)half);
+    fy0[t] = y0;
+    ffy[t] = fy;
+    fxa[t] = x0 & ~1;
+  }
+  __syncthreads();
+  // every load of the staging is in flight before the first LDS store
+  uint32_t stage[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = threadIdx.x + i * 16 * PX;
+    stage[i] = 0u;
+    if (e < T * 2 * WD) {
+      const int t = e / (2 * WD), rr = (e / WD) & 1, d = e % WD;
+      const int y0 = fy0[t];
+      const int y = rr ? (y0 + 1 < N ? y0 + 1 : N - 1) : y0;
+      const int col = fxa[t] + 2 * d;
+      const uint16_t* row = frames + (size_t)t * P + (size_t)y * N;
+      if (col + 1 < N) stage[i] = *reinterpret_cast<const uint32_t*>(row + col);
+      else if (col < N) stage[i] = row[col];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = threadIdx.x + i * 16 * PX;
+    if (e < T * 2 * WD) foot[e] = stage[i];
+  }
+  __syncthreads();
+
+  float2 a[T2];
+#pragma unroll
+  for (int t2 = 0; t2 < T2; ++t2) {
+    const int t = r + 16 * t2;
+    // N/2 + (c0 + px) s_t = fp[t] + px s_t up to FP64 rounding; column and weight as in the tables
+    const double Pd = fma((double)px, fs[t], fp[t]);
+    const double p0 = floor(Pd);
+    const int o0 = (int)p0 - fxa[t];
+    const float fx = (float)(Pd - p0);
+    const float fy = ffy[t];
+    // right tap: the next sample of the window (zero past the last column, where fx is exactly 0)
+    const uint16_t* w0 = reinterpret_cast<const uint16_t*>(foot + (t * 2) * WD);
+    const uint16_t* w1 = reinterpret_cast<const uint16_t*>(foot + (t * 2 + 1) * WD);
+    const float a00 = w0[o0], a01 = w0[o0 + 1], a10 = w1[o0], a11 = w1[o0 + 1];
+    const float ya = a00 + fy * (a10 - a00);          // lerp along y, then along x
+    const float yb = a01 + fy * (a11 - a01);
+    a[t2] = make_float2(ya + fx * (yb - ya), 0.f);
+  }
+  __syncthreads();   // window reads done before the transposition buffer is written
+  if constexpr (T2 > 1) dft_small<T2, -1>(a);
+#pragma unroll
+  for (int q2 = 0; q2 < T2; ++q2) lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], wt[(q2 * r) % T]);
+  __syncthreads();
+  if (r >= T2) return;
+  float2 b[16];
+#pragma unroll
+  for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+  dft16<-1>(b);
+#pragma unroll
+  for (int q1 = 0; q1 < 16; ++q1) {
+    const int q = r + T2 * q1;
+    if (2 * q <= T) st_once<SSOCT_DFFT_NT>(G + (size_t)q * P + pix0 + px, b[q1]);
+  }
+}
+
+template <int T2>
+static hipError_t rescale_dft_t(int N, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                                const double* params, const float2* wt, float2* G, hipStream_t s) {
+  int logN = 0;
+  while ((1 << logN) < N) ++logN;
+  const size_t P = (size_t)N * N;
+  if (N >= 64) {
+    hipLaunchKernelGGL((k_rescale_dft_lds<T2>), dim3((unsigned)(P / 32)), dim3(512), 0, s, frames, params, wt, G, N,
+                       logN);
+  } else {
+    constexpr int PX = SSOCT_DFFT_PX;
+    hipLaunchKernelGGL((k_rescale_dft<T2, PX>), dim3((unsigned)(P / PX)), dim3(16 * PX), 0, s, frames, rows, cols,
+                       wt, G, N, logN);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                              const double* params, const float2* wt, float2* G, hipStream_t s) {
+  if ((size_t)N * N % SSOCT_DFFT_PX != 0) return hipErrorInvalidValue;
+  switch (T) {
+    case 16: return rescale_dft_t<1>(N, frames, rows, cols, params, wt, G, s);
+    case 32: return rescale_dft_t<2>(N, frames, rows, cols, params, wt, G, s);
+    case 64: return rescale_dft_t<4>(N, frames, rows, cols, params, wt, G, s);
+    case 128: return rescale_dft_t<8>(N, frames, rows, cols, params, wt, G, s);
+    case 256: return rescale_dft_t<16>(N, frames, rows, cols, params, wt, G, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int T2, int DIR, int EPI>
 static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, hipStream_t s) {
   constexpr int PX = SSOCT_DFFT_PX;

@@ -90,6 +90,19 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
                            const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
 
+// Depth-first order (frame-independent chirp, no per-frame phase):
+// G [T/2 + 1][N][N] = depth DFT of the rescaled frames (stage 1); then per
+// chunk of nb bins from qa: row DFTs of fac G_q and fac conj(G_q) into
+// inter[f] and inter[Fh + f], and column DFTs of a chunk into the volume,
+// frame f of the chunk at V + f fstride N^2.
+hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
+                              const double* params, const float2* wt, float2* G, hipStream_t s);
+hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
+                             const AxisTab* cols0, const float2* tw, const float2* aberr, const float2* outfac,
+                             float2* inter, int Fh, hipStream_t s);
+hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
+                             int fstride, int grid, hipStream_t s);
+
 // Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
 // into `inter`, then row DFT^- fused with the recomputed row input and the
 // per-frame FP64 moments of Im(conj(g) z) (partials [T][nblk][N_MONO]).

@@ -61,8 +61,12 @@ struct ssoct_plan {
   std::vector<hipEvent_t> ev;   // [MAXREC][4]
   std::vector<hipEvent_t> kev;  // [MAXREC][2 KMAX], created on first use
   std::vector<int> rec_nch;     // chunks of each record (0: no per-kernel events)
+  std::vector<int> rec_df;      // record made in the depth-first order
   int rec = 0;
   bool streaming = false;      // a stream object uses the plan's tables
+  bool df_allowed = false;     // current tables allow the depth-first order (SSOCT_DEPTH_FFT)
+  int order = 0;               // tuning: 1 = depth-first order where allowed, 0 = frame order
+  bool depth_first() const { return df_allowed && order == 1; }
 };
 
 namespace ssoct {
@@ -83,5 +87,7 @@ int render_core(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char*
 int render_chunk(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, int t0,
                  int Fc);
 int render_depth(ssoct_plan* p, hipStream_t stream, char* ws, const WsLayout& L, void* vol);
+// Fresnel-stage launches per render (chunks of frames, or of bins in the depth-first order)
+int fresnel_chunks(const ssoct_plan* p);
 
 }  // namespace ssoct

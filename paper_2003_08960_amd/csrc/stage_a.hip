@@ -21,7 +21,7 @@ namespace ssoct {
 
 // Tuning knobs (compile-time; the defaults are the tuned values)
 #ifndef SSOCT_ROW_RPG
-#define SSOCT_ROW_RPG 4          // rows per row group and workgroup iteration count
+#define SSOCT_ROW_RPG 8          // rows per row group and workgroup iteration count
 #endif
 #ifndef SSOCT_ROW_WAVESYNC
 #define SSOCT_ROW_WAVESYNC 1     // single-wave row groups exchange with wave-level ordering
@@ -195,6 +195,73 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
   }
 }
 
+// ------------------------------------------------------------------ bin-pair row pass (depth-first order)
+// Row m of G_q (q = qa + f, FFT positions, from the depth DFT of the rescaled
+// frames) times the frame-independent chirp, sign and optional aberration:
+// DFT of fac G_q into chunk frame f, and for 0 < q < T/2 DFT of fac conj(G_q)
+// into chunk frame Fh + f.  The column pass turns these into V[q] and
+// V[T - q] (Eq. 6 is linear and its chirp does not depend on the frame when
+// lambda_1 is used for every frame and no per-frame phase is applied).
+template <int N, bool ABERR, bool EQ6>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g(
+    const float2* __restrict__ Gq, int qa, int T, const AxisTab* __restrict__ rows0,
+    const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const float2* __restrict__ outfac, float2* __restrict__ inter, int Fh) {
+  using S = FFTShape<N>;
+  using R = RowCfg<N>;
+  constexpr int G = S::G;
+  __shared__ AxisTab ctab[N];
+  __shared__ float2 xbuf[R::GR][RowLds<N>::XS];
+  const int g = threadIdx.x / G, j = threadIdx.x % G;
+  const int f = blockIdx.y;
+  const int q = qa + f;
+  const bool both = q >= 1 && 2 * q < T;
+  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
+  stage_ctab<N>(ctab, cols0);
+  float2 nxt[16];
+  {
+    const float2* src = Gq + ((size_t)q * N + m0) * N;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
+  }
+  __syncthreads();  // column table visible
+#pragma unroll 1
+  for (int i = 0; i < R::RPG; ++i) {
+    const int m = m0 + i;
+    float2 gv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gv[k] = nxt[k];
+    if (i + 1 < R::RPG) {  // prefetch the next row of this group
+      const float2* src = Gq + ((size_t)q * N + m + 1) * N;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
+    }
+    const float2 rowfac = rows0[m].fac;
+    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+#pragma unroll 1
+    for (int h = 0; h < (both ? 2 : 1); ++h) {
+      float2 v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int n = j + k * G;
+        float2 fac = cmul(ctab[n].fac, rowfac);
+        if constexpr (ABERR) fac = cmul(fac, arow[n]);
+        v[k] = cmul(fac, h == 0 ? gv[k] : cconj(gv[k]));
+      }
+      exchange_sync<R::WAVE>();  // the previous transform's exchange reads are done
+      fft_group<N, +1, R::WAVE>(v, j, xbuf[g], 1, tw);
+      float2* dst = inter + ((size_t)(h == 0 ? f : Fh + f) * N + m) * N;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int vv = j + out_offset<N>(e);
+        float2 val = v[e];
+        if constexpr (EQ6) val = cmul(val, outfac[vv]);
+        st_once<SSOCT_ROW_NT>(dst + vv, val);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ H storage formats
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -218,7 +285,7 @@ __device__ __forceinline__ uint32_t split_pack(float x) {
 }
 
 template <int FMT>
-__device__ __forceinline__ void store_h(void* __restrict__ H, size_t idx, float2 val, float scale) {
+__device__ __forceinline__ void store_h(void* __restrict__ H, long long idx, float2 val, float scale) {
   if constexpr (FMT == HF_F32) {
     st_once<SSOCT_COL_NT>(reinterpret_cast<float2*>(H) + idx, val);
   } else {
@@ -238,7 +305,8 @@ template <int N, int DIR, int FMT, bool EQ6>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* __restrict__ src,
                                                                  const float2* __restrict__ tw,
                                                                  const float2* __restrict__ outfac,
-                                                                 void* __restrict__ dst, float scale, int ntiles) {
+                                                                 void* __restrict__ dst, float scale, int ntiles,
+                                                                 int fstride) {
   using S = FFTShape<N>;
   constexpr int G = S::G;
   constexpr int C = ColCfg<N>::C;
@@ -268,13 +336,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
     }
     const int f = tile / NCB, col = (tile % NCB) * C + c;
     fft_group<N, DIR>(v, j, xbuf + c, C, tw);
-    const size_t fo = (size_t)f * N * N;
+    const long long fo = (long long)f * fstride * N * N;   // output frame f at dst + f fstride N^2
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int u = j + out_offset<N>(e);
       float2 val = v[e];
       if constexpr (EQ6) val = cmul(val, outfac[u]);
-      store_h<FMT>(dst, fo + (size_t)u * N + col, val, scale);
+      store_h<FMT>(dst, fo + (long long)u * N + col, val, scale);
     }
   }
 }
@@ -407,7 +475,7 @@ static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* t
   const bool eq6 = outfac != nullptr;
 #define SSOCT_COL(FMT, E)                                                                                  \
   hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E>), grid, block, 0, s, inter, tw, outfac, (void*)dst, scale, \
-                     ntiles)
+                     ntiles, 1)
   if (fmt == HF_F32) { if (eq6) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
   else if (fmt == HF_F16) { if (eq6) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
   else { if (eq6) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
@@ -423,7 +491,7 @@ static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* t
   dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
   const float2* src = B + (size_t)t0 * N * N;
   hipLaunchKernelGGL((k_col_pass<N, -1, HF_F32, false>), grid, block, 0, s, src, tw, (const float2*)nullptr,
-                     (void*)inter, 1.0f, ntiles);
+                     (void*)inter, 1.0f, ntiles, 1);
   return hipGetLastError();
 }
 
@@ -452,6 +520,53 @@ static hipError_t row_pass_adj_n(int F, int t0, const uint16_t* frames, const Ax
     case 2048: return CALL(2048);        \
     default: return hipErrorInvalidValue; \
   }
+
+template <int N>
+static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const AxisTab* rows0, const AxisTab* cols0,
+                               const float2* tw, const float2* aberr, const float2* outfac, float2* inter, int Fh,
+                               hipStream_t s) {
+  using R = RowCfg<N>;
+  dim3 grid(N / R::ROWS, nb), block(R::THREADS);
+#define SSOCT_RG(A, E)                                                                                            \
+  hipLaunchKernelGGL((k_row_pass_g<N, A, E>), grid, block, 0, s, G, qa, T, rows0, cols0, tw, aberr, outfac, inter, \
+                     Fh)
+  if (aberr && outfac) SSOCT_RG(true, true);
+  else if (aberr) SSOCT_RG(true, false);
+  else if (outfac) SSOCT_RG(false, true);
+  else SSOCT_RG(false, false);
+#undef SSOCT_RG
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t col_pass_v_n(int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
+                               int fstride, int req_grid, hipStream_t s) {
+  using C = ColCfg<N>;
+  const int ntiles = F * (N / C::C);
+  dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
+  if (outfac)
+    hipLaunchKernelGGL((k_col_pass<N, +1, HF_F32, true>), grid, block, 0, s, inter, tw, outfac, (void*)V, 1.0f,
+                       ntiles, fstride);
+  else
+    hipLaunchKernelGGL((k_col_pass<N, +1, HF_F32, false>), grid, block, 0, s, inter, tw, outfac, (void*)V, 1.0f,
+                       ntiles, fstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
+                             const AxisTab* cols0, const float2* tw, const float2* aberr, const float2* outfac,
+                             float2* inter, int Fh, hipStream_t s) {
+#define CALL(n) row_pass_g_n<n>(nb, qa, T, G, rows0, cols0, tw, aberr, outfac, inter, Fh, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
+                             int fstride, int grid, hipStream_t s) {
+#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
 
 hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
                            const float2* tw, const float2* aberr, const float2* outfac, float2* inter, hipStream_t s) {

@@ -124,6 +124,12 @@ int finish(ssoct_stream* st, int k, hipGraphExec_t g) {
 int run_landed_chunks(ssoct_stream* st, int k) {
   Slot& s = st->slots[k];
   const int T = st->plan->T, F = st->F;
+  if (s.chunk.empty()) {  // whole-volume graph: wait for every frame
+    if (s.filled < T) return SSOCT_OK;
+    SSOCT_HIP(hipEventRecord(s.landed, st->copy));
+    SSOCT_HIP(hipStreamWaitEvent(s.s, s.landed, 0));
+    return SSOCT_OK;
+  }
   const int ready = s.filled == T ? (int)s.chunk.size() : s.filled / F;
   if (ready <= s.chunks_run) return SSOCT_OK;
   SSOCT_HIP(hipEventRecord(s.landed, st->copy));
@@ -188,7 +194,8 @@ int ssoct_stream_create(ssoct_stream** out, ssoct_plan* p, const double* lambda,
   const WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
   const size_t ncut = (size_t)N * N + 2 * (size_t)T * N;
   const int F = p->F_run;
-  const int nch = (T + F - 1) / F;
+  // chunk-wise Fresnel graphs need the frame order; the depth-first order starts with all frames
+  const int nch = p->depth_first() ? 0 : (T + F - 1) / F;
   st->F = F;
   const bool power = (p->flags & SSOCT_CUT_POWER) != 0;
   hipError_t e = hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
@@ -215,11 +222,14 @@ int ssoct_stream_create(ssoct_stream** out, ssoct_plan* p, const double* lambda,
       return SSOCT_OK;
     };
     rc = capture(s.s, &s.exec, [&]() -> int {
-      for (int t0 = 0; t0 < T; t0 += F)
-        if (int r = render_chunk(p, s.s, s.frames, s.ws, L, t0, T - t0 < F ? T - t0 : F)) return r;
-      return tail();
+      if (int r = render_core(p, s.s, s.frames, s.ws, L, s.vol, nullptr)) return r;   // whichever order applies
+      float* c = s.cuts;
+      SSOCT_HIP(launch_cuts(T, N, s.vol, x0, y0, q0, power ? 1 : 0, c, c + (size_t)N * N,
+                            c + (size_t)N * N + (size_t)T * N, s.s));
+      SSOCT_HIP(hipMemcpyAsync(s.hcuts, c, ncut * sizeof(float), hipMemcpyDeviceToHost, s.s));
+      return SSOCT_OK;
     });
-    if (rc == SSOCT_OK) rc = capture(s.s, &s.tail, tail);
+    if (rc == SSOCT_OK && nch > 0) rc = capture(s.s, &s.tail, tail);
     s.chunk.assign(nch, nullptr);
     for (int c = 0; c < nch && rc == SSOCT_OK; ++c) {
       const int t0 = c * F;
@@ -301,7 +311,7 @@ int ssoct_stream_push_frames(ssoct_stream* st, const uint16_t* host, int nframes
     if (int r = run_landed_chunks(st, k)) return r;
     if (pos + run == T) {
       st->filling = -1;
-      if (int r = finish(st, k, s.tail)) return r;
+      if (int r = finish(st, k, s.chunk.empty() ? s.exec : s.tail)) return r;
     }
   }
   return rc;

@@ -223,14 +223,19 @@ def test_profile_record_splits_the_fresnel_stage(gpu_lib):
 
 # ---------------------------------------------------------------- radix-FFT depth transform
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("T,N", [(16, 64), (32, 32), (64, 16), (128, 32), (256, 16), (256, 64)])
-def test_fft_depth_every_supported_length(gpu_lib, T, N):
-    """Every T the FFT form takes, with P = N^2 pixels a multiple of the pixel tile or not (N = 16: P = 256)."""
+def test_fft_depth_every_supported_length(gpu_lib, T, N, order):
+    """Every T the FFT form takes, in both evaluation orders."""
+    from paper_2003_08960_amd.api import Plan
     frames, lam = random_case(T, N, seed=3 * T + N)
-    _, _, V = gpu_render(frames, lam, 20e-6, 0.05, precision="fp32_fft")
+    print(f"\n[gpu] fft depth T={T} N={N} order={order}", flush=True)
+    plan = Plan(T, N, precision="fp32_fft")
+    plan.set_tuning(plan.get_tuning()[:3] + [order])
+    V = plan.render(torch.from_numpy(frames).cuda(), lam, 20e-6, 0.05)
     ref = O.render(frames, lam, 20e-6, 0.05)
     err = rel_l2(V.cpu().numpy(), ref)
-    print(f"T={T} N={N} rel-L2 {err:.3e}")
+    print(f"T={T} N={N} order={order} rel-L2 {err:.3e}")
     assert err <= FP32_BAR
 
 
@@ -257,3 +262,60 @@ def test_fft_depth_rejections(gpu_lib):
         with pytest.raises(native.SsoctError) as e:
             Plan(T, 32, precision="fp32_fft")
         assert e.value.code == native.EUNSUPPORTED
+
+
+# ---------------------------------------------------------------- depth-first order of the FFT form
+# With the default chirp (lambda_1 for every frame) and no dispersion phase, the FFT form takes the
+# depth DFT of the rescaled frames first and one 2-D transform per bin pair (q, T - q).
+
+@pytest.mark.parametrize("aberr,eq6", [(False, False), (True, False), (False, True), (True, True)])
+def test_depth_first_options(gpu_lib, tiny, aberr, eq6):
+    from paper_2003_08960_amd.api import Plan
+    zern = np.random.default_rng(5).normal(0, 0.3, 15) if aberr else None
+    T, N = tiny.frames.shape[:2]
+    plan = Plan(T, N, precision="fp32_fft", eq6_phase=eq6)
+    plan.set_tuning(plan.get_tuning()[:3] + [1])
+    V = plan.render(torch.from_numpy(tiny.frames).cuda(), tiny.lam, tiny.pitch, tiny.z, None, zern)
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, None, zern, eq6_phase=eq6)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"aberr={aberr} eq6={eq6} rel-L2 {err:.3e}")
+    assert err <= FP32_BAR
+
+
+def test_depth_first_zero_dispersion_and_chunking(gpu_lib, tiny):
+    """An all-zero dispersion array keeps the depth-first order; the number of bins per
+    chunk (frames-per-chunk tuning) changes no bit of the volume."""
+    from paper_2003_08960_amd.api import Plan
+    T, N = tiny.frames.shape[:2]
+    fr = torch.from_numpy(tiny.frames).cuda()
+    plan = Plan(T, N, precision="fp32_fft")
+    Vf = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()              # frame order
+    plan.set_tuning(plan.get_tuning()[:3] + [1])
+    V0 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()              # depth-first order
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
+    assert rel_l2(V0.cpu().numpy(), ref) <= FP32_BAR
+    assert rel_l2(Vf.cpu().numpy(), ref) <= FP32_BAR
+    assert not torch.equal(V0, Vf)                                          # two rounding orders
+    V1 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z, np.zeros(T)).clone()
+    assert torch.equal(V0, V1)
+    for F in (1, 2, 3, 7, T):
+        plan.set_tuning([F, 0, 0, 1])
+        assert torch.equal(plan.render(fr, tiny.lam, tiny.pitch, tiny.z), V0), F
+    Vd = plan.render(fr, tiny.lam, tiny.pitch, tiny.z, np.full(T, 0.5)).cpu().numpy()   # falls back to frame order
+    assert rel_l2(Vd, O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, np.full(T, 0.5))) <= FP32_BAR
+
+
+@pytest.mark.parametrize("T,N", [(256, 256), (128, 1024), (16, 2048)])
+def test_depth_first_large_frames(gpu_lib, T, N):
+    from paper_2003_08960_amd.api import Plan
+    frames, lam = random_case(T, N, seed=T + N)
+    print(f"\n[gpu] depth-first T={T} N={N}", flush=True)
+    plan = Plan(T, N, precision="fp32_fft")
+    plan.set_tuning(plan.get_tuning()[:3] + [1])
+    V = plan.render(torch.from_numpy(frames).cuda(), lam, 12e-6, 0.3)
+    pix = [(0, 0), (N // 2, N // 2), (N - 1, 3), (17, N - 5)]
+    ref = O.render_columns(frames, lam, 12e-6, 0.3, pix)
+    got = np.stack([V[:, u, v].cpu().numpy() for u, v in pix], axis=1)
+    err = rel_l2(got, ref)
+    print(f"T={T} N={N} sampled rel-L2 {err:.3e}")
+    assert err <= FP32_BAR

@@ -156,7 +156,7 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
     V0 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     cache = str(tmp_path / "tuning.json")
     choice = plan.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache)
-    assert 1 <= choice[0] <= T
+    assert 1 <= choice[0] <= T and len(choice) == 4
     V1 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     assert torch.equal(V0, V1)
     for tuning in ([1, 0, 0], [3, 7, 5], [T, 1024, 64]):
@@ -166,6 +166,8 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
     assert plan2.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache) == choice   # from the cache
     with pytest.raises(native.SsoctError):
         plan.set_tuning([0, 0, 0])
+    with pytest.raises(native.SsoctError):
+        plan.set_tuning([1, 0, 0, 2])
 
 
 def test_chunkwise_fresnel_with_ragged_chunks_and_discarded_sweep(gpu_lib, sweeps):
@@ -196,4 +198,28 @@ def test_chunkwise_fresnel_with_ragged_chunks_and_discarded_sweep(gpu_lib, sweep
     assert torch.equal(st.slot_volume(r["slot"]), refs[2][0])
     s = st.stats()
     assert s["dropped_sweeps"] == 1 and s["done"] == 2
+    st.close()
+
+
+def test_stream_with_fft_depth_form(gpu_lib, sweeps):
+    """The FFT form in the depth-first order streams through one whole-volume graph per slot."""
+    from paper_2003_08960_amd.api import Plan, Stream
+    plan = Plan(T, N, precision="fp32_fft")
+    plan.set_tuning(plan.get_tuning()[:3] + [1])
+    refs = [eager(plan, s) for s in sweeps[:3]]
+    sw = sweeps[0]
+    st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=2)
+    allframes = np.concatenate([s.frames for s in sweeps[:3]])
+    for j in range(0, allframes.shape[0], 9):
+        assert st.push_frames(np.ascontiguousarray(allframes[j:j + 9]), j) == native.OK
+        if st.stats()["in_flight"] >= 1:       # keep a slot free for the next sweep
+            r = st.pop(wait=True)
+            assert torch.equal(st.slot_volume(r["slot"]), refs[r["seq"]][0])
+    while True:
+        r = st.pop(wait=True)
+        if r is None:
+            break
+        assert torch.equal(st.slot_volume(r["slot"]), refs[r["seq"]][0])
+        assert np.array_equal(r["cut_xz"], refs[r["seq"]][1][1])
+    assert st.stats()["done"] == 3
     st.close()
