@@ -282,6 +282,98 @@ def bench_stream(sw, form, n_vol=16, slots=3, fps=512.0, chunk=16, paced=True):
     return out
 
 
+def bench_slide(sw, form, hop=13, windows=200, fps=512.0, paced_frames=768, paced=True):
+    """The paper's operating mode: a gate of T frames advanced by `hop` over a frame stream, every frame
+    transformed once into a ring of holograms, one depth transform + cuts per hop.  Output throughput =
+    windows x T N^2 voxels per second (the quantity of the paper's 10 Gvoxel/s)."""
+    import torch
+
+    from paper_2003_08960_amd import native
+    from paper_2003_08960_amd.api import Plan, Slide
+    T, N, _ = sw.frames.shape
+    plan = Plan(T, N, precision=form)
+    sl = Slide(plan, sw.lam, sw.pitch, sw.z, hop=hop, slots=3)
+    sl.ring().copy_(torch.from_numpy(sw.frames).cuda())    # device-resident: the sweep repeats
+    torch.cuda.synchronize()
+    seq = 0
+    assert sl.advance(T, 0) == native.OK                      # fill: first window
+    seq = T
+    while sl.pop(wait=True, cuts=False) is not None:
+        pass
+    for _ in range(5):                                        # warm-up windows
+        sl.advance(hop, seq)
+        seq += hop
+    while sl.pop(wait=True, cuts=False) is not None:
+        pass
+    done = 0
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(windows):
+        assert sl.advance(hop, seq) == native.OK
+        seq += hop
+        while True:
+            r = sl.pop(wait=False, cuts=False)
+            if r is None:
+                break
+            done += 1
+            lat.append(r["latency_ms"])
+    while True:
+        r = sl.pop(wait=True, cuts=False)
+        if r is None:
+            break
+        done += 1
+        lat.append(r["latency_ms"])
+    el = time.perf_counter() - t0
+    st = sl.stats()
+    out = {"form": form, "hop": hop, "T": T, "N": N,
+           "device_resident": {"windows": done, "dropped": st["dropped_windows"], "volumes_per_s": done / el,
+                               "output_gvoxel_s": done * T * N * N / el / 1e9,
+                               "input_frames_per_s": windows * hop / el,
+                               "ms_per_window": el * 1e3 / max(done, 1),
+                               "latency_ms_p50": pctl(lat, 50), "latency_ms_p99": pctl(lat, 99)}}
+    out["device_resident"]["vs_paper_output_throughput"] = out["device_resident"]["output_gvoxel_s"] / PAPER_GVOXEL_S
+    log(f"slide {form} hop {hop}: {out['device_resident']['volumes_per_s']:.0f} volumes/s, "
+        f"{out['device_resident']['output_gvoxel_s']:.1f} output Gvoxel/s")
+    sl.close()
+    if paced:
+        # host-fed at the camera rate, one hop of frames per push
+        sl = Slide(plan, sw.lam, sw.pitch, sw.z, hop=hop, slots=3)
+        pinned = torch.from_numpy(sw.frames).pin_memory()
+        lat = []
+        done = 0
+        t_start = time.perf_counter()
+        seq = 0
+        while seq < paced_frames:
+            n = min(hop, paced_frames - seq)
+            dt = t_start + seq / fps - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            pos = seq % T
+            if pos + n <= T:
+                sl.push(pinned[pos:pos + n], seq)
+            else:
+                sl.push(pinned[pos:], seq)
+                sl.push(pinned[:pos + n - T], seq + T - pos)
+            seq += n
+            while (r := sl.pop(wait=False, cuts=True)) is not None:
+                done += 1
+                lat.append(r["latency_ms"])
+        while (r := sl.pop(wait=True, cuts=True)) is not None:
+            done += 1
+            lat.append(r["latency_ms"])
+        el = time.perf_counter() - t_start
+        out["paced"] = {"fps": fps, "frames": paced_frames, "windows": done, "volumes_per_s": done / el,
+                        "latency_ms_p50": pctl(lat, 50), "latency_ms_p99": pctl(lat, 99),
+                        "dropped": sl.stats()["dropped_windows"]}
+        log(f"slide paced {fps:.0f} fps: {done} windows, latency p50 {out['paced']['latency_ms_p50']:.2f} ms, "
+            f"p99 {out['paced']['latency_ms_p99']:.2f} ms")
+        sl.close()
+        del pinned
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_backward(steps=10, warmup=3):
     """Loss sum |V|^4 and its gradient (z, 15 Zernike coefficients, T dispersion
     phases) on the aberrated T=128, N=512 workload: fused recompute-forward +
@@ -331,6 +423,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming form")
     ap.add_argument("--no-paced", action="store_true", help="skip the 512 frames/s paced stream (about 8 s)")
     ap.add_argument("--no-backward", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--no-slide", action="store_true", help="skip the sliding-window (hop 13) measurement")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch-shape tuner before timing each form (default: the plan's defaults; "
                          "the streaming form is always tuned)")
@@ -457,6 +550,9 @@ def main():
     if not args.no_stream:
         stream_form = "bf16_split" if "bf16_split" in forms else head
         out["streaming"] = bench_stream(sw, stream_form, paced=not args.no_paced)
+    if not args.no_slide:
+        out["sliding"] = bench_slide(sw, head if head in ("fp32", "fp32_fft") else "fp32_fft",
+                                     paced=not args.no_paced)
     if not args.no_backward:
         out["backward"] = bench_backward()
     if not args.no_cpu_baseline:

@@ -240,6 +240,56 @@ int ssoct_stream_stats(ssoct_stream* stream, uint64_t* counters);
 /* Wait for every volume in flight and release the stream. NULL is accepted. */
 int ssoct_stream_destroy(ssoct_stream* stream);
 
+/* ---------------------------------------------------------------- sliding windows
+ * The short-time Fourier transform of Eq. 7 over a continuous frame stream:
+ * a rectangular gate of T consecutive holograms advanced by `hop` frames
+ * (the paper's real-time mode: hop ~13 turns 512 frames/s into ~38 volumes
+ * per second).  Every frame is rescaled and Fresnel-transformed once into
+ * slot seq % T of a ring of holograms (sweep position seq % T selects
+ * lambda, disp_phase and the tables); the window starting at frame j is
+ * transformed from the ring with bin q multiplied by exp(+2 pi i q (j % T) / T),
+ * which makes it exactly the DFT of frames j .. j + T - 1 in time order.  A
+ * window is emitted every `hop` frames once T consecutive frames have
+ * arrived: depth transform, cuts and copy of the cuts to pinned host memory,
+ * into one of `slots` output volumes.  All work runs in order on one stream
+ * owned by the object.  Windows never span a gap in the frame sequence: a gap
+ * restarts the run (the call returns SSOCT_EDROPPED), and a window that finds
+ * every output volume still held is dropped and counted.  The plan's
+ * parameters are fixed while the object exists; the SSOCT_DEPTH_FFT form
+ * always uses the frame order here. */
+typedef struct ssoct_slide ssoct_slide;
+
+int ssoct_slide_create(ssoct_slide** slide, ssoct_plan* plan, const double* lambda, double pitch, double z,
+                       const double* disp_phase, const double* zernike, int hop, int slots, int x0, int y0, int q0);
+
+/* Host-fed frames [nframes][N][N] (pinned memory is copied asynchronously;
+ * keep the buffer unchanged until a later call has returned a window that
+ * contains them, or until ssoct_slide_destroy), sequence numbers first_seq,
+ * first_seq + 1, ... (non-decreasing across calls). */
+int ssoct_slide_push(ssoct_slide* slide, const uint16_t* host_frames, int nframes, uint64_t first_seq);
+
+/* Device-resident input: the frame ring [T][N][N] (frame seq at slot
+ * seq % T).  The caller writes frames there and then calls
+ * ssoct_slide_advance, ordering its writes before that call; a slot must not
+ * be rewritten while an earlier frame in it may still be unprocessed
+ * (synchronise with the windows it belongs to). */
+int ssoct_slide_ring(ssoct_slide* slide, uint16_t** device_ring);
+int ssoct_slide_advance(ssoct_slide* slide, int nframes, uint64_t first_seq);
+
+/* Oldest finished window: its first frame, output slot, cuts (host, N*N and
+ * 2 T*N floats, or NULL) and latency from the arrival of its last frame to
+ * completion.  wait = 0 returns SSOCT_EAGAIN when it is not finished; also
+ * SSOCT_EAGAIN when no window is in flight.  The slot's volume stays valid
+ * until a later window reuses it. */
+int ssoct_slide_pop(ssoct_slide* slide, int wait, uint64_t* window_start, int* slot, float* cut_xy, float* cut_xz,
+                    float* cut_yz, double* latency_ms);
+int ssoct_slide_volume(ssoct_slide* slide, int slot, const void** device_volume);
+
+/* counters[5]: windows done, windows dropped (no free output volume), frames
+ * transformed, run restarts (sequence gaps), windows in flight. */
+int ssoct_slide_stats(ssoct_slide* slide, uint64_t* counters);
+int ssoct_slide_destroy(ssoct_slide* slide);
+
 #ifdef __cplusplus
 }
 #endif

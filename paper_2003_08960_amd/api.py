@@ -316,3 +316,97 @@ class Stream:
             self.close()
         except Exception:
             pass
+
+
+class Slide:
+    """ssoct_slide: sliding-window depth transform (gate of T frames advanced by `hop`) over a frame stream."""
+
+    def __init__(self, plan: Plan, lam, pitch, z, disp_phase=None, zernike=None, hop: int = 13, slots: int = 2,
+                 x0: int | None = None, y0: int | None = None, q0: int | None = None):
+        self.plan, self.lib = plan, plan.lib
+        self.T, self.N = plan.T, plan.N
+        self.x0 = self.N // 2 if x0 is None else int(x0)
+        self.y0 = self.N // 2 if y0 is None else int(y0)
+        self.q0 = self.T // 4 if q0 is None else int(q0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            native.check(self.lib.ssoct_slide_create(
+                ctypes.byref(h), plan._h, native.host_doubles(lam, self.T), float(pitch), float(z),
+                native.host_doubles(disp_phase, self.T), native.host_doubles(zernike, 15), int(hop), int(slots),
+                self.x0, self.y0, self.q0))
+        self._h = h
+        self._keep = []   # (last frame, host buffer) until a finished window ends at or after that frame
+
+    def push(self, host_frames, first_seq: int) -> int:
+        """Frames [n, N, N] uint16 (numpy array or CPU tensor). Returns OK, or EDROPPED after a sequence gap."""
+        arr = host_frames
+        if isinstance(arr, torch.Tensor):
+            if arr.is_cuda or arr.dtype != torch.uint16 or not arr.is_contiguous():
+                raise ValueError("host_frames must be a contiguous CPU uint16 tensor")
+            ptr, n = arr.data_ptr(), arr.shape[0]
+        else:
+            import numpy as np
+            if arr.dtype != np.uint16 or not arr.flags["C_CONTIGUOUS"]:
+                raise ValueError("host_frames must be a C-contiguous uint16 array")
+            ptr, n = arr.ctypes.data, arr.shape[0]
+        if tuple(arr.shape[1:]) != (self.N, self.N):
+            raise ValueError("frame shape mismatch")
+        self._keep.append((int(first_seq) + n - 1, arr))
+        rc = self.lib.ssoct_slide_push(self._h, ctypes.c_void_p(ptr), int(n), ctypes.c_uint64(first_seq))
+        return rc if rc == native.EDROPPED else native.check(rc)
+
+    def ring(self) -> torch.Tensor:
+        """The device frame ring [T, N, N] uint16 (frame seq in slot seq % T)."""
+        ptr = ctypes.c_void_p()
+        native.check(self.lib.ssoct_slide_ring(self._h, ctypes.byref(ptr)))
+        return torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N), "<u2"), device=self.plan.device)
+
+    def advance(self, n: int, first_seq: int) -> int:
+        """Frames first_seq .. first_seq + n - 1 are in the ring: transform them (and emit windows)."""
+        rc = self.lib.ssoct_slide_advance(self._h, int(n), ctypes.c_uint64(first_seq))
+        return rc if rc == native.EDROPPED else native.check(rc)
+
+    def pop(self, wait: bool = True, cuts: bool = True):
+        """Oldest finished window as a dict (start, slot, latency_ms, cut_xy, cut_xz, cut_yz), or None."""
+        import numpy as np
+        start = ctypes.c_uint64()
+        slot = ctypes.c_int()
+        lat = ctypes.c_double()
+        xy = np.empty((self.N, self.N), np.float32) if cuts else None
+        xz = np.empty((self.T, self.N), np.float32) if cuts else None
+        yz = np.empty((self.T, self.N), np.float32) if cuts else None
+        ptr = (lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None)
+        rc = self.lib.ssoct_slide_pop(self._h, 1 if wait else 0, ctypes.byref(start), ctypes.byref(slot), ptr(xy),
+                                      ptr(xz), ptr(yz), ctypes.byref(lat))
+        if rc == native.EAGAIN:
+            return None
+        native.check(rc)
+        last = int(start.value) + self.T - 1
+        self._keep = [(v, a) for v, a in self._keep if v > last]
+        return {"start": int(start.value), "slot": int(slot.value), "latency_ms": float(lat.value),
+                "cut_xy": xy, "cut_xz": xz, "cut_yz": yz}
+
+    def volume(self, slot: int) -> torch.Tensor:
+        """Device complex volume of an output slot (a view, valid until the slot is reused)."""
+        ptr = ctypes.c_void_p()
+        native.check(self.lib.ssoct_slide_volume(self._h, int(slot), ctypes.byref(ptr)))
+        raw = torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N, 2), "<f4"), device=self.plan.device)
+        return torch.view_as_complex(raw)
+
+    def stats(self):
+        c = (ctypes.c_uint64 * 5)()
+        native.check(self.lib.ssoct_slide_stats(self._h, c))
+        return {"done": int(c[0]), "dropped_windows": int(c[1]), "frames": int(c[2]), "restarts": int(c[3]),
+                "in_flight": int(c[4])}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ssoct_slide_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

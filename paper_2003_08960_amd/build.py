@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["tables.hip", "stage_a.hip", "depth.hip", "depth_fft.hip", "misc.hip"]
-CPP_SOURCES = ["abi.cpp", "stream.cpp"]
+CPP_SOURCES = ["abi.cpp", "stream.cpp", "slide.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{os.path.join(ROOT, 'include')}"]
 # packed FP32 instructions are kept out of every kernel (build notes)

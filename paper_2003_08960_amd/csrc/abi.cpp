@@ -257,16 +257,16 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
   return SSOCT_OK;
 }
 
-int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void* vol) {
+int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void* vol, int shift) {
   const int prec = depth_prec(p->flags);
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
   if (p->flags & SSOCT_DEPTH_FFT) {
-    SSOCT_HIP(launch_depth_fft(p->T, p->N * p->N, +1, epi, reinterpret_cast<const float2*>(ws + L.H), p->dtw, vol,
-                               s));
+    SSOCT_HIP(launch_depth_fft(p->T, p->N * p->N, +1, epi, reinterpret_cast<const float2*>(ws + L.H), p->dtw, vol, s,
+                               shift));
     return SSOCT_OK;
   }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
-                         depth_grid_for(p), s));
+                         depth_grid_for(p), s, p->dtw, shift));
   return SSOCT_OK;
 }
 
@@ -435,8 +435,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   }
   if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
-  if (e == hipSuccess && (flags & SSOCT_DEPTH_FFT)) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
-  if (e == hipSuccess && (flags & SSOCT_DEPTH_FFT)) e = launch_depth_twiddles(T, p->dtw, stream);
+  if (e == hipSuccess) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
+  if (e == hipSuccess) e = launch_depth_twiddles(T, p->dtw, stream);
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");

@@ -60,7 +60,8 @@ template <int PREC, int KC, int WAVES, int DIR, int EPI>
 __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ in, const void* __restrict__ amat,
                                                       void* __restrict__ out, int T, int T_pad, int P, int slabs,
                                                       float out_scale, float gamma_scale,
-                                                      double* __restrict__ loss_partials) {
+                                                      double* __restrict__ loss_partials,
+                                                      const float2* __restrict__ wt, int shift) {
   using PT_ = PrecTraits<PREC>;
   constexpr int NA = PT_::F32 ? KC / 2 : (PT_::SPLIT ? KC / 2 : KC / 4);  // dwords of A per lane
   constexpr int PER_ROW = PT / 2;                                       // uint4 per tile row
@@ -210,9 +211,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
       for (int o = 0; o < 2; ++o) {
         const int q = o == 0 ? q1 : q2;
         if (q < 0) continue;
-        const float2 V = o == 0 ? v1 : v2;
+        float2 V = o == 0 ? v1 : v2;
         const size_t idx = (size_t)q * P + p;
         if constexpr (EPI == EPI_STORE) {
+          // window starting `shift` frames into the ring: bin q gains exp(+2 pi i q shift / T)
+          if (DIR > 0 && shift != 0) {
+            const float2 w = wt[(q * shift) % T];   // V conj(w)
+            V = make_float2(V.x * w.x + V.y * w.y, V.y * w.x - V.x * w.y);
+          }
           st_once<SSOCT_DEPTH_NT>(reinterpret_cast<float2*>(out) + idx, V);
         } else if constexpr (EPI == EPI_ABS) {
           st_once<SSOCT_DEPTH_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(V.x * V.x + V.y * V.y));
@@ -240,37 +246,38 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
 
 template <int PREC, int KC, int WAVES, int DIR, int EPI>
 static hipError_t depth_go(int grid, hipStream_t s, const void* in, const void* amat, void* out, int T, int T_pad,
-                           int P, int slabs, float out_scale, float gamma_scale, double* partials) {
+                           int P, int slabs, float out_scale, float gamma_scale, double* partials, const float2* wt,
+                           int shift) {
   hipLaunchKernelGGL((k_depth<PREC, KC, WAVES, DIR, EPI>), dim3(grid), dim3(WAVES * 64), 0, s,
                      reinterpret_cast<const uint2*>(in), amat, out, T, T_pad, P, slabs, out_scale, gamma_scale,
-                     partials);
+                     partials, wt, shift);
   return hipGetLastError();
 }
 
 template <int PREC, int KC, int WAVES>
 static hipError_t depth_dir_epi(int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
-                                void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part) {
+                                void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift) {
   if (dir > 0) {
-    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, +1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    if (epi == EPI_ABS) return depth_go<PREC, KC, WAVES, +1, EPI_ABS>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, +1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    if (epi == EPI_ABS) return depth_go<PREC, KC, WAVES, +1, EPI_ABS>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
     if constexpr (PREC == DP_F32)
-      return depth_go<PREC, KC, WAVES, +1, EPI_GAMMA>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+      return depth_go<PREC, KC, WAVES, +1, EPI_GAMMA>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
     return hipErrorInvalidValue;
   }
   if constexpr (PREC == DP_F32) {
-    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, -1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, -1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
   }
   return hipErrorInvalidValue;
 }
 
 template <int PREC, int KC>
 static hipError_t depth_waves(int waves, int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
-                              void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part) {
+                              void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift) {
   switch (waves) {
-    case 1: return depth_dir_epi<PREC, KC, 1>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 2: return depth_dir_epi<PREC, KC, 2>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 4: return depth_dir_epi<PREC, KC, 4>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 8: return depth_dir_epi<PREC, KC, 8>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 1: return depth_dir_epi<PREC, KC, 1>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 2: return depth_dir_epi<PREC, KC, 2>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 4: return depth_dir_epi<PREC, KC, 4>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 8: return depth_dir_epi<PREC, KC, 8>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
     default: return hipErrorInvalidValue;
   }
 }
@@ -278,12 +285,12 @@ static hipError_t depth_waves(int waves, int dir, int epi, int grid, hipStream_t
 template <int PREC>
 static hipError_t depth_kc(int KC, int waves, int dir, int epi, int grid, hipStream_t s, const void* in,
                            const void* amat, void* out, int T, int T_pad, int P, int slabs, float os, float gs,
-                           double* part) {
+                           double* part, const float2* wt, int shift) {
   switch (KC) {
-    case 32: return depth_waves<PREC, 32>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 64: return depth_waves<PREC, 64>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 128: return depth_waves<PREC, 128>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
-    case 256: return depth_waves<PREC, 256>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part);
+    case 32: return depth_waves<PREC, 32>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 64: return depth_waves<PREC, 64>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 128: return depth_waves<PREC, 128>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 256: return depth_waves<PREC, 256>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
     default: return hipErrorInvalidValue;
   }
 }
@@ -298,16 +305,18 @@ int depth_grid(int T, int P, int cu_count) {
 }
 
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat, void* out,
-                        int sigma, int gamma_exp, double* partials, int grid, hipStream_t s) {
+                        int sigma, int gamma_exp, double* partials, int grid, hipStream_t s, const float2* wt,
+                        int shift) {
+  if (shift != 0 && !wt) return hipErrorInvalidValue;
   DepthLayout L = depth_layout(T);
   const float os = ldexpf(1.0f, sigma);
   const float gs = ldexpf(1.0f, -gamma_exp);
   switch (prec) {
-    case DP_F32: return depth_kc<DP_F32>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
-    case DP_F16: return depth_kc<DP_F16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
-    case DP_BF16: return depth_kc<DP_BF16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
-    case DP_F16_SPLIT: return depth_kc<DP_F16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
-    case DP_BF16_SPLIT: return depth_kc<DP_BF16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials);
+    case DP_F32: return depth_kc<DP_F32>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
+    case DP_F16: return depth_kc<DP_F16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
+    case DP_BF16: return depth_kc<DP_BF16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
+    case DP_F16_SPLIT: return depth_kc<DP_F16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
+    case DP_BF16_SPLIT: return depth_kc<DP_BF16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
     default: return hipErrorInvalidValue;
   }
 }

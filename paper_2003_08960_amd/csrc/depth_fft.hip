@@ -19,13 +19,16 @@ namespace ssoct {
 #ifndef SSOCT_DFFT_PX
 #define SSOCT_DFFT_PX 32         // pixels per workgroup (threads = 16 PX)
 #endif
+#ifndef SSOCT_XCDS
+#define SSOCT_XCDS 8             // accelerator complex dies of an MI355X (one L2 each)
+#endif
 #ifndef SSOCT_DFFT_NT
 #define SSOCT_DFFT_NT 1          // non-temporal loads of H and stores of the volume (both touched once)
 #endif
 
 template <int T2, int DIR, int EPI, int PX>
 __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict__ H, const float2* __restrict__ wt,
-                                                        void* __restrict__ out, int P) {
+                                                        void* __restrict__ out, int P, int shift) {
   constexpr int T = 16 * T2;
   constexpr int ED = -DIR;           // engine sign: forward depth DFT has exponent -2 pi i q t / T
   __shared__ float2 lds[T * PX];     // [q2][t1][px]
@@ -59,6 +62,8 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
     const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
     if constexpr (EPI == EPI_ABS)
       st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
+    else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
+      st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
     else
       st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
   }
@@ -151,7 +156,13 @@ __global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restr
   uint32_t* foot = reinterpret_cast<uint32_t*>(lds);   // [T][2][WD]
   const int px = threadIdx.x % PX, r = threadIdx.x / PX;
   const size_t P = (size_t)N * N;
-  const int pix0 = blockIdx.x * PX;
+  // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so that neighbouring strips and rows, which share
+  // source rows, meet in one L2
+  const int tile = (gridDim.x % SSOCT_XCDS == 0)
+                       ? (blockIdx.x % SSOCT_XCDS) * (gridDim.x / SSOCT_XCDS) + blockIdx.x / SSOCT_XCDS
+                       : blockIdx.x;
+  const int pix0 = tile * PX;
   const int m = pix0 >> logN, n0 = pix0 & (N - 1);
   const int half = N >> 1;
   const int c0 = ((n0 + half) & (N - 1)) - half;   // centred index of the first column (same half as the tile)
@@ -258,20 +269,21 @@ hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTa
 }
 
 template <int T2, int DIR, int EPI>
-static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, hipStream_t s) {
+static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, int shift, hipStream_t s) {
   constexpr int PX = SSOCT_DFFT_PX;
-  hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3((P + PX - 1) / PX), dim3(16 * PX), 0, s, H, wt, out, P);
+  hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3((P + PX - 1) / PX), dim3(16 * PX), 0, s, H, wt, out, P,
+                     shift);
   return hipGetLastError();
 }
 
 template <int DIR, int EPI>
-static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, hipStream_t s) {
+static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, int shift, hipStream_t s) {
   switch (T) {
-    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, s);
-    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, s);
-    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, s);
-    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, s);
-    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, s);
+    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, s);
+    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, s);
+    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, s);
+    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, s);
+    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -279,14 +291,14 @@ static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, v
 bool depth_fft_supported(int T) { return T == 16 || T == 32 || T == 64 || T == 128 || T == 256; }
 
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s) {
+                            hipStream_t s, int shift) {
   if (P <= 0) return hipSuccess;
   if (dir > 0) {
-    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, s);
-    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, s);
+    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, s);
+    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, s);
   }
   if (epi != EPI_STORE) return hipErrorInvalidValue;
-  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, s);
+  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, s);
 }
 
 // wt[k] = exp(-2 pi i k / T), k = 0..T-1, from FP64 (sincospi) rounded to FP32

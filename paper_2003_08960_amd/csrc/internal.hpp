@@ -115,16 +115,18 @@ int row_adj_blocks(int N);
 
 // Depth transform over the whole stack: out[q][p] = sum_t W[q][t] in[t][p]
 // (dir = +1) or sum_t conj(W[q][t]) in[t][p] (dir = -1).
+// shift > 0 (forward, EPI_STORE): the stack is a ring whose window starts at
+// slot `shift`; bin q is multiplied by exp(+2 pi i q shift / T) = conj(wt[q shift mod T]).
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat,
                         void* out, int sigma, int gamma_exp, double* partials, int grid,
-                        hipStream_t s);
+                        hipStream_t s, const float2* wt = nullptr, int shift = 0);
 int depth_grid(int T, int P, int cu_count);
 
 // Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).
 // epi: EPI_STORE (complex64) or EPI_ABS (forward only).  wt: exp(-2 pi i k/T).
 bool depth_fft_supported(int T);
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s);
+                            hipStream_t s, int shift = 0);
 hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,

@@ -48,7 +48,7 @@ struct ssoct_plan {
   float* a_f32 = nullptr;
   uint4* a_f16 = nullptr;
   uint4* a_bf16 = nullptr;
-  float2* dtw = nullptr;       // exp(-2 pi i k / T), SSOCT_DEPTH_FFT
+  float2* dtw = nullptr;       // exp(-2 pi i k / T): FFT depth twiddles and window phase
   double zmat[15][ssoct::N_MONO];
   std::vector<double> cache;   // parameter set the tables were last built from
   bool have_aberr = false;
@@ -86,7 +86,9 @@ int render_core(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char*
 // H stack into vol.
 int render_chunk(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, int t0,
                  int Fc);
-int render_depth(ssoct_plan* p, hipStream_t stream, char* ws, const WsLayout& L, void* vol);
+// shift: the stack is a ring of frames by sweep position and the window
+// starts at slot `shift` (bin q gains exp(+2 pi i q shift / T)); 0 otherwise
+int render_depth(ssoct_plan* p, hipStream_t stream, char* ws, const WsLayout& L, void* vol, int shift = 0);
 // Fresnel-stage launches per render (chunks of frames, or of bins in the depth-first order)
 int fresnel_chunks(const ssoct_plan* p);
 

@@ -42,7 +42,8 @@ EXPORTS = (
     "ssoct_backward_sharpness", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
     "ssoct_plan_set_tuning", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
     "ssoct_stream_submit", "ssoct_stream_pop", "ssoct_stream_slot_volume", "ssoct_stream_stats",
-    "ssoct_stream_destroy",
+    "ssoct_stream_destroy", "ssoct_slide_create", "ssoct_slide_push", "ssoct_slide_ring", "ssoct_slide_advance",
+    "ssoct_slide_pop", "ssoct_slide_volume", "ssoct_slide_stats", "ssoct_slide_destroy",
 )
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EHIP: "EHIP", ENOMEM: "ENOMEM", EALIAS: "EALIAS",
@@ -115,6 +116,24 @@ def _declare(lib):
     lib.ssoct_stream_stats.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_uint64)]
     lib.ssoct_stream_destroy.restype = c_int
     lib.ssoct_stream_destroy.argtypes = [c_void_p]
+    lib.ssoct_slide_create.restype = c_int
+    lib.ssoct_slide_create.argtypes = [ctypes.POINTER(c_void_p), c_void_p, _dptr, c_double, c_double, _dptr, _dptr,
+                                       c_int, c_int, c_int, c_int, c_int]
+    lib.ssoct_slide_push.restype = c_int
+    lib.ssoct_slide_push.argtypes = [c_void_p, c_void_p, c_int, ctypes.c_uint64]
+    lib.ssoct_slide_ring.restype = c_int
+    lib.ssoct_slide_ring.argtypes = [c_void_p, ctypes.POINTER(c_void_p)]
+    lib.ssoct_slide_advance.restype = c_int
+    lib.ssoct_slide_advance.argtypes = [c_void_p, c_int, ctypes.c_uint64]
+    lib.ssoct_slide_pop.restype = c_int
+    lib.ssoct_slide_pop.argtypes = [c_void_p, c_int, ctypes.POINTER(ctypes.c_uint64), _iptr, c_void_p, c_void_p,
+                                    c_void_p, _dptr]
+    lib.ssoct_slide_volume.restype = c_int
+    lib.ssoct_slide_volume.argtypes = [c_void_p, c_int, ctypes.POINTER(c_void_p)]
+    lib.ssoct_slide_stats.restype = c_int
+    lib.ssoct_slide_stats.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ssoct_slide_destroy.restype = c_int
+    lib.ssoct_slide_destroy.argtypes = [c_void_p]
     return lib
 
 

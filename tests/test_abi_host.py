@@ -118,3 +118,21 @@ def test_stream_and_tuning_entry_points_reject_null(lib):
     assert lib.ssoct_plan_get_tuning(None, t) == native.EINVAL
     assert lib.ssoct_plan_set_tuning(None, t) == native.EINVAL
     assert lib.ssoct_plan_tune(None, None, lam, 1e-5, 0.1, None, None, None, 0, None, t) == native.EINVAL
+
+
+def test_slide_entry_points_reject_null(lib):
+    from paper_2003_08960_amd import native
+    lam = (ctypes.c_double * 4)(1e-6, 1e-6, 1e-6, 1e-6)
+    h = ctypes.c_void_p(7)
+    assert lib.ssoct_slide_create(ctypes.byref(h), None, lam, 1e-5, 0.1, None, None, 1, 1, 0, 0, 0) == native.EINVAL
+    assert not h.value
+    assert lib.ssoct_slide_create(None, None, lam, 1e-5, 0.1, None, None, 1, 1, 0, 0, 0) == native.EINVAL
+    assert lib.ssoct_slide_push(None, None, 1, 0) == native.EINVAL
+    ptr = ctypes.c_void_p()
+    assert lib.ssoct_slide_ring(None, ctypes.byref(ptr)) == native.EINVAL
+    assert lib.ssoct_slide_advance(None, 1, 0) == native.EINVAL
+    assert lib.ssoct_slide_pop(None, 1, None, None, None, None, None, None) == native.EINVAL
+    assert lib.ssoct_slide_volume(None, 0, ctypes.byref(ptr)) == native.EINVAL
+    c = (ctypes.c_uint64 * 5)()
+    assert lib.ssoct_slide_stats(None, c) == native.EINVAL
+    assert lib.ssoct_slide_destroy(None) == native.OK
