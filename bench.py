@@ -303,20 +303,18 @@ def bench_slide(sw, form, hop=13, windows=200, fps=512.0, paced_frames=768, pace
     for _ in range(5):                                        # warm-up windows
         sl.advance(hop, seq)
         seq += hop
-    while sl.pop(wait=True, cuts=False) is not None:
-        pass
+        while sl.pop(wait=True, cuts=False) is not None:
+            pass
     done = 0
     lat = []
     t0 = time.perf_counter()
     for _ in range(windows):
-        assert sl.advance(hop, seq) == native.OK
-        seq += hop
-        while True:
-            r = sl.pop(wait=False, cuts=False)
-            if r is None:
-                break
+        while sl.stats()["in_flight"] >= 3:                   # keep an output volume free (back-pressure)
+            r = sl.pop(wait=True, cuts=False)
             done += 1
             lat.append(r["latency_ms"])
+        assert sl.advance(hop, seq) == native.OK
+        seq += hop
     while True:
         r = sl.pop(wait=True, cuts=False)
         if r is None:
