@@ -46,6 +46,14 @@ Readings of points the paper leaves open (each one also listed in the design doc):
     only as a motivation); they parameterise the sharpness gradient.
   * Cuts are |V| (caption of Fig. 3); ``power=True`` gives |V|^2 (text after
     Eq. 7).
+  * Gate and sweep linearity.  The paper's gate g is rectangular and its
+    laser is swept linearly in wavenumber (setup paragraph; Eq. 7).  Two
+    generalisations are offered: ``gate`` (real weights g_t on h_t before the
+    depth transform, an apodised gate) and ``nonuniform_k`` (the depth
+    transform evaluated at the uniform depth grid of a sweep whose k_t is
+    not linear in t: V[q] = sum_t h_t exp(-2 pi i q kappa_t / T) with
+    kappa_t = (k_t - k_0) / dk, dk = (k_{T-1} - k_0) / (T - 1), which is t
+    for a k-linear sweep).
 """
 from __future__ import annotations
 
@@ -257,6 +265,29 @@ def depth_dft(h: np.ndarray) -> np.ndarray:
     return np.fft.fft(h, axis=0)
 
 
+def wavenumber_positions(lam) -> np.ndarray:
+    """kappa_t = (k_t - k_0) / dk with k = 2 pi / lambda and dk the mean step
+    (k_{T-1} - k_0) / (T - 1): the sweep position in units of the mean
+    wavenumber step (equal to t for a sweep linear in k, setup paragraph)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    T = lam.shape[0]
+    if T == 1:
+        return np.zeros(1)
+    k = 2.0 * np.pi / lam
+    dk = (k[-1] - k[0]) / (T - 1)
+    return (k - k[0]) / dk
+
+
+def depth_nudft(h: np.ndarray, kappa) -> np.ndarray:
+    """V[q] = sum_t h_t exp(-2 pi i q kappa_t / T): Eq. 7 evaluated at the
+    uniform depth grid for sweep positions kappa_t (a matrix product)."""
+    T = h.shape[0]
+    kappa = np.asarray(kappa, dtype=np.float64)
+    cyc = np.mod(np.outer(np.arange(T), kappa), T) / T
+    W = np.exp(-2j * np.pi * cyc)
+    return np.tensordot(W, h, axes=(1, 0))
+
+
 def depth_dft_adjoint(G: np.ndarray) -> np.ndarray:
     """beta_t = sum_q G_q exp(+2 pi i q t / T)."""
     return G.shape[0] * np.fft.ifft(G, axis=0)
@@ -289,23 +320,24 @@ def sensor_fields(frames, lam, pitch, z, zernike_coeffs=None, exact_chirp=False)
 
 
 def render(frames, lam, pitch, z, disp_phase=None, zernike_coeffs=None,
-           exact_chirp=False, eq6_phase=False) -> np.ndarray:
+           exact_chirp=False, eq6_phase=False, gate=None, nonuniform_k=False) -> np.ndarray:
     """Complex volume V[q, u, v] (complex128) of one sweep of T frames."""
     frames, lam = _check(frames, lam)
     T, N, _ = frames.shape
     phi = np.zeros(T) if disp_phase is None else np.asarray(disp_phase, dtype=np.float64)
+    g = np.ones(T) if gate is None else np.asarray(gate, dtype=np.float64)
     out = np.empty((T, N, N), dtype=np.complex128)
     fac = eq6_output_factor(N, reference_wavelength(lam), pitch, z) if eq6_phase else None
     for t, x in sensor_fields(frames, lam, pitch, z, zernike_coeffs, exact_chirp):
         h = fresnel_fft(x)
         if fac is not None:
             h = h * fac
-        out[t] = np.exp(1j * phi[t]) * h
-    return depth_dft(out)
+        out[t] = g[t] * np.exp(1j * phi[t]) * h
+    return depth_nudft(out, wavenumber_positions(lam)) if nonuniform_k else depth_dft(out)
 
 
 def render_columns(frames, lam, pitch, z, pixels, disp_phase=None, zernike_coeffs=None,
-                   exact_chirp=False, eq6_phase=False) -> np.ndarray:
+                   exact_chirp=False, eq6_phase=False, gate=None, nonuniform_k=False) -> np.ndarray:
     """V[:, u, v] for each (u, v) in ``pixels``, by direct evaluation of the sums.
 
     Returns complex128 [T, P].  The Fresnel sum of Eq. 6 and the depth sum of
@@ -328,9 +360,12 @@ def render_columns(frames, lam, pitch, z, pixels, disp_phase=None, zernike_coeff
     h = np.empty((T, pix.shape[0]), dtype=np.complex128)
     for t, x in sensor_fields(frames, lam, pitch, z, zernike_coeffs, exact_chirp):
         xv = x @ Ev.T                                   # [N(m), P]
-        h[t] = np.exp(1j * phi[t]) * fac * np.sum(Eu * xv.T, axis=1)
+        h[t] = (1.0 if gate is None else float(gate[t])) * np.exp(1j * phi[t]) * fac * np.sum(Eu * xv.T, axis=1)
     tt = np.arange(T)
-    W = np.exp(-2j * np.pi * (np.mod(np.outer(tt, tt), T) / T))  # W[q, t]
+    if nonuniform_k:
+        W = np.exp(-2j * np.pi * (np.mod(np.outer(tt, wavenumber_positions(lam)), T) / T))
+    else:
+        W = np.exp(-2j * np.pi * (np.mod(np.outer(tt, tt), T) / T))  # W[q, t]
     return W @ h
 
 

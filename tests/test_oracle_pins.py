@@ -393,6 +393,106 @@ def test_gradient_invariants():
 
 
 # --------------------------------------------------------------------------
+# Apodised gate and sweeps that are not linear in k (extensions of Eq. 7)
+# --------------------------------------------------------------------------
+
+def chirped_wavelengths(T, lam_max=870e-9, lam_min=800e-9, bend=0.15):
+    """A sweep whose wavenumber is a quadratic, not linear, function of t."""
+    u = np.linspace(0.0, 1.0, T)
+    k0, k1 = 2 * np.pi / lam_max, 2 * np.pi / lam_min
+    return 2 * np.pi / (k0 + (k1 - k0) * (u + bend * u * (u - 1.0)))
+
+
+def check_wavenumber_positions():
+    # k = 2 pi (1, 2, 4): mean step 3 pi, so kappa = (0, 2/3, 2) exactly
+    kap = O.wavenumber_positions([1.0, 0.5, 0.25])
+    assert np.allclose(kap, [0.0, 2.0 / 3.0, 2.0], rtol=0, atol=1e-14)
+    lam = synth.sweep_wavelengths(37, 870e-9, 800e-9)          # linear in k
+    assert np.allclose(O.wavenumber_positions(lam), np.arange(37), rtol=0, atol=1e-9)
+
+
+def check_nudft_tone():
+    T = 48
+    kap = O.wavenumber_positions(chirped_wavelengths(T))
+    assert not np.allclose(kap, np.arange(T), atol=0.5)       # really non-uniform
+    for qm in (0, 5, 17, 40):
+        h = np.exp(2j * np.pi * qm * kap / T)[:, None]
+        V = O.depth_nudft(h, kap)
+        assert abs(V[qm, 0] - T) < 1e-9 * T
+    h = np.random.default_rng(1).standard_normal((T, 3)) + 1j
+    assert np.allclose(O.depth_nudft(h, np.arange(T)), np.fft.fft(h, axis=0), atol=1e-10)
+
+
+def check_chirped_scatterer_focus():
+    """Field of a reflector at depth delta: h_t = exp(i 2 k_t delta).  On the uniform depth grid
+    delta_q = q pi / (T dk) the non-uniform transform puts exactly T in bin q_m; the plain DFT,
+    which assumes k linear in t, spreads it."""
+    T = 64
+    lam = chirped_wavelengths(T)
+    k = 2 * np.pi / lam
+    dk = (k[-1] - k[0]) / (T - 1)
+    qm = 13
+    delta = qm * np.pi / (T * dk)
+    h = np.exp(1j * 2 * (k - k[0]) * delta)[:, None]
+    V = O.depth_nudft(h, O.wavenumber_positions(lam))
+    assert abs(abs(V[qm, 0]) - T) < 1e-8 * T
+    assert np.argmax(np.abs(V[:, 0])) == qm
+    assert abs(O.depth_dft(h)[qm, 0]) < 0.9 * T
+
+
+def check_hann_gate():
+    """Frames F0 U + a cos(2 pi q_m t / T) P at one wavelength: with the periodic Hann gate
+    sin^2(pi t / T) the tone's bin halves and its neighbours take exactly -1/2 of it."""
+    T, N, qm = 32, 16, 6
+    rng = np.random.default_rng(4)
+    U = np.ones((N, N))
+    Pm = rng.uniform(0.0, 1.0, (N, N))
+    t = np.arange(T)
+    frames = 1000.0 * U[None] + 300.0 * np.cos(2 * np.pi * qm * t / T)[:, None, None] * Pm[None]
+    lam = np.full(T, 850e-9)
+    g = np.sin(np.pi * t / T) ** 2
+    Vr = O.render(frames, lam, 20e-6, 0.05)
+    Vh = O.render(frames, lam, 20e-6, 0.05, gate=g)
+    scale = np.abs(Vr[qm]).max()
+    assert np.allclose(Vh[qm], 0.5 * Vr[qm], atol=1e-9 * scale)
+    assert np.allclose(Vh[qm + 1], -0.25 * Vr[qm], atol=1e-9 * scale)
+    assert np.allclose(Vh[qm - 1], -0.25 * Vr[qm], atol=1e-9 * scale)
+    assert np.abs(Vh[qm + 3]).max() < 1e-9 * scale
+
+
+def test_wavenumber_positions():
+    check_wavenumber_positions()
+
+
+def test_nudft_tone():
+    check_nudft_tone()
+
+
+def test_chirped_scatterer_focus():
+    check_chirped_scatterer_focus()
+
+
+def test_hann_gate():
+    check_hann_gate()
+
+
+def test_render_extensions_reduce_to_the_paper_form():
+    """nonuniform_k on a k-linear sweep and a unit gate change nothing; direct sums agree."""
+    sw = synth.make_config("tiny")
+    V = O.render(sw.frames, sw.lam, sw.pitch, sw.z)
+    assert np.allclose(O.render(sw.frames, sw.lam, sw.pitch, sw.z, nonuniform_k=True), V,
+                       atol=1e-9 * np.abs(V).max())
+    assert np.array_equal(O.render(sw.frames, sw.lam, sw.pitch, sw.z, gate=np.ones(len(sw.lam))), V)
+    lam = chirped_wavelengths(len(sw.lam))
+    g = np.hanning(len(lam))
+    Vn = O.render(sw.frames, lam, sw.pitch, sw.z, gate=g, nonuniform_k=True)
+    pix = [(3, 5), (64, 64), (100, 20)]
+    cols = O.render_columns(sw.frames, lam, sw.pitch, sw.z, pix, gate=g, nonuniform_k=True)
+    for i, (u, v) in enumerate(pix):
+        assert np.allclose(cols[:, i], Vn[:, u, v], atol=1e-8 * np.abs(Vn).max())
+
+
+# --------------------------------------------------------------------------
 # Planted mistakes: each plausible error in the oracle must fail a pin
 # --------------------------------------------------------------------------
 
@@ -410,6 +510,17 @@ def _plants():
         check_point_source_focus
     yield "axial range halved", "axial_range", lambda orig: (lambda a, b, n: orig(a, b, n) / 2), \
         check_printed_axial
+    yield "kappa from lambda", "wavenumber_positions", lambda orig: (
+        lambda lam: (np.asarray(lam, float) - lam[0]) / ((lam[-1] - lam[0]) / (len(lam) - 1))), \
+        check_wavenumber_positions
+    yield "kappa from lambda (physics)", "wavenumber_positions", lambda orig: (
+        lambda lam: (np.asarray(lam, float) - lam[0]) / ((lam[-1] - lam[0]) / (len(lam) - 1))), \
+        check_chirped_scatterer_focus
+    yield "nudft sign", "depth_nudft", lambda orig: (lambda h, kap: np.conj(orig(np.conj(h), kap))), check_nudft_tone
+    yield "gate ignored", "render", lambda orig: (lambda *a, gate=None, **k: orig(*a, **k)), check_hann_gate
+    yield "gate squared", "render", lambda orig: (
+        lambda *a, gate=None, **k: orig(*a, gate=None if gate is None else np.asarray(gate) ** 2, **k)), \
+        check_hann_gate
 
 
 def _shifted_positions(N, s):
