@@ -75,6 +75,8 @@ extern "C" {
 #define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
 #define SSOCT_PROFILE_KERNELS 512u /* with SSOCT_PROFILE: an event after every Fresnel-stage launch too
                                       (each adds a few microseconds to the render) */
+#define SSOCT_NONUNIFORM_K 2048u  /* depth transform exp(-2 pi i q kappa_t / T), kappa_t = (k_t - k_0)/dk from lambda:
+                                      the uniform depth grid of a sweep not linear in k (dense forms only) */
 #define SSOCT_DEPTH_FFT 1024u     /* FP32 depth transform as a radix FFT along the sweep (T in {16..256},
                                       powers of two) instead of the dense DFT-matrix product */
 
@@ -145,6 +147,12 @@ int ssoct_backward(ssoct_plan* plan, const uint16_t* frames, const double* lambd
 int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch,
                              double z, const double* disp_phase, const double* zernike, void* workspace,
                              size_t workspace_bytes, double* grad_out);
+
+/* Apodising gate g_t (host [T] real weights, or NULL for the rectangular gate
+ * of Eq. 7): h_t is multiplied by g_t before the depth transform.  Kept in
+ * the plan until changed; fails while a stream or sliding window uses the
+ * plan.  Not available for the gradient entry points or sliding windows. */
+int ssoct_plan_set_gate(ssoct_plan* plan, const double* gate);
 
 /* With SSOCT_PROFILE every ssoct_render records HIP events on the plan's
  * stream around its stages (and, with SSOCT_PROFILE_KERNELS, after every

@@ -34,6 +34,7 @@ class Plan:
 
     def __init__(self, T: int, N: int, precision: str = "fp32", exact_chirp: bool = False,
                  eq6_phase: bool = False, write_abs: bool = False, cut_power: bool = False,
+                 nonuniform_k: bool = False,
                  backward: bool = False, profile: bool = False, device=None):
         self.lib = native.load()
         self.T, self.N = int(T), int(N)
@@ -42,6 +43,7 @@ class Plan:
         flags |= native.CHIRP_EXACT if exact_chirp else 0
         flags |= native.EQ6_PHASE if eq6_phase else 0
         flags |= native.WRITE_ABS if write_abs else 0
+        flags |= native.NONUNIFORM_K if nonuniform_k else 0
         flags |= native.CUT_POWER if cut_power else 0
         flags |= native.BACKWARD if backward else 0
         flags |= native.PROFILE if profile else 0
@@ -137,6 +139,10 @@ class Plan:
             native.host_doubles(disp_phase, T), native.host_doubles(zernike, 15),
             ctypes.c_void_p(_ptr(self.workspace)), self.workspace.numel(), ctypes.c_void_p(_ptr(out))))
         return out
+
+    def set_gate(self, gate=None):
+        """Apodising gate g_t (T real weights) applied before the depth transform; None: rectangular."""
+        native.check(self.lib.ssoct_plan_set_gate(self._h, native.host_doubles(gate, self.T)))
 
     def profile_read(self):
         """Mean times (ms) per render since the last read: (tables, Fresnel stage, depth transform,

@@ -120,6 +120,7 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->a_f16);
   (void)hipFree(p->a_bf16);
   (void)hipFree(p->dtw);
+  (void)hipFree(p->kappa);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->kev)
@@ -179,6 +180,8 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   if (zern && !finite_all(zern, 15)) return fail(SSOCT_EINVAL, "zernike has a non-finite entry");
   if (for_backward && (p->flags & SSOCT_EQ6_PHASE))
     return fail(SSOCT_EUNSUPPORTED, "gradients are not available with SSOCT_EQ6_PHASE");
+  if (for_backward && (p->general || !p->gate.empty()))
+    return fail(SSOCT_EUNSUPPORTED, "gradients are not available with a gate or SSOCT_NONUNIFORM_K");
 
   double lam1 = lambda[0];
   for (int t = 1; t < T; ++t) lam1 = lambda[t] > lam1 ? lambda[t] : lam1;
@@ -193,6 +196,8 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   if (disp) key.insert(key.end(), disp, disp + T);
   key.push_back(zern ? 1.0 : 0.0);
   if (zern) key.insert(key.end(), zern, zern + 15);
+  key.push_back((double)p->gate.size());
+  key.insert(key.end(), p->gate.begin(), p->gate.end());
   if (key == p->cache) return status;
   if (p->streaming) return fail(SSOCT_EINVAL, "the plan's parameters are fixed while a stream uses it");
 
@@ -208,7 +213,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     pf[0] = s;
     pf[1] = kappa;
     pf[2] = (disp ? disp[t] / two_pi : 0.0) + eq6_cyc;
-    pf[3] = eq6 ? pitch * pitch / (lam1 * z) : 1.0;
+    pf[3] = (eq6 ? pitch * pitch / (lam1 * z) : 1.0) * (p->gate.empty() ? 1.0 : p->gate[t]);   // gate g_t
     h[ParamLayout::count(T) + t] = two_pi * kappa / z;  // alpha_t / z
   }
   double* g = &h[ParamLayout::globals(T)];
@@ -225,12 +230,24 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   if (zern && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
+  if (p->general) {
+    // kappa_t = (k_t - k_0) / dk, dk = (k_{T-1} - k_0) / (T - 1): sweep position in mean wavenumber steps
+    std::vector<double> kap(T, 0.0);
+    if (T > 1) {
+      const double two_pi_ = 6.283185307179586476925;
+      const double k0 = two_pi_ / lambda[0], dk = (two_pi_ / lambda[T - 1] - k0) / (double)(T - 1);
+      if (!(dk != 0.0) || !std::isfinite(dk)) return fail(SSOCT_EINVAL, "SSOCT_NONUNIFORM_K needs lambda_0 != lambda_{T-1}");
+      for (int t = 0; t < T; ++t) kap[t] = (two_pi_ / lambda[t] - k0) / dk;
+    }
+    SSOCT_HIP(hipMemcpyAsync(p->kappa, kap.data(), (size_t)T * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    SSOCT_HIP(launch_depth_tables(T, p->kappa, p->a_f32, p->a_f16, p->a_bf16, p->stream));
+  }
   SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern ? p->aberr : nullptr, p->stream));
   p->have_aberr = zern != nullptr;
   // depth-first order: the chirp and the per-frame row factor must not depend on the frame
   bool no_disp = true;
   for (int t = 0; disp && t < T; ++t) no_disp = no_disp && disp[t] == 0.0;
-  p->df_allowed = (p->flags & SSOCT_DEPTH_FFT) && !exact && !(p->flags & SSOCT_WRITE_ABS) && no_disp;
+  p->df_allowed = (p->flags & SSOCT_DEPTH_FFT) && !exact && !(p->flags & SSOCT_WRITE_ABS) && no_disp && p->gate.empty();
   // FP16 operands: |H| <= N^2 * 65535 * amplitude, kept below 2^15 by an exact power-of-two scale
   p->sigma = 0;
   if (h_format(depth_prec(p->flags)) == HF_F16) {
@@ -244,7 +261,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
 // Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
 // row DFT) into the chunk buffer, then column DFT into H.
 static int depth_grid_for(const ssoct_plan* p) {
-  return p->depth_grid > 0 ? p->depth_grid : depth_grid(p->T, p->N * p->N, p->cu);
+  return p->depth_grid > 0 ? p->depth_grid : depth_grid(p->T, p->N * p->N, p->cu, p->general);
 }
 
 int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, int t0, int Fc) {
@@ -266,7 +283,7 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
     return SSOCT_OK;
   }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
-                         depth_grid_for(p), s, p->dtw, shift));
+                         depth_grid_for(p), s, p->dtw, shift, p->general));
   return SSOCT_OK;
 }
 
@@ -399,6 +416,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
     return fail(SSOCT_EINVAL, "SSOCT_SPLIT needs SSOCT_PREC_FP16 or SSOCT_PREC_BF16");
   if ((flags & SSOCT_DEPTH_FFT) && (flags & (SSOCT_PREC_MASK | SSOCT_SPLIT)))
     return fail(SSOCT_EINVAL, "SSOCT_DEPTH_FFT is an FP32 form");
+  if ((flags & SSOCT_DEPTH_FFT) && (flags & SSOCT_NONUNIFORM_K))
+    return fail(SSOCT_EINVAL, "SSOCT_NONUNIFORM_K needs the dense depth transform (no SSOCT_DEPTH_FFT)");
   if ((flags & SSOCT_DEPTH_FFT) && !depth_fft_supported(T))
     return fail(SSOCT_EUNSUPPORTED, "SSOCT_DEPTH_FFT needs T in {16, 32, 64, 128, 256}");
   ssoct_plan* p = new (std::nothrow) ssoct_plan();
@@ -409,7 +428,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   p->stream = stream;
   p->F = frames_per_chunk(T, N);
   p->F_run = p->F;
-  p->dl = depth_layout(T);
+  p->general = (flags & SSOCT_NONUNIFORM_K) != 0;
+  p->dl = depth_layout(T, p->general);
   zernike_monomials(p->zmat);
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cu, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -433,7 +453,9 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
     for (auto& ev : p->ev)
       if (e == hipSuccess) e = hipEventCreate(&ev);
   }
-  if (e == hipSuccess) e = launch_depth_tables(T, p->a_f32, p->a_f16, p->a_bf16, stream);
+  // the general matrix depends on lambda: built with the other tables on the first render
+  if (e == hipSuccess && p->general) e = hipMalloc(&p->kappa, (size_t)T * sizeof(double));
+  if (e == hipSuccess && !p->general) e = launch_depth_tables(T, nullptr, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
   if (e == hipSuccess) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
   if (e == hipSuccess) e = launch_depth_twiddles(T, p->dtw, stream);
@@ -564,6 +586,16 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   return status;
 }
 
+int ssoct_plan_set_gate(ssoct_plan* p, const double* gate) {
+  if (int rc = check_plan(p)) return rc;
+  if (p->streaming) return fail(SSOCT_EINVAL, "the plan's parameters are fixed while a stream uses it");
+  if (gate && !finite_all(gate, p->T)) return fail(SSOCT_EINVAL, "gate has a non-finite entry");
+  if (gate) p->gate.assign(gate, gate + p->T);
+  else p->gate.clear();
+  p->cache.clear();   // tables rebuilt on the next call
+  return SSOCT_OK;
+}
+
 int ssoct_profile_read(ssoct_plan* p, float* ms) {
   if (int rc = check_plan(p)) return rc;
   if (!ms) return fail(SSOCT_EINVAL, "ms is NULL");
@@ -675,7 +707,7 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
   p->F_run = bestF;
   p->col_grid = bestC;
   // depth transform: default persistent grid or twice as many workgroups
-  const int d0 = depth_grid(p->T, p->N * p->N, p->cu);
+  const int d0 = depth_grid(p->T, p->N * p->N, p->cu, p->general);
   const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};
   best = 1e30f;
   for (int di = 0; di < 2 && rc == SSOCT_OK; ++di) {

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
                                                       void* __restrict__ out, int T, int T_pad, int P, int slabs,
                                                       float out_scale, float gamma_scale,
                                                       double* __restrict__ loss_partials,
-                                                      const float2* __restrict__ wt, int shift) {
+                                                      const float2* __restrict__ wt, int shift, int general) {
   using PT_ = PrecTraits<PREC>;
   constexpr int NA = PT_::F32 ? KC / 2 : (PT_::SPLIT ? KC / 2 : KC / 4);  // dwords of A per lane
   constexpr int PER_ROW = PT / 2;                                       // uint4 per tile row
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
   const int ntp = P / PT;
   const int ntiles = ntp * slabs;
   const int h = T / 2;
-  const int npairs = T - h;
+  const int npairs = general ? T : T - h;   // general matrix: one row pair per bin
   const int my_tiles = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int nitems = my_tiles * nch;                                    // (tile, chunk) work items
   const int cq = threadIdx.x % PER_ROW, r0 = threadIdx.x / PER_ROW;
@@ -197,7 +197,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
       const float Br = acc_re[r + 1] * out_scale, Bi = acc_im[r + 1] * out_scale;
       float2 v1, v2;
       int q1, q2;
-      if (k == 0) {
+      if (general) {          // rows (Re W_k, Im W_k) of a general matrix: V[k] = A + i B
+        q1 = k; v1 = make_float2(Ar - Bi, Ai + Br);
+        q2 = -1; v2 = v1;
+      } else if (k == 0) {
         q1 = 0; v1 = make_float2(Ar, Ai);
         q2 = (T % 2 == 0) ? h : -1; v2 = make_float2(Br, Bi);
       } else {
@@ -247,37 +250,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ 
 template <int PREC, int KC, int WAVES, int DIR, int EPI>
 static hipError_t depth_go(int grid, hipStream_t s, const void* in, const void* amat, void* out, int T, int T_pad,
                            int P, int slabs, float out_scale, float gamma_scale, double* partials, const float2* wt,
-                           int shift) {
+                           int shift, int general) {
   hipLaunchKernelGGL((k_depth<PREC, KC, WAVES, DIR, EPI>), dim3(grid), dim3(WAVES * 64), 0, s,
                      reinterpret_cast<const uint2*>(in), amat, out, T, T_pad, P, slabs, out_scale, gamma_scale,
-                     partials, wt, shift);
+                     partials, wt, shift, general);
   return hipGetLastError();
 }
 
 template <int PREC, int KC, int WAVES>
 static hipError_t depth_dir_epi(int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
-                                void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift) {
+                                void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift, int general) {
   if (dir > 0) {
-    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, +1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    if (epi == EPI_ABS) return depth_go<PREC, KC, WAVES, +1, EPI_ABS>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, +1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    if (epi == EPI_ABS) return depth_go<PREC, KC, WAVES, +1, EPI_ABS>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
     if constexpr (PREC == DP_F32)
-      return depth_go<PREC, KC, WAVES, +1, EPI_GAMMA>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+      return depth_go<PREC, KC, WAVES, +1, EPI_GAMMA>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
     return hipErrorInvalidValue;
   }
   if constexpr (PREC == DP_F32) {
-    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, -1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    if (epi == EPI_STORE) return depth_go<PREC, KC, WAVES, -1, EPI_STORE>(grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
   }
   return hipErrorInvalidValue;
 }
 
 template <int PREC, int KC>
 static hipError_t depth_waves(int waves, int dir, int epi, int grid, hipStream_t s, const void* in, const void* amat,
-                              void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift) {
+                              void* out, int T, int T_pad, int P, int slabs, float os, float gs, double* part, const float2* wt, int shift, int general) {
   switch (waves) {
-    case 1: return depth_dir_epi<PREC, KC, 1>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 2: return depth_dir_epi<PREC, KC, 2>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 4: return depth_dir_epi<PREC, KC, 4>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 8: return depth_dir_epi<PREC, KC, 8>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 1: return depth_dir_epi<PREC, KC, 1>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 2: return depth_dir_epi<PREC, KC, 2>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 4: return depth_dir_epi<PREC, KC, 4>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 8: return depth_dir_epi<PREC, KC, 8>(dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
     default: return hipErrorInvalidValue;
   }
 }
@@ -285,18 +288,18 @@ static hipError_t depth_waves(int waves, int dir, int epi, int grid, hipStream_t
 template <int PREC>
 static hipError_t depth_kc(int KC, int waves, int dir, int epi, int grid, hipStream_t s, const void* in,
                            const void* amat, void* out, int T, int T_pad, int P, int slabs, float os, float gs,
-                           double* part, const float2* wt, int shift) {
+                           double* part, const float2* wt, int shift, int general) {
   switch (KC) {
-    case 32: return depth_waves<PREC, 32>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 64: return depth_waves<PREC, 64>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 128: return depth_waves<PREC, 128>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
-    case 256: return depth_waves<PREC, 256>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift);
+    case 32: return depth_waves<PREC, 32>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 64: return depth_waves<PREC, 64>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 128: return depth_waves<PREC, 128>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
+    case 256: return depth_waves<PREC, 256>(waves, dir, epi, grid, s, in, amat, out, T, T_pad, P, slabs, os, gs, part, wt, shift, general);
     default: return hipErrorInvalidValue;
   }
 }
 
-int depth_grid(int T, int P, int cu_count) {
-  DepthLayout L = depth_layout(T);
+int depth_grid(int T, int P, int cu_count, bool general) {
+  DepthLayout L = depth_layout(T, general);
   const int ntiles = (P / PT) * L.slabs;
   int per_cu = 8 / L.waves;          // waves per CU target ~8
   if (per_cu < 1) per_cu = 1;
@@ -306,17 +309,19 @@ int depth_grid(int T, int P, int cu_count) {
 
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat, void* out,
                         int sigma, int gamma_exp, double* partials, int grid, hipStream_t s, const float2* wt,
-                        int shift) {
+                        int shift, bool general) {
   if (shift != 0 && !wt) return hipErrorInvalidValue;
-  DepthLayout L = depth_layout(T);
+  if (general && (dir < 0 || epi == EPI_GAMMA || shift != 0)) return hipErrorInvalidValue;   // forward only
+  DepthLayout L = depth_layout(T, general);
+  const int gen = general ? 1 : 0;
   const float os = ldexpf(1.0f, sigma);
   const float gs = ldexpf(1.0f, -gamma_exp);
   switch (prec) {
-    case DP_F32: return depth_kc<DP_F32>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
-    case DP_F16: return depth_kc<DP_F16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
-    case DP_BF16: return depth_kc<DP_BF16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
-    case DP_F16_SPLIT: return depth_kc<DP_F16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
-    case DP_BF16_SPLIT: return depth_kc<DP_BF16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift);
+    case DP_F32: return depth_kc<DP_F32>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift, gen);
+    case DP_F16: return depth_kc<DP_F16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift, gen);
+    case DP_BF16: return depth_kc<DP_BF16>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift, gen);
+    case DP_F16_SPLIT: return depth_kc<DP_F16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift, gen);
+    case DP_BF16_SPLIT: return depth_kc<DP_BF16_SPLIT>(L.KC, L.waves, dir, epi, grid, s, in, amat, out, T, L.T_pad, P, L.slabs, os, gs, partials, wt, shift, gen);
     default: return hipErrorInvalidValue;
   }
 }

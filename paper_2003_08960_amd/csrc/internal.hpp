@@ -71,7 +71,7 @@ struct DepthLayout {
   int waves;    // waves per workgroup (row blocks per slab, <= 8)
   int slabs;    // ceil(nrb / waves)
 };
-DepthLayout depth_layout(int T);
+DepthLayout depth_layout(int T, bool general = false);   // general: 2T rows (sweeps not linear in k)
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows, AxisTab* cols,
@@ -80,7 +80,9 @@ hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac
 // FFT engine twiddles (per-thread layout), FP64 -> FP32; size in float2 entries
 hipError_t launch_twiddles(int N, float2* tw, hipStream_t s);
 size_t twiddle_table_size(int N);
-hipError_t launch_depth_tables(int T, float* a_f32, uint4* a_f16, uint4* a_bf16, hipStream_t s);
+// kappa == nullptr: DFT matrix (paired real form); else the general matrix exp(-2 pi i q kappa_t / T)
+hipError_t launch_depth_tables(int T, const double* kappa, float* a_f32, uint4* a_f16, uint4* a_bf16,
+                               hipStream_t s);
 
 // Forward Fresnel stage on frames [t0, t0 + F): rescale + chirp + row DFT into
 // `inter` ([F][N][N] complex64), then column DFT into H (format `fmt`).
@@ -119,8 +121,8 @@ int row_adj_blocks(int N);
 // slot `shift`; bin q is multiplied by exp(+2 pi i q shift / T) = conj(wt[q shift mod T]).
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat,
                         void* out, int sigma, int gamma_exp, double* partials, int grid,
-                        hipStream_t s, const float2* wt = nullptr, int shift = 0);
-int depth_grid(int T, int P, int cu_count);
+                        hipStream_t s, const float2* wt = nullptr, int shift = 0, bool general = false);
+int depth_grid(int T, int P, int cu_count, bool general = false);
 
 // Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).
 // epi: EPI_STORE (complex64) or EPI_ABS (forward only).  wt: exp(-2 pi i k/T).

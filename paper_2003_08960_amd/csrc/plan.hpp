@@ -49,6 +49,9 @@ struct ssoct_plan {
   uint4* a_f16 = nullptr;
   uint4* a_bf16 = nullptr;
   float2* dtw = nullptr;       // exp(-2 pi i k / T): FFT depth twiddles and window phase
+  bool general = false;        // SSOCT_NONUNIFORM_K: general depth matrix from kappa_t
+  double* kappa = nullptr;     // device kappa_t (general matrix)
+  std::vector<double> gate;    // apodising gate g_t (empty: rectangular)
   double zmat[15][ssoct::N_MONO];
   std::vector<double> cache;   // parameter set the tables were last built from
   bool have_aberr = false;

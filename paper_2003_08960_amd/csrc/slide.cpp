@@ -174,6 +174,8 @@ int ssoct_slide_create(ssoct_slide** out, ssoct_plan* p, const double* lambda, d
   if (hop < 1 || hop > p->T) return fail(SSOCT_EINVAL, "hop must be in [1, T]");
   if (slots < 1 || slots > 64) return fail(SSOCT_EINVAL, "slots must be in [1, 64]");
   if (p->flags & SSOCT_WRITE_ABS) return fail(SSOCT_EUNSUPPORTED, "sliding windows need a complex64 volume");
+  if (p->general || !p->gate.empty())
+    return fail(SSOCT_EUNSUPPORTED, "sliding windows take the rectangular gate of a sweep linear in k");
   if (x0 < 0 || x0 >= p->N || y0 < 0 || y0 >= p->N || q0 < 0 || q0 >= p->T)
     return fail(SSOCT_EINVAL, "cut position out of range");
   SSOCT_HIP(hipSetDevice(p->device));

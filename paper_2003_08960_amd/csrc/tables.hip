@@ -142,14 +142,14 @@ __global__ void k_misc_tables(const double* __restrict__ params, int T, int N, f
   }
 }
 
-DepthLayout depth_layout(int T) {
+DepthLayout depth_layout(int T, bool general) {
   DepthLayout L;
   L.T = T;
   const int t32 = (T + 31) / 32 * 32;
   L.KC = 32;                                   // chunk of 32, 64, 128 or 256 frames
   while (L.KC < t32 && L.KC < 256) L.KC *= 2;
   L.T_pad = (T + L.KC - 1) / L.KC * L.KC;
-  L.rows = (T % 2 == 0) ? T : T + 1;
+  L.rows = general ? 2 * T : ((T % 2 == 0) ? T : T + 1);
   L.M_pad = (L.rows + 31) / 32 * 32;
   L.nrb = L.M_pad / 32;
   L.waves = 1;                                 // 1, 2, 4 or 8 waves of 32 rows each
@@ -177,6 +177,19 @@ __device__ __forceinline__ double depth_entry(int row, int t, int T) {
   return which == 0 ? c : -s;
 }
 
+// General matrix W[q][t] = exp(-2 pi i q kappa_t / T) (sweeps not linear in
+// k): row pair q holds (Re W_q, Im W_q) for every q = 0 .. T-1; the phase
+// q kappa_t is reduced modulo T in FP64 before the sine and cosine.
+__device__ __forceinline__ double depth_entry_general(int row, int t, int T, const double* __restrict__ kappa) {
+  const int q = row >> 1, which = row & 1;
+  if (t >= T || q >= T) return 0.0;
+  const double x = (double)q * kappa[t];
+  const double r = x - (double)T * floor(x / (double)T);
+  double s, c;
+  sincospi(2.0 * r / (double)T, &s, &c);
+  return which == 0 ? c : -s;
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   u += 0x7fffu + ((u >> 16) & 1u);
@@ -187,16 +200,18 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // One thread per (row block, k-step, lane).
 //   f32 : value A[row = 32 rb + l % 32][t = 2 s + l / 32]       -> a_f32[(rb * T_pad/2 + s) * 64 + l]
 //   f16 : 8 halves A[row][t = 16 s + 8 (l / 32) + i], hi and lo -> a_x[((rb * T_pad/16 + s) * 2 + hl) * 64 + l]
-__global__ void k_depth_tables(int T, int T_pad, int nrb, float* __restrict__ a_f32, uint4* __restrict__ a_f16,
-                               uint4* __restrict__ a_bf16) {
+// kappa == nullptr: the DFT matrix in its paired real form; else the general matrix
+__global__ void k_depth_tables(int T, int T_pad, int nrb, const double* __restrict__ kappa, float* __restrict__ a_f32,
+                               uint4* __restrict__ a_f16, uint4* __restrict__ a_bf16) {
   const int l = threadIdx.x;          // lane 0..63
   const int s = blockIdx.x;           // k-step of 2 (f32)
   const int rb = blockIdx.y;
   if (rb >= nrb) return;
   const int row = 32 * rb + (l & 31);
+  auto entry = [&](int t) { return kappa ? depth_entry_general(row, t, T, kappa) : depth_entry(row, t, T); };
   if (s < T_pad / 2) {
     const int t = 2 * s + (l >> 5);
-    a_f32[((size_t)rb * (T_pad / 2) + s) * 64 + l] = (float)depth_entry(row, t, T);
+    a_f32[((size_t)rb * (T_pad / 2) + s) * 64 + l] = (float)entry(t);
   }
   if (s < T_pad / 16) {
     uint32_t h16[2][4], b16[2][4];
@@ -204,7 +219,7 @@ __global__ void k_depth_tables(int T, int T_pad, int nrb, float* __restrict__ a_
       uint16_t hh[2], hl[2], bh[2], bl[2];
       for (int u = 0; u < 2; ++u) {
         const int t = 16 * s + 8 * (l >> 5) + i + u;
-        const float x = (float)depth_entry(row, t, T);
+        const float x = (float)entry(t);
         const _Float16 h = (_Float16)x;
         const _Float16 lo = (_Float16)(x - (float)h);
         hh[u] = __builtin_bit_cast(uint16_t, h);
@@ -240,10 +255,11 @@ hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac
   return hipGetLastError();
 }
 
-hipError_t launch_depth_tables(int T, float* a_f32, uint4* a_f16, uint4* a_bf16, hipStream_t s) {
-  DepthLayout L = depth_layout(T);
+hipError_t launch_depth_tables(int T, const double* kappa, float* a_f32, uint4* a_f16, uint4* a_bf16,
+                               hipStream_t s) {
+  DepthLayout L = depth_layout(T, kappa != nullptr);
   dim3 block(64), grid(L.T_pad / 2, L.nrb);
-  hipLaunchKernelGGL(k_depth_tables, grid, block, 0, s, T, L.T_pad, L.nrb, a_f32, a_f16, a_bf16);
+  hipLaunchKernelGGL(k_depth_tables, grid, block, 0, s, T, L.T_pad, L.nrb, kappa, a_f32, a_f16, a_bf16);
   return hipGetLastError();
 }
 

@@ -35,11 +35,12 @@ BACKWARD = 128
 PROFILE = 256
 PROFILE_KERNELS = 512
 DEPTH_FFT = 1024
+NONUNIFORM_K = 2048
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",
     "ssoct_plan_set_stream", "ssoct_plan_destroy", "ssoct_render", "ssoct_cuts", "ssoct_backward",
-    "ssoct_backward_sharpness", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
+    "ssoct_backward_sharpness", "ssoct_plan_set_gate", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
     "ssoct_plan_set_tuning", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
     "ssoct_stream_submit", "ssoct_stream_pop", "ssoct_stream_slot_volume", "ssoct_stream_stats",
     "ssoct_stream_destroy", "ssoct_slide_create", "ssoct_slide_push", "ssoct_slide_ring", "ssoct_slide_advance",
@@ -88,6 +89,8 @@ def _declare(lib):
     lib.ssoct_backward_sharpness.restype = c_int
     lib.ssoct_backward_sharpness.argtypes = [c_void_p, c_void_p, _dptr, c_double, c_double, _dptr, _dptr, c_void_p,
                                              c_size_t, c_void_p]
+    lib.ssoct_plan_set_gate.restype = c_int
+    lib.ssoct_plan_set_gate.argtypes = [c_void_p, _dptr]
     lib.ssoct_profile_read.restype = c_int
     lib.ssoct_profile_read.argtypes = [c_void_p, _fptr]
     _iptr = ctypes.POINTER(c_int)

@@ -42,6 +42,7 @@ class SweepConfig:
     speckle: float = 0.0
     aberration_rms: float = 0.0       # rad, std of the 15 Zernike coefficients
     dispersion_kappa: float = 0.0     # rad, quadratic dispersion amplitude
+    k_bend: float = 0.0               # quadratic departure of k(t) from a linear sweep
     name: str = ""
 
 
@@ -73,11 +74,15 @@ class Sweep:
     dispersion_true: np.ndarray | None = None
 
 
-def sweep_wavelengths(T: int, lam_max: float, lam_min: float) -> np.ndarray:
-    """Wavelengths linear in wavenumber, from lam_max down to lam_min inclusive."""
+def sweep_wavelengths(T: int, lam_max: float, lam_min: float, bend: float = 0.0) -> np.ndarray:
+    """Wavelengths from lam_max down to lam_min inclusive, linear in wavenumber
+    (bend = 0) or with the quadratic wavenumber k(u) = k0 + (k1 - k0)(u + bend u (u - 1)),
+    u = t / (T - 1), of a sweep that is not linear in k."""
     if T == 1:
         return np.array([lam_max])
-    k = np.linspace(2 * np.pi / lam_max, 2 * np.pi / lam_min, T)
+    u = np.linspace(0.0, 1.0, T)
+    k0, k1 = 2 * np.pi / lam_max, 2 * np.pi / lam_min
+    k = k0 + (k1 - k0) * (u + bend * u * (u - 1.0))
     return 2 * np.pi / k
 
 
@@ -108,7 +113,7 @@ def _zernike_cartesian(x, y):
 def make_sweep(cfg: SweepConfig, seed: int, dtype=np.complex64) -> Sweep:
     rng = np.random.Generator(np.random.PCG64(seed))
     T, N, d, z = cfg.T, cfg.N, cfg.pitch, cfg.z
-    lam = sweep_wavelengths(T, cfg.lam_max, cfg.lam_min)
+    lam = sweep_wavelengths(T, cfg.lam_max, cfg.lam_min, cfg.k_bend)
     k = 2 * np.pi / lam
     dk = (k[-1] - k[0]) / max(T - 1, 1)
     c = np.arange(N) - N // 2

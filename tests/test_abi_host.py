@@ -74,7 +74,10 @@ def test_plan_create_rejects_bad_sizes(lib):
     assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, fft | native.PREC_FP16, None) == native.EINVAL
     for T in (8, 100, 512):
         assert lib.ssoct_plan_create(ctypes.byref(h), T, 64, fft, None) == native.EUNSUPPORTED
+    assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, fft | native.NONUNIFORM_K, None) == native.EINVAL
     assert not h.value
+    g = (ctypes.c_double * 4)(1, 1, 1, 1)
+    assert lib.ssoct_plan_set_gate(None, g) == native.EINVAL
 
 
 def test_null_plan_is_rejected(lib):
