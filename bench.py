@@ -372,6 +372,48 @@ def bench_slide(sw, form, hop=13, windows=200, fps=512.0, paced_frames=768, pace
     return out
 
 
+def bench_nonuniform(sw, forms=("fp32", "bf16_split"), steps=10, warmup=3, accuracy=True):
+    """Sweep not linear in k (quadratic k(t), bend 0.15): the depth transform becomes a general T x T
+    matrix (2T real rows on MFMA, twice the flops and operand rows of the DFT's paired form)."""
+    import torch
+
+    from paper_2003_08960_amd import synth
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = sw.frames.shape
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9, bend=0.15)
+    frames = torch.from_numpy(sw.frames).cuda()
+    pix = sampled_pixels(sw)
+    ref = None
+    if accuracy:
+        from oracle import ssoct_oracle as O
+        ref = O.render_columns(sw.frames, lam, sw.pitch, sw.z, pix, nonuniform_k=True)
+    out = {"workload": f"paper-shaped frames, T={T}, N={N}, wavenumber quadratic in t (bend 0.15)", "forms": {}}
+    for form in forms:
+        plan = Plan(T, N, precision=form, nonuniform_k=True, profile=True)
+        vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
+        for _ in range(warmup):
+            plan.render(frames, lam, sw.pitch, sw.z, out=vol)
+        torch.cuda.synchronize()
+        plan.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.render(frames, lam, sw.pitch, sw.z, out=vol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = plan.profile_read()
+        rec = {"ms_per_step": ms, "gvoxel_s": T * N * N / (ms * 1e-3) / 1e9, "depth_ms": st[2],
+               "depth_tflop_s": 8.0 * T * T * N * N * depth_products(form) / (st[2] * 1e-3) / 1e12}
+        if ref is not None:
+            got = np.stack([vol[:, u, v].cpu().numpy() for u, v in pix], axis=1)
+            rec["rel_l2_sampled"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["forms"][form] = rec
+        log(f"nonuniform k {form}: {ms:.3f} ms/step, depth {st[2]:.3f} ms"
+            + (f", rel-L2 {rec['rel_l2_sampled']:.2e}" if "rel_l2_sampled" in rec else ""))
+        del plan, vol
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_backward(steps=10, warmup=3):
     """Loss sum |V|^4 and its gradient (z, 15 Zernike coefficients, T dispersion
     phases) on the aberrated T=128, N=512 workload: fused recompute-forward +
@@ -422,6 +464,7 @@ def main():
     ap.add_argument("--no-paced", action="store_true", help="skip the 512 frames/s paced stream (about 8 s)")
     ap.add_argument("--no-backward", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-slide", action="store_true", help="skip the sliding-window (hop 13) measurement")
+    ap.add_argument("--no-nonuniform", action="store_true", help="skip the non-k-linear sweep measurement")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch-shape tuner before timing each form (default: the plan's defaults; "
                          "the streaming form is always tuned)")
@@ -551,6 +594,8 @@ def main():
     if not args.no_slide:
         out["sliding"] = bench_slide(sw, head if head in ("fp32", "fp32_fft") else "fp32_fft",
                                      paced=not args.no_paced)
+    if not args.no_nonuniform:
+        out["nonuniform_k"] = bench_nonuniform(sw, accuracy=not args.no_accuracy)
     if not args.no_backward:
         out["backward"] = bench_backward()
     if not args.no_cpu_baseline:
