@@ -54,6 +54,12 @@ Readings of points the paper leaves open (each one also listed in the design doc):
     not linear in t: V[q] = sum_t h_t exp(-2 pi i q kappa_t / T) with
     kappa_t = (k_t - k_0) / dk, dk = (k_{T-1} - k_0) / (T - 1), which is t
     for a k-linear sweep).
+  * Angular-spectrum propagation (the alternative the paper contrasts with
+    the Fresnel transform; it keeps the sensor pitch for every wavelength, so
+    no rescale): h_t = F^-1{ F{I_t} exp(2 pi i z sqrt(lambda_t^-2 - fx^2 - fy^2)) }
+    with F the unnormalised DFT (negative exponent), F^-1 its inverse (1/N^2),
+    frequencies fx = k / (N d) for the DFT index k folded to [-N/2, N/2), and
+    the evanescent components (negative radicand) set to zero.
 """
 from __future__ import annotations
 
@@ -291,6 +297,40 @@ def depth_nudft(h: np.ndarray, kappa) -> np.ndarray:
 def depth_dft_adjoint(G: np.ndarray) -> np.ndarray:
     """beta_t = sum_q G_q exp(+2 pi i q t / T)."""
     return G.shape[0] * np.fft.ifft(G, axis=0)
+
+
+# ---------------------------------------------------------------------------
+# Angular-spectrum propagation (alternative propagator, no rescale)
+# ---------------------------------------------------------------------------
+
+def as_transfer(N: int, lam: float, pitch: float, z: float) -> np.ndarray:
+    """exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) on the DFT frequency grid, 0 where evanescent."""
+    f = np.fft.fftfreq(N, d=pitch)
+    rad = 1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2
+    H = np.zeros((N, N), dtype=np.complex128)
+    ok = rad > 0
+    cyc = z * np.sqrt(rad[ok])
+    H[ok] = np.exp(2j * np.pi * (cyc - np.floor(cyc)))
+    return H
+
+
+def as_propagate(x, lam: float, pitch: float, z: float) -> np.ndarray:
+    """Field x on the sensor grid propagated by z (angular spectrum, same grid)."""
+    x = np.asarray(x)
+    return np.fft.ifft2(np.fft.fft2(x) * as_transfer(x.shape[-1], lam, pitch, z))
+
+
+def render_as(frames, lam, pitch, z, disp_phase=None, gate=None, nonuniform_k=False) -> np.ndarray:
+    """Complex volume with angular-spectrum propagation of every frame at its own
+    wavelength, then the depth transform of Eq. 7 (optionally gated / non-uniform)."""
+    frames, lam = _check(frames, lam)
+    T, N, _ = frames.shape
+    phi = np.zeros(T) if disp_phase is None else np.asarray(disp_phase, dtype=np.float64)
+    g = np.ones(T) if gate is None else np.asarray(gate, dtype=np.float64)
+    out = np.empty((T, N, N), dtype=np.complex128)
+    for t in range(T):
+        out[t] = g[t] * np.exp(1j * phi[t]) * as_propagate(frames[t].astype(np.float64), lam[t], pitch, z)
+    return depth_nudft(out, wavenumber_positions(lam)) if nonuniform_k else depth_dft(out)
 
 
 # ---------------------------------------------------------------------------

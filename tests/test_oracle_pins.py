@@ -493,6 +493,73 @@ def test_render_extensions_reduce_to_the_paper_form():
 
 
 # --------------------------------------------------------------------------
+# Angular-spectrum propagation
+# --------------------------------------------------------------------------
+
+def check_as_plane_wave():
+    """An on-grid plane wave exp(2 pi i (a m + b n) / N) is an eigenfunction: it gains exactly
+    exp(2 pi i z sqrt(1/lambda^2 - (a/(N d))^2 - (b/(N d))^2)), or vanishes if evanescent."""
+    N, d, lam, z = 32, 10e-6, 850e-9, 0.01
+    m = np.arange(N)
+    for a, b in ((0, 0), (3, -5), (-16, 7), (11, 11)):
+        x = np.exp(2j * np.pi * (a * m[:, None] + b * m[None, :]) / N)
+        fx, fy = a / (N * d), b / (N * d)
+        want = np.exp(2j * np.pi * z * np.sqrt(1 / lam ** 2 - fx ** 2 - fy ** 2))
+        assert np.allclose(O.as_propagate(x, lam, d, z), want * x, atol=1e-9)
+    dd = 0.3e-6                                           # pitch below lambda / 2: the highest frequencies are evanescent
+    x = np.exp(2j * np.pi * (16 * m[:, None]) / N) * np.ones((1, N))   # f = 1/(2 dd) > 1/lambda
+    assert np.abs(O.as_propagate(x, lam, dd, z)).max() < 1e-12
+    with np.errstate(all="ignore"):
+        assert np.abs(O.as_propagate(x, lam, dd, -z)).max() < 1e-12   # dropped, not amplified, going back
+
+
+def check_as_composition():
+    """Propagating by z1 then z2 equals propagating by z1 + z2; z = 0 is the identity."""
+    rng = np.random.default_rng(8)
+    N, d, lam = 32, 12e-6, 830e-9
+    x = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    assert np.allclose(O.as_propagate(x, lam, d, 0.0), x, atol=1e-12)
+    a = O.as_propagate(O.as_propagate(x, lam, d, 0.004), lam, d, 0.011)
+    assert np.allclose(a, O.as_propagate(x, lam, d, 0.015), atol=1e-9)
+    back = O.as_propagate(O.as_propagate(x, lam, d, 0.02), lam, d, -0.02)
+    assert np.allclose(back, x, atol=1e-9)               # no evanescent band at this pitch
+
+
+def check_as_point_focus():
+    """The field of a point source at distance z, sampled on the sensor and band-limited to the
+    grid, propagates back (by -z) to a peak at the source pixel."""
+    N, d, lam, z = 64, 8e-6, 850e-9, 0.004
+    c = (np.arange(N) - N // 2) * d
+    r = np.sqrt(c[:, None] ** 2 + (c[None, :] - 5 * d) ** 2 + z ** 2)
+    x = np.exp(2j * np.pi * (r / lam)) / r
+    back = np.abs(O.as_propagate(x, lam, d, -z))
+    i, j = np.unravel_index(np.argmax(back), back.shape)
+    assert (i, j) == (N // 2, N // 2 + 5)
+
+
+def test_as_plane_wave():
+    check_as_plane_wave()
+
+
+def test_as_composition():
+    check_as_composition()
+
+
+def test_as_point_focus():
+    check_as_point_focus()
+
+
+def test_render_as_parseval_and_depth():
+    """With no evanescent band, the angular spectrum is unitary per frame: sum |V|^2 = T sum ||I_t||^2."""
+    rng = np.random.default_rng(2)
+    T, N = 8, 16
+    frames = rng.integers(0, 4096, size=(T, N, N)).astype(np.uint16)
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9)
+    V = O.render_as(frames, lam, 10e-6, 0.02)
+    assert abs(np.sum(np.abs(V) ** 2) / (T * np.sum(frames.astype(np.float64) ** 2)) - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
 # Planted mistakes: each plausible error in the oracle must fail a pin
 # --------------------------------------------------------------------------
 
@@ -518,9 +585,33 @@ def _plants():
         check_chirped_scatterer_focus
     yield "nudft sign", "depth_nudft", lambda orig: (lambda h, kap: np.conj(orig(np.conj(h), kap))), check_nudft_tone
     yield "gate ignored", "render", lambda orig: (lambda *a, gate=None, **k: orig(*a, **k)), check_hann_gate
+    yield "AS conjugate kernel", "as_transfer", lambda orig: (lambda *a: np.conj(orig(*a))), check_as_plane_wave
+    yield "AS Fresnel kernel", "as_transfer", lambda orig: (lambda N, lam, d, z: _fresnel_transfer(N, lam, d, z)), \
+        check_as_plane_wave
+    yield "AS keeps evanescent", "as_transfer", lambda orig: (lambda N, lam, d, z: _no_cutoff_transfer(N, lam, d, z)), \
+        check_as_plane_wave
+    yield "AS frequencies unfolded", "as_transfer", lambda orig: (lambda N, lam, d, z: _unfolded_transfer(N, lam, d, z)), \
+        check_as_point_focus
     yield "gate squared", "render", lambda orig: (
         lambda *a, gate=None, **k: orig(*a, gate=None if gate is None else np.asarray(gate) ** 2, **k)), \
         check_hann_gate
+
+
+def _fresnel_transfer(N, lam, d, z):
+    f = np.fft.fftfreq(N, d=d)
+    return np.exp(2j * np.pi * z / lam) * np.exp(-1j * np.pi * lam * z * (f[:, None] ** 2 + f[None, :] ** 2))
+
+
+def _no_cutoff_transfer(N, lam, d, z):
+    f = np.fft.fftfreq(N, d=d)
+    rad = (1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2).astype(np.complex128)
+    return np.exp(2j * np.pi * z * np.sqrt(rad))
+
+
+def _unfolded_transfer(N, lam, d, z):
+    f = np.arange(N) / (N * d)
+    rad = 1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2
+    return np.where(rad > 0, np.exp(2j * np.pi * z * np.sqrt(np.maximum(rad, 0))), 0)
 
 
 def _shifted_positions(N, s):
