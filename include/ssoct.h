@@ -75,6 +75,9 @@ extern "C" {
 #define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
 #define SSOCT_PROFILE_KERNELS 512u /* with SSOCT_PROFILE: an event after every Fresnel-stage launch too
                                       (each adds a few microseconds to the render) */
+#define SSOCT_ANGULAR_SPECTRUM 4096u /* propagate each frame by the angular spectrum at its own wavelength
+                                      (no rescale, sensor pitch, valid for any z) instead of Eq. 6;
+                                      not with SSOCT_CHIRP_EXACT, SSOCT_EQ6_PHASE, aberration or gradients */
 #define SSOCT_NONUNIFORM_K 2048u  /* depth transform exp(-2 pi i q kappa_t / T), kappa_t = (k_t - k_0)/dk from lambda:
                                       the uniform depth grid of a sweep not linear in k (dense forms only) */
 #define SSOCT_DEPTH_FFT 1024u     /* FP32 depth transform as a radix FFT along the sweep (T in {16..256},

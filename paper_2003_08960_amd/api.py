@@ -34,7 +34,7 @@ class Plan:
 
     def __init__(self, T: int, N: int, precision: str = "fp32", exact_chirp: bool = False,
                  eq6_phase: bool = False, write_abs: bool = False, cut_power: bool = False,
-                 nonuniform_k: bool = False,
+                 nonuniform_k: bool = False, angular_spectrum: bool = False,
                  backward: bool = False, profile: bool = False, device=None):
         self.lib = native.load()
         self.T, self.N = int(T), int(N)
@@ -44,6 +44,7 @@ class Plan:
         flags |= native.EQ6_PHASE if eq6_phase else 0
         flags |= native.WRITE_ABS if write_abs else 0
         flags |= native.NONUNIFORM_K if nonuniform_k else 0
+        flags |= native.ANGULAR_SPECTRUM if angular_spectrum else 0
         flags |= native.CUT_POWER if cut_power else 0
         flags |= native.BACKWARD if backward else 0
         flags |= native.PROFILE if profile else 0

@@ -121,6 +121,7 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->a_bf16);
   (void)hipFree(p->dtw);
   (void)hipFree(p->kappa);
+  (void)hipFree(p->as_params);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->kev)
@@ -180,12 +181,17 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   if (zern && !finite_all(zern, 15)) return fail(SSOCT_EINVAL, "zernike has a non-finite entry");
   if (for_backward && (p->flags & SSOCT_EQ6_PHASE))
     return fail(SSOCT_EUNSUPPORTED, "gradients are not available with SSOCT_EQ6_PHASE");
-  if (for_backward && (p->general || !p->gate.empty()))
-    return fail(SSOCT_EUNSUPPORTED, "gradients are not available with a gate or SSOCT_NONUNIFORM_K");
+  if (for_backward && (p->general || !p->gate.empty() || (p->flags & SSOCT_ANGULAR_SPECTRUM)))
+    return fail(SSOCT_EUNSUPPORTED,
+                "gradients are not available with a gate, SSOCT_NONUNIFORM_K or SSOCT_ANGULAR_SPECTRUM");
+  if ((p->flags & SSOCT_ANGULAR_SPECTRUM) && zern)
+    return fail(SSOCT_EUNSUPPORTED, "the aberration screen belongs to the Fresnel path");
 
   double lam1 = lambda[0];
   for (int t = 1; t < T; ++t) lam1 = lambda[t] > lam1 ? lambda[t] : lam1;
-  const int status = (std::fabs(z) < (double)N * pitch * pitch / lam1) ? SSOCT_WARN_UNDERSAMPLED : SSOCT_OK;
+  const bool as = (p->flags & SSOCT_ANGULAR_SPECTRUM) != 0;
+  // the validity bound after Eq. 6 concerns the Fresnel transform only
+  const int status = (!as && std::fabs(z) < (double)N * pitch * pitch / lam1) ? SSOCT_WARN_UNDERSAMPLED : SSOCT_OK;
 
   std::vector<double> key;
   key.reserve(3 * T + 20);
@@ -230,6 +236,18 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   if (zern && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
+  if (as) {
+    // per frame: 1/lambda_t^2, dispersion phase in cycles, gate / N^2 (inverse DFT normalisation)
+    std::vector<double> a(3 * (size_t)T);
+    for (int t = 0; t < T; ++t) {
+      a[3 * t] = 1.0 / (lambda[t] * lambda[t]);
+      a[3 * t + 1] = disp ? disp[t] / two_pi : 0.0;
+      a[3 * t + 2] = (p->gate.empty() ? 1.0 : p->gate[t]) / ((double)N * N);
+    }
+    SSOCT_HIP(hipMemcpyAsync(p->as_params, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    p->as_pitch = pitch;
+    p->as_z = z;
+  }
   if (p->general) {
     // kappa_t = (k_t - k_0) / dk, dk = (k_{T-1} - k_0) / (T - 1): sweep position in mean wavenumber steps
     std::vector<double> kap(T, 0.0);
@@ -247,7 +265,8 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   // depth-first order: the chirp and the per-frame row factor must not depend on the frame
   bool no_disp = true;
   for (int t = 0; disp && t < T; ++t) no_disp = no_disp && disp[t] == 0.0;
-  p->df_allowed = (p->flags & SSOCT_DEPTH_FFT) && !exact && !(p->flags & SSOCT_WRITE_ABS) && no_disp && p->gate.empty();
+  p->df_allowed = (p->flags & SSOCT_DEPTH_FFT) && !exact && !(p->flags & SSOCT_WRITE_ABS) && no_disp &&
+                  p->gate.empty() && !as;
   // FP16 operands: |H| <= N^2 * 65535 * amplitude, kept below 2^15 by an exact power-of-two scale
   p->sigma = 0;
   if (h_format(depth_prec(p->flags)) == HF_F16) {
@@ -267,6 +286,11 @@ static int depth_grid_for(const ssoct_plan* p) {
 int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, int t0, int Fc) {
   const int N = p->N;
   const int fmt = h_format(depth_prec(p->flags));
+  if (p->flags & SSOCT_ANGULAR_SPECTRUM) {
+    SSOCT_HIP(launch_as_stage(N, Fc, t0, frames, p->tw, p->as_params, 1.0 / ((double)N * p->as_pitch), p->as_z,
+                              reinterpret_cast<float2*>(ws + L.inter), ws + L.H, fmt, p->sigma, p->col_grid, s));
+    return SSOCT_OK;
+  }
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   const float2* ab = p->have_aberr ? p->aberr : nullptr;
   SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
@@ -416,6 +440,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
     return fail(SSOCT_EINVAL, "SSOCT_SPLIT needs SSOCT_PREC_FP16 or SSOCT_PREC_BF16");
   if ((flags & SSOCT_DEPTH_FFT) && (flags & (SSOCT_PREC_MASK | SSOCT_SPLIT)))
     return fail(SSOCT_EINVAL, "SSOCT_DEPTH_FFT is an FP32 form");
+  if ((flags & SSOCT_ANGULAR_SPECTRUM) && (flags & (SSOCT_CHIRP_EXACT | SSOCT_EQ6_PHASE)))
+    return fail(SSOCT_EINVAL, "SSOCT_CHIRP_EXACT and SSOCT_EQ6_PHASE belong to the Fresnel transform");
   if ((flags & SSOCT_DEPTH_FFT) && (flags & SSOCT_NONUNIFORM_K))
     return fail(SSOCT_EINVAL, "SSOCT_NONUNIFORM_K needs the dense depth transform (no SSOCT_DEPTH_FFT)");
   if ((flags & SSOCT_DEPTH_FFT) && !depth_fft_supported(T))
@@ -455,6 +481,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   }
   // the general matrix depends on lambda: built with the other tables on the first render
   if (e == hipSuccess && p->general) e = hipMalloc(&p->kappa, (size_t)T * sizeof(double));
+  if (e == hipSuccess && (flags & SSOCT_ANGULAR_SPECTRUM)) e = hipMalloc(&p->as_params, (size_t)3 * T * sizeof(double));
   if (e == hipSuccess && !p->general) e = launch_depth_tables(T, nullptr, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
   if (e == hipSuccess) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));

@@ -92,6 +92,14 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
                            const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
 
+// Angular-spectrum propagation of frames [t0, t0 + F) into H (format fmt):
+// row DFT^-, column DFT^- x transfer function x DFT^+, row DFT^+ (uncentred,
+// natural pixel order).  asp: per frame {1/lambda^2, phase offset (cycles),
+// amplitude (gate / N^2)}; inv_nd = 1 / (N pitch).
+hipError_t launch_as_stage(int N, int F, int t0, const uint16_t* frames, const float2* tw, const double* asp,
+                           double inv_nd, double z, float2* inter, void* H, int fmt, int sigma, int grid,
+                           hipStream_t s);
+
 // Depth-first order (frame-independent chirp, no per-frame phase):
 // G [T/2 + 1][N][N] = depth DFT of the rescaled frames (stage 1); then per
 // chunk of nb bins from qa: row DFTs of fac G_q and fac conj(G_q) into

@@ -52,6 +52,8 @@ struct ssoct_plan {
   bool general = false;        // SSOCT_NONUNIFORM_K: general depth matrix from kappa_t
   double* kappa = nullptr;     // device kappa_t (general matrix)
   std::vector<double> gate;    // apodising gate g_t (empty: rectangular)
+  double* as_params = nullptr; // SSOCT_ANGULAR_SPECTRUM: per frame {1/lambda^2, phase cycles, amplitude}
+  double as_pitch = 0.0, as_z = 0.0;
   double zmat[15][ssoct::N_MONO];
   std::vector<double> cache;   // parameter set the tables were last built from
   bool have_aberr = false;

@@ -296,6 +296,120 @@ __device__ __forceinline__ void store_h(void* __restrict__ H, long long idx, flo
   }
 }
 
+// ------------------------------------------------------------------ angular-spectrum passes
+// Propagation of the sensor field by the angular spectrum (no rescale, no
+// chirp, plain uncentred DFTs; pixel and frequency indices both natural):
+//   pass 1 (k_as_row_fwd): DFT^- of every u16 frame row into the chunk buffer;
+//   pass 2 (k_as_col): per column tile, DFT^- down the columns, times the
+//     transfer function, DFT^+ back, in place;
+//   pass 3 (k_as_row_inv): DFT^+ of every row into H (depth operand format).
+// The per-frame block `asp` holds 1/lambda_t^2, a phase offset in cycles
+// (dispersion) and an amplitude (gate / N^2) for each frame.
+template <int N>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_fwd(const uint16_t* __restrict__ frames, int t0,
+                                                                  const float2* __restrict__ tw,
+                                                                  float2* __restrict__ inter) {
+  using S = FFTShape<N>;
+  using R = RowCfg<N>;
+  constexpr int G = S::G;
+  __shared__ float2 xbuf[R::GR][RowLds<N>::XS];
+  const int g = threadIdx.x / G, j = threadIdx.x % G;
+  const int f = blockIdx.y;
+  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
+  const uint16_t* I = frames + (size_t)(t0 + f) * N * N;
+#pragma unroll 1
+  for (int i = 0; i < R::RPG; ++i) {
+    const int m = m0 + i;
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = make_float2((float)I[(size_t)m * N + j + k * G], 0.f);
+    exchange_sync<R::WAVE>();
+    fft_group<N, -1, R::WAVE>(v, j, xbuf[g], 1, tw);
+    float2* dst = inter + ((size_t)f * N + m) * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[j + out_offset<N>(e)] = v[e];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(float2* __restrict__ buf, int t0,
+                                                              const float2* __restrict__ tw,
+                                                              const double* __restrict__ asp, double inv_nd,
+                                                              double z, int ntiles) {
+  using S = FFTShape<N>;
+  constexpr int G = S::G;
+  constexpr int C = ColCfg<N>::C;
+  constexpr int NCB = N / C;
+  __shared__ float2 xbuf[S::LDS * C];
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int f = tile / NCB, kx = (tile % NCB) * C + c;
+    float2* col = buf + (size_t)f * N * N + kx;
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = col[(size_t)(j + k * G) * N];
+    fft_group<N, -1>(v, j, xbuf + c, C, tw);
+    const double* pf = asp + 3 * (size_t)(t0 + f);
+    const double inv_l2 = pf[0], cyc0 = pf[1], amp = pf[2];
+    const double fx = (double)(kx < N / 2 ? kx : kx - N) * inv_nd;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int ky = j + out_offset<N>(e);
+      const double fy = (double)(ky < N / 2 ? ky : ky - N) * inv_nd;
+      const double rad = inv_l2 - fx * fx - fy * fy;
+      float2 h = make_float2(0.f, 0.f);
+      if (rad > 0.0) {   // propagating: exp(2 pi i (z sqrt(rad) + cyc0)) amp; evanescent: 0
+        double cyc = z * sqrt(rad) + cyc0;
+        cyc -= floor(cyc);
+        double sn, cs;
+        sincospi(2.0 * cyc, &sn, &cs);
+        h = make_float2((float)(cs * amp), (float)(sn * amp));
+      }
+      v[e] = cmul(v[e], h);
+    }
+    __syncthreads();   // the forward transform's exchange reads are done
+    // back to rows: DFT^+ expects input element ky at register (ky - j) / G;
+    // the forward output sits at j + out_offset(e), so go through LDS once
+#pragma unroll
+    for (int e = 0; e < 16; ++e) xbuf[(size_t)lds_slot(j + out_offset<N>(e)) * C + c] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = xbuf[(size_t)lds_slot(j + k * G) * C + c];
+    __syncthreads();
+    fft_group<N, +1>(v, j, xbuf + c, C, tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) col[(size_t)(j + out_offset<N>(e)) * N] = v[e];
+    __syncthreads();   // this tile's exchange reads are done before the next tile writes LDS
+  }
+}
+
+template <int N, int FMT>
+__global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2* __restrict__ inter, int t0,
+                                                                  const float2* __restrict__ tw,
+                                                                  void* __restrict__ H, float scale) {
+  using S = FFTShape<N>;
+  using R = RowCfg<N>;
+  constexpr int G = S::G;
+  __shared__ float2 xbuf[R::GR][RowLds<N>::XS];
+  const int g = threadIdx.x / G, j = threadIdx.x % G;
+  const int f = blockIdx.y;
+  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
+#pragma unroll 1
+  for (int i = 0; i < R::RPG; ++i) {
+    const int m = m0 + i;
+    const float2* src = inter + ((size_t)f * N + m) * N;
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = src[j + k * G];
+    exchange_sync<R::WAVE>();
+    fft_group<N, +1, R::WAVE>(v, j, xbuf[g], 1, tw);
+    const long long base = ((long long)(t0 + f) * N + m) * N;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) store_h<FMT>(H, base + j + out_offset<N>(e), v[e], scale);
+  }
+}
+
 // ------------------------------------------------------------------ column pass (both directions)
 // Tiles are (frame f, block of C columns) over the F frames of the launch,
 // walked persistently.  src, dst: frame 0 of this launch; frame f at + f N^2.
@@ -564,6 +678,32 @@ hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, cons
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
                              int fstride, int grid, hipStream_t s) {
 #define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, s)
+  SSOCT_DISPATCH_N(N, CALL)
+#undef CALL
+}
+
+template <int N>
+static hipError_t as_stage_n(int F, int t0, const uint16_t* frames, const float2* tw, const double* asp,
+                             double inv_nd, double z, float2* inter, void* H, int fmt, int sigma, int req_grid,
+                             hipStream_t s) {
+  using R = RowCfg<N>;
+  using C = ColCfg<N>;
+  dim3 rgrid(N / R::ROWS, F), rblock(R::THREADS);
+  hipLaunchKernelGGL((k_as_row_fwd<N>), rgrid, rblock, 0, s, frames, t0, tw, inter);
+  const int ntiles = F * (N / C::C);
+  hipLaunchKernelGGL((k_as_col<N>), dim3(col_grid(ntiles, req_grid)), dim3(C::THREADS), 0, s, inter, t0, tw, asp,
+                     inv_nd, z, ntiles);
+  const float scale = ldexpf(1.0f, -sigma);
+  if (fmt == HF_F32) hipLaunchKernelGGL((k_as_row_inv<N, HF_F32>), rgrid, rblock, 0, s, inter, t0, tw, H, scale);
+  else if (fmt == HF_F16) hipLaunchKernelGGL((k_as_row_inv<N, HF_F16>), rgrid, rblock, 0, s, inter, t0, tw, H, scale);
+  else hipLaunchKernelGGL((k_as_row_inv<N, HF_BF16>), rgrid, rblock, 0, s, inter, t0, tw, H, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_as_stage(int N, int F, int t0, const uint16_t* frames, const float2* tw, const double* asp,
+                           double inv_nd, double z, float2* inter, void* H, int fmt, int sigma, int grid,
+                           hipStream_t s) {
+#define CALL(n) as_stage_n<n>(F, t0, frames, tw, asp, inv_nd, z, inter, H, fmt, sigma, grid, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }

@@ -36,6 +36,7 @@ PROFILE = 256
 PROFILE_KERNELS = 512
 DEPTH_FFT = 1024
 NONUNIFORM_K = 2048
+ANGULAR_SPECTRUM = 4096
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",
