@@ -414,6 +414,38 @@ def bench_nonuniform(sw, forms=("fp32", "bf16_split"), steps=10, warmup=3, accur
     return out
 
 
+def bench_angular_spectrum(sw, forms=("fp32_fft", "bf16_split"), steps=10, warmup=3, z=0.01):
+    """Angular-spectrum propagation of every frame at its own wavelength (z = 1 cm, well below
+    z_b = 0.17 m of the 12 um camera, where the Fresnel transform is undersampled), then the depth
+    transform.  Three passes per frame instead of two; parity is covered by the GPU tests."""
+    import torch
+
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = sw.frames.shape
+    frames = torch.from_numpy(sw.frames).cuda()
+    out = {"workload": f"paper-shaped frames, T={T}, N={N}, z={z} m", "forms": {}}
+    for form in forms:
+        plan = Plan(T, N, precision=form, angular_spectrum=True, profile=True)
+        vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
+        for _ in range(warmup):
+            plan.render(frames, sw.lam, sw.pitch, z, out=vol)
+        torch.cuda.synchronize()
+        plan.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.render(frames, sw.lam, sw.pitch, z, out=vol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = plan.profile_read()
+        out["forms"][form] = {"ms_per_step": ms, "gvoxel_s": T * N * N / (ms * 1e-3) / 1e9,
+                              "propagation_ms": st[1], "depth_ms": st[2],
+                              "propagation_hbm_gb_s": 42 * T * N * N / (st[1] * 1e-3) / 1e9}
+        log(f"angular spectrum {form}: {ms:.3f} ms/step, propagation {st[1]:.3f} ms, depth {st[2]:.3f} ms")
+        del plan, vol
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_backward(steps=10, warmup=3):
     """Loss sum |V|^4 and its gradient (z, 15 Zernike coefficients, T dispersion
     phases) on the aberrated T=128, N=512 workload: fused recompute-forward +
@@ -465,6 +497,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-slide", action="store_true", help="skip the sliding-window (hop 13) measurement")
     ap.add_argument("--no-nonuniform", action="store_true", help="skip the non-k-linear sweep measurement")
+    ap.add_argument("--no-as", action="store_true", help="skip the angular-spectrum measurement")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch-shape tuner before timing each form (default: the plan's defaults; "
                          "the streaming form is always tuned)")
@@ -596,6 +629,8 @@ def main():
                                      paced=not args.no_paced)
     if not args.no_nonuniform:
         out["nonuniform_k"] = bench_nonuniform(sw, accuracy=not args.no_accuracy)
+    if not args.no_as:
+        out["angular_spectrum"] = bench_angular_spectrum(sw)
     if not args.no_backward:
         out["backward"] = bench_backward()
     if not args.no_cpu_baseline:

@@ -195,12 +195,13 @@ __device__ __forceinline__ void exchange_sync() {
 }
 
 // Full N-point FFT of one group.  `lds` points to this group's LDS region of
-// FFTShape<N>::LDS complex slots with element stride `ls` (1 for row FFTs,
-// C for a C-column tile).  With WAVE = false every thread of the workgroup
-// must call this the same number of times (workgroup barriers).
-template <int N, int DIR, bool WAVE = false>
-__device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, int ls,
-                                          const float2* __restrict__ tw) {
+// FFTShape<N>::LDS complex slots with element stride LS (1 for row FFTs, C
+// for a C-column tile; a compile-time constant so that every LDS address is a
+// base plus an immediate offset).  With WAVE = false every thread of the
+// workgroup must call this the same number of times (workgroup barriers).
+template <int N, int DIR, int LS, bool WAVE = false>
+__device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, const float2* __restrict__ tw) {
+  constexpr int ls = LS;
   using S = FFTShape<N>;
   constexpr int G = S::G;
   int Ns = 1;

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
       const int n = j + k * G;
       v[k] = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, arow, n);
     }
-    fft_group<N, +1, R::WAVE>(v, j, lds.xbuf[g], 1, tw);
+    fft_group<N, +1, 1, R::WAVE>(v, j, lds.xbuf[g], tw);
     float2* dst = inter + ((size_t)f * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
         v[k] = cmul(fac, h == 0 ? gv[k] : cconj(gv[k]));
       }
       exchange_sync<R::WAVE>();  // the previous transform's exchange reads are done
-      fft_group<N, +1, R::WAVE>(v, j, xbuf[g], 1, tw);
+      fft_group<N, +1, 1, R::WAVE>(v, j, xbuf[g], tw);
       float2* dst = inter + ((size_t)(h == 0 ? f : Fh + f) * N + m) * N;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -324,21 +324,30 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_fwd(const uint16_
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = make_float2((float)I[(size_t)m * N + j + k * G], 0.f);
     exchange_sync<R::WAVE>();
-    fft_group<N, -1, R::WAVE>(v, j, xbuf[g], 1, tw);
+    fft_group<N, -1, 1, R::WAVE>(v, j, xbuf[g], tw);
     float2* dst = inter + ((size_t)f * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[j + out_offset<N>(e)] = v[e];
   }
 }
 
+// The transfer-function column pass keeps 16 FP64 phase evaluations in flight
+// per thread, so its tiles are narrower than the column pass's: at most 512
+// threads, which leaves 256 VGPRs per thread.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(float2* __restrict__ buf, int t0,
-                                                              const float2* __restrict__ tw,
-                                                              const double* __restrict__ asp, double inv_nd,
-                                                              double z, int ntiles) {
+struct AsColCfg {
+  static constexpr int C = ColCfg<N>::C * FFTShape<N>::G > 512 ? 512 / FFTShape<N>::G : ColCfg<N>::C;
+  static constexpr int THREADS = C * FFTShape<N>::G;
+};
+
+template <int N>
+__global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restrict__ buf, int t0,
+                                                                const float2* __restrict__ tw,
+                                                                const double* __restrict__ asp, double inv_nd,
+                                                                double z, int ntiles) {
   using S = FFTShape<N>;
   constexpr int G = S::G;
-  constexpr int C = ColCfg<N>::C;
+  constexpr int C = AsColCfg<N>::C;
   constexpr int NCB = N / C;
   __shared__ float2 xbuf[S::LDS * C];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
@@ -349,7 +358,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(float2* __restric
     float2 v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = col[(size_t)(j + k * G) * N];
-    fft_group<N, -1>(v, j, xbuf + c, C, tw);
+    fft_group<N, -1, C>(v, j, xbuf + c, tw);
     const double* pf = asp + 3 * (size_t)(t0 + f);
     const double inv_l2 = pf[0], cyc0 = pf[1], amp = pf[2];
     const double fx = (double)(kx < N / 2 ? kx : kx - N) * inv_nd;
@@ -360,11 +369,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(float2* __restric
       const double rad = inv_l2 - fx * fx - fy * fy;
       float2 h = make_float2(0.f, 0.f);
       if (rad > 0.0) {   // propagating: exp(2 pi i (z sqrt(rad) + cyc0)) amp; evanescent: 0
+        // the phase (up to ~1e5 cycles) is reduced to a fraction in FP64; sine and cosine of the
+        // fraction in FP32 are then good to about one ulp
         double cyc = z * sqrt(rad) + cyc0;
         cyc -= floor(cyc);
-        double sn, cs;
-        sincospi(2.0 * cyc, &sn, &cs);
-        h = make_float2((float)(cs * amp), (float)(sn * amp));
+        float sn, cs;
+        sincospif(2.0f * (float)cyc, &sn, &cs);
+        h = make_float2(cs * (float)amp, sn * (float)amp);
       }
       v[e] = cmul(v[e], h);
     }
@@ -377,7 +388,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_as_col(float2* __restric
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = xbuf[(size_t)lds_slot(j + k * G) * C + c];
     __syncthreads();
-    fft_group<N, +1>(v, j, xbuf + c, C, tw);
+    fft_group<N, +1, C>(v, j, xbuf + c, tw);
 #pragma unroll
     for (int e = 0; e < 16; ++e) col[(size_t)(j + out_offset<N>(e)) * N] = v[e];
     __syncthreads();   // this tile's exchange reads are done before the next tile writes LDS
@@ -403,7 +414,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2*
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = src[j + k * G];
     exchange_sync<R::WAVE>();
-    fft_group<N, +1, R::WAVE>(v, j, xbuf[g], 1, tw);
+    fft_group<N, +1, 1, R::WAVE>(v, j, xbuf[g], tw);
     const long long base = ((long long)(t0 + f) * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) store_h<FMT>(H, base + j + out_offset<N>(e), v[e], scale);
@@ -449,7 +460,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
       for (int k = 0; k < 16; ++k) v[k] = pf[k];
     }
     const int f = tile / NCB, col = (tile % NCB) * C + c;
-    fft_group<N, DIR>(v, j, xbuf + c, C, tw);
+    fft_group<N, DIR, C>(v, j, xbuf + c, tw);
     const long long fo = (long long)f * fstride * N * N;   // output frame f at dst + f fstride N^2
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     float2 v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = srow[j + k * G];
-    fft_group<N, -1, R::WAVE>(v, j, lds.xbuf[g], 1, tw);
+    fft_group<N, -1, 1, R::WAVE>(v, j, lds.xbuf[g], tw);
     exchange_sync<R::WAVE>();   // FFT reads of xbuf done before rbuf (aliased) is written
     lerp_rows<N>(cur, rc.f, rbuf, j);
     exchange_sync<R::WAVE>();
@@ -687,7 +698,7 @@ static hipError_t as_stage_n(int F, int t0, const uint16_t* frames, const float2
                              double inv_nd, double z, float2* inter, void* H, int fmt, int sigma, int req_grid,
                              hipStream_t s) {
   using R = RowCfg<N>;
-  using C = ColCfg<N>;
+  using C = AsColCfg<N>;
   dim3 rgrid(N / R::ROWS, F), rblock(R::THREADS);
   hipLaunchKernelGGL((k_as_row_fwd<N>), rgrid, rblock, 0, s, frames, t0, tw, inter);
   const int ntiles = F * (N / C::C);
