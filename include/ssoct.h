@@ -107,7 +107,9 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
 /* Change the stream of a plan. */
 int ssoct_plan_set_stream(ssoct_plan* plan, hipStream_t stream);
 
-/* Release a plan (waits for its stream). NULL is accepted. */
+/* Release a plan (waits for its stream). NULL is accepted.  SSOCT_EINVAL (and
+ * nothing released) while a stream or sliding-window object uses the plan:
+ * destroy those first. */
 int ssoct_plan_destroy(ssoct_plan* plan);
 
 /* Render one sweep: frames [T][N][N] uint16 -> vol [T][N][N] (steps 1-3).

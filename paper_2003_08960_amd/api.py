@@ -22,11 +22,26 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
-def _check_frames(frames: torch.Tensor, T: int, N: int):
+def _check_tensor(t: torch.Tensor, name: str, dtype, shape, device):
+    """Every buffer handed to the library: right dtype, shape, contiguity and device (the kernels
+    index it with the plan's sizes, so anything else would be read or written out of bounds)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous tensor of shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+
+
+def _check_frames(frames: torch.Tensor, T: int, N: int, device=None):
     if frames.dtype != torch.uint16:
         raise TypeError("frames must be torch.uint16")
     if tuple(frames.shape) != (T, N, N) or not frames.is_contiguous() or not frames.is_cuda:
         raise ValueError(f"frames must be a contiguous CUDA tensor of shape {(T, N, N)}")
+    if device is not None and frames.device != device:
+        raise ValueError(f"frames must be on {device}, got {frames.device}")
 
 
 class Plan:
@@ -72,8 +87,9 @@ class Plan:
             self._stream = s
 
     def close(self):
+        """Release the plan (raises while a Stream or Slide still uses it)."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            self.lib.ssoct_plan_destroy(self._h)
+            native.check(self.lib.ssoct_plan_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -86,12 +102,13 @@ class Plan:
                out: torch.Tensor | None = None) -> torch.Tensor:
         """Complex volume V [T, N, N] (complex64), or |V| (float32) for a write_abs plan."""
         T, N = self.T, self.N
-        _check_frames(frames, T, N)
+        _check_frames(frames, T, N, self.device)
         if out is None:
             if self.write_abs:
                 out = torch.empty((T, N, N), dtype=torch.float32, device=self.device)
             else:
                 out = torch.empty((T, N, N), dtype=torch.complex64, device=self.device)
+        _check_tensor(out, "out", torch.float32 if self.write_abs else torch.complex64, (T, N, N), self.device)
         lam_c = native.host_doubles(lam, T)
         ph_c = native.host_doubles(disp_phase, T)
         zc_c = native.host_doubles(zernike, 15)
@@ -104,8 +121,7 @@ class Plan:
     def cuts(self, vol: torch.Tensor, x0: int, y0: int, q0: int):
         """(cut_xy [N, N], cut_xz [T, N], cut_yz [T, N]) of the envelope."""
         T, N = self.T, self.N
-        if vol.dtype != torch.complex64 or tuple(vol.shape) != (T, N, N) or not vol.is_contiguous():
-            raise ValueError("vol must be a contiguous complex64 tensor [T, N, N]")
+        _check_tensor(vol, "vol", torch.complex64, (T, N, N), self.device)
         xy = torch.empty((N, N), dtype=torch.float32, device=self.device)
         xz = torch.empty((T, N), dtype=torch.float32, device=self.device)
         yz = torch.empty((T, N), dtype=torch.float32, device=self.device)
@@ -118,9 +134,8 @@ class Plan:
     def backward(self, frames, lam, pitch, z, grad_vol: torch.Tensor, disp_phase=None, zernike=None):
         """(dL/dz, dL/dc[15], dL/dphi[T]) as a float64 device tensor of 2 + 15 + T entries."""
         T, N = self.T, self.N
-        _check_frames(frames, T, N)
-        if grad_vol.dtype != torch.complex64 or tuple(grad_vol.shape) != (T, N, N) or not grad_vol.is_contiguous():
-            raise ValueError("grad_vol must be a contiguous complex64 tensor [T, N, N]")
+        _check_frames(frames, T, N, self.device)
+        _check_tensor(grad_vol, "grad_vol", torch.complex64, (T, N, N), self.device)
         out = torch.empty(2 + 15 + T, dtype=torch.float64, device=self.device)
         self._sync_stream()
         native.check(self.lib.ssoct_backward(
@@ -132,7 +147,7 @@ class Plan:
     def backward_sharpness(self, frames, lam, pitch, z, disp_phase=None, zernike=None):
         """[L, dL/dz, dL/dc (15), dL/dphi (T)] for L = sum |V|^4, float64 device tensor."""
         T, N = self.T, self.N
-        _check_frames(frames, T, N)
+        _check_frames(frames, T, N, self.device)
         out = torch.empty(2 + 15 + T, dtype=torch.float64, device=self.device)
         self._sync_stream()
         native.check(self.lib.ssoct_backward_sharpness(
@@ -184,7 +199,7 @@ class Plan:
             if cached is not None:
                 self.set_tuning(cached)
                 return list(cached)
-        _check_frames(frames, self.T, self.N)
+        _check_frames(frames, self.T, self.N, self.device)
         out = self.render(frames, lam, pitch, z, disp_phase, zernike, out=out)
         t = (ctypes.c_int * 4)()
         self._sync_stream()

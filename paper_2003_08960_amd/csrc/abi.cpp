@@ -504,6 +504,7 @@ int ssoct_plan_set_stream(ssoct_plan* plan, hipStream_t stream) {
 
 int ssoct_plan_destroy(ssoct_plan* plan) {
   if (!plan) return SSOCT_OK;
+  if (plan->streaming) return fail(SSOCT_EINVAL, "a stream or sliding-window object still uses the plan");
   (void)hipStreamSynchronize(plan->stream);
   plan_free(plan);
   return SSOCT_OK;

@@ -223,3 +223,25 @@ def test_stream_with_fft_depth_form(gpu_lib, sweeps):
         assert np.array_equal(r["cut_xz"], refs[r["seq"]][1][1])
     assert st.stats()["done"] == 3
     st.close()
+
+
+def test_binding_guards(gpu_lib, sweeps):
+    """Buffers of the wrong shape, dtype or device are refused before any launch, and a plan cannot
+    be released while a stream uses it."""
+    from paper_2003_08960_amd.api import Plan, Stream
+    plan = Plan(T, N)
+    sw = sweeps[0]
+    fr = torch.from_numpy(sw.frames).cuda()
+    with pytest.raises(ValueError):
+        plan.render(fr, sw.lam, sw.pitch, sw.z, out=torch.empty((T, N, N - 1), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(TypeError):
+        plan.render(fr, sw.lam, sw.pitch, sw.z, out=torch.empty((T, N, N), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.render(fr, sw.lam, sw.pitch, sw.z, out=torch.empty((T, N, N), dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        plan.cuts(torch.empty((T, N, N), dtype=torch.complex64, device="cuda")[:, :, ::1].transpose(1, 2), 0, 0, 0)
+    st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=1)
+    with pytest.raises(native.SsoctError):
+        plan.close()
+    st.close()
+    plan.close()
