@@ -457,9 +457,10 @@ def bench_backward(steps=10, warmup=3):
     sw = synth.make_config("diff")
     T, N, _ = sw.frames.shape
     fr = torch.from_numpy(sw.frames).cuda()
-    disp = np.zeros(T)
-    zern = np.zeros(15)
-    plan = Plan(T, N, backward=True)
+    # a point in general position of the optimisation (non-zero coefficients: the screen is built and read)
+    rng = np.random.default_rng(4)
+    zern = rng.normal(0, 0.3, 15)
+    disp = rng.uniform(-1, 1, T)
     vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
 
     def timed(fn):
@@ -472,15 +473,19 @@ def bench_backward(steps=10, warmup=3):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    ms_fwd = timed(lambda: plan.render(fr, sw.lam, sw.pitch, sw.z, disp, zern, out=vol))
-    ms_bwd = timed(lambda: plan.backward_sharpness(fr, sw.lam, sw.pitch, sw.z, disp, zern))
-    del plan, vol, fr
-    torch.cuda.empty_cache()
     rec = {"workload": f"aberrated sweep T={T}, N={N}: loss sum |V|^4, gradient w.r.t. z, 15 Zernike "
-                       f"coefficients and {T} dispersion phases (FP32, forward recomputed)",
-           "ms_forward_render": ms_fwd, "ms_loss_and_gradient": ms_bwd, "ratio": ms_bwd / ms_fwd,
-           "gvoxel_s_loss_and_gradient": T * N * N / (ms_bwd * 1e-3) / 1e9}
-    log(f"backward: forward {ms_fwd:.3f} ms, loss+gradient {ms_bwd:.3f} ms ({ms_bwd / ms_fwd:.2f}x)")
+                       f"coefficients and {T} dispersion phases (FP32, forward recomputed)", "forms": {}}
+    for form in ("fp32", "fp32_fft"):
+        plan = Plan(T, N, precision=form, backward=True)
+        ms_fwd = timed(lambda: plan.render(fr, sw.lam, sw.pitch, sw.z, disp, zern, out=vol))
+        ms_bwd = timed(lambda: plan.backward_sharpness(fr, sw.lam, sw.pitch, sw.z, disp, zern))
+        plan.close()
+        del plan
+        rec["forms"][form] = {"ms_forward_render": ms_fwd, "ms_loss_and_gradient": ms_bwd, "ratio": ms_bwd / ms_fwd,
+                              "gvoxel_s_loss_and_gradient": T * N * N / (ms_bwd * 1e-3) / 1e9}
+        log(f"backward {form}: forward {ms_fwd:.3f} ms, loss+gradient {ms_bwd:.3f} ms ({ms_bwd / ms_fwd:.2f}x)")
+    del vol, fr
+    torch.cuda.empty_cache()
     return rec
 
 

@@ -138,8 +138,9 @@ int ssoct_cuts(ssoct_plan* plan, const void* vol, int x0, int y0, int q0, float*
  * convention G = 2 dL/d conj(V)).  Writes device double grad_out[2 + 15 + T]:
  * [0] = 0, [1] = dL/dz, [2..16] = dL/dc_j, [17..17+T) = dL/dphi_t.
  * The forward transform is not needed: the rescaled, chirped frames are
- * recomputed inside the adjoint.  Needs a plan with SSOCT_PREC_FP32 or any
- * precision (the adjoint always runs in FP32) and a workspace sized with
+ * recomputed inside the adjoint.  Any precision (the adjoint always runs in
+ * FP32: a plan with SSOCT_DEPTH_FFT takes the adjoint depth transform as a
+ * radix FFT, any other plan as the dense FP32 product); a workspace sized with
  * SSOCT_BACKWARD; SSOCT_EQ6_PHASE is not supported (SSOCT_EUNSUPPORTED). */
 int ssoct_backward(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                    const double* disp_phase, const double* zernike, const void* grad_vol, void* workspace,

@@ -47,6 +47,13 @@ int frames_per_chunk(int T, int N) {
   return (int)f;
 }
 
+// FP64 loss partials of the sharpness epilogue: one per dense depth
+// workgroup (at most 4096) or one per FFT depth workgroup
+static size_t loss_partial_capacity(int N) {
+  const size_t nfft = (size_t)depth_fft_blocks(N * N);
+  return nfft > 4096 ? nfft : 4096;
+}
+
 WsLayout ws_layout(int T, int N, uint32_t flags, int F) {
   WsLayout w{};
   const size_t stack = (size_t)T * N * N * 8;
@@ -61,7 +68,7 @@ WsLayout ws_layout(int T, int N, uint32_t flags, int F) {
     w.mono = off;
     off += align256((size_t)T * row_adj_blocks(N) * N_MONO * sizeof(double));
     w.loss = off;
-    off += align256((size_t)4096 * sizeof(double));
+    off += align256((size_t)loss_partial_capacity(N) * sizeof(double));
   }
   w.total = off;
   return w;
@@ -224,7 +231,10 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   }
   double* g = &h[ParamLayout::globals(T)];
   g[ParamLayout::G_KAPPA_OUT] = lam1 * z / (2.0 * (double)N * N * pitch * pitch);
-  if (zern) {
+  // all-zero coefficients give A = 1 exactly: no screen is built or read
+  bool zern_on = false;
+  for (int j = 0; zern && j < 15; ++j) zern_on = zern_on || zern[j] != 0.0;
+  if (zern_on) {
     for (int k = 0; k < N_MONO; ++k) {
       double c = 0.0;
       for (int j = 0; j < 15; ++j) c += zern[j] * p->zmat[j][k];
@@ -233,7 +243,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     g[ParamLayout::G_HAS_ABERR] = 1.0;
   }
   std::memcpy(&h[ParamLayout::count(T) + T], &p->zmat[0][0], sizeof(double) * 15 * N_MONO);
-  if (zern && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
+  if (zern_on && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
   if (as) {
@@ -260,8 +270,8 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     SSOCT_HIP(hipMemcpyAsync(p->kappa, kap.data(), (size_t)T * sizeof(double), hipMemcpyHostToDevice, p->stream));
     SSOCT_HIP(launch_depth_tables(T, p->kappa, p->a_f32, p->a_f16, p->a_bf16, p->stream));
   }
-  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern ? p->aberr : nullptr, p->stream));
-  p->have_aberr = zern != nullptr;
+  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern_on ? p->aberr : nullptr, p->stream));
+  p->have_aberr = zern_on;
   // depth-first order: the chirp and the per-frame row factor must not depend on the frame
   bool no_disp = true;
   for (int t = 0; disp && t < T; ++t) no_disp = no_disp && disp[t] == 0.0;
@@ -388,8 +398,11 @@ static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, c
   float2* beta = reinterpret_cast<float2*>(ws + L.H);
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   double* mono = reinterpret_cast<double*>(ws + L.mono);
-  SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, depth_grid_for(p),
-                         p->stream));
+  if (p->flags & SSOCT_DEPTH_FFT)
+    SSOCT_HIP(launch_depth_fft(T, N * N, -1, EPI_STORE, static_cast<const float2*>(G), p->dtw, beta, p->stream));
+  else
+    SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, depth_grid_for(p),
+                           p->stream));
   for (int t0 = 0; t0 < T; t0 += F) {
     const int Fc = T - t0 < F ? T - t0 : F;
     SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->col_grid, p->stream));
@@ -607,10 +620,17 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   const double bound = (double)T * N * N * 65535.0;
   int e = (int)std::ceil(std::log2(bound)) - 40;
   if (e < 0) e = 0;
-  const int grid = depth_grid_for(p);
-  if (grid > 4096) return fail(SSOCT_EINVAL, "depth grid larger than the loss-partial buffer");
-  SSOCT_HIP(launch_depth(T, N * N, DP_F32, +1, EPI_GAMMA, H, p->a_f32, gam, 0, e, loss, grid, p->stream));
-  if (int rc = adjoint_chain(p, frames, gam, ws, L, loss, grid, std::ldexp(1.0, 3 * e), grad_out)) return rc;
+  int n_loss;
+  if (p->flags & SSOCT_DEPTH_FFT) {
+    n_loss = depth_fft_blocks(N * N);
+    SSOCT_HIP(launch_depth_fft(T, N * N, +1, EPI_GAMMA, static_cast<const float2*>(H), p->dtw, gam, p->stream, 0, e,
+                               loss));
+  } else {
+    n_loss = depth_grid_for(p);
+    if (n_loss > 4096) return fail(SSOCT_EINVAL, "depth grid larger than the loss-partial buffer");
+    SSOCT_HIP(launch_depth(T, N * N, DP_F32, +1, EPI_GAMMA, H, p->a_f32, gam, 0, e, loss, n_loss, p->stream));
+  }
+  if (int rc = adjoint_chain(p, frames, gam, ws, L, loss, n_loss, std::ldexp(1.0, 3 * e), grad_out)) return rc;
   return status;
 }
 

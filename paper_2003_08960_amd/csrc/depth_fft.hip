@@ -28,7 +28,8 @@ namespace ssoct {
 
 template <int T2, int DIR, int EPI, int PX>
 __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict__ H, const float2* __restrict__ wt,
-                                                        void* __restrict__ out, int P, int shift) {
+                                                        void* __restrict__ out, int P, int shift, float gamma_scale,
+                                                        double* __restrict__ loss_partials) {
   constexpr int T = 16 * T2;
   constexpr int ED = -DIR;           // engine sign: forward depth DFT has exponent -2 pi i q t / T
   __shared__ float2 lds[T * PX];     // [q2][t1][px]
@@ -49,23 +50,54 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
     lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], w);
   }
   __syncthreads();
-  if (r >= T2) return;
+  if constexpr (EPI == EPI_GAMMA) {
+    // sharpness loss: every thread stays for the workgroup's loss reduction
+    double loss = 0.0;
+    if (r < T2 && live) {
+      float2 b[16];
+#pragma unroll
+      for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+      dft16<ED>(b);
+#pragma unroll
+      for (int q1 = 0; q1 < 16; ++q1) {
+        const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
+        const double a2 = (double)b[q1].x * b[q1].x + (double)b[q1].y * b[q1].y;
+        loss += a2 * a2;
+        // Gamma = 4 |V~|^2 V~ with V~ = V 2^-e, finite in FP32
+        const float sx = b[q1].x * gamma_scale, sy = b[q1].y * gamma_scale;
+        const float m2 = 4.0f * (sx * sx + sy * sy);
+        reinterpret_cast<float2*>(out)[idx] = make_float2(m2 * sx, m2 * sy);
+      }
+    }
+    __shared__ double red[16 * PX / 64];
+    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < 16 * PX / 64; ++i) sum += red[i];
+      loss_partials[blockIdx.x] = sum;
+    }
+    return;
+  } else {
+    if (r >= T2) return;
 
-  // stage B: DFT over t1 for bin column q2 = r
-  float2 b[16];
+    // stage B: DFT over t1 for bin column q2 = r
+    float2 b[16];
 #pragma unroll
-  for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
-  dft16<ED>(b);
-  if (!live) return;
+    for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+    dft16<ED>(b);
+    if (!live) return;
 #pragma unroll
-  for (int q1 = 0; q1 < 16; ++q1) {
-    const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
-    if constexpr (EPI == EPI_ABS)
-      st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
-    else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
-      st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
-    else
-      st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
+    for (int q1 = 0; q1 < 16; ++q1) {
+      const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
+      if constexpr (EPI == EPI_ABS)
+        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
+      else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
+        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
+      else
+        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
+    }
   }
 }
 
@@ -269,36 +301,44 @@ hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTa
 }
 
 template <int T2, int DIR, int EPI>
-static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, int shift, hipStream_t s) {
+static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, int shift, float gs,
+                              double* partials, hipStream_t s) {
   constexpr int PX = SSOCT_DFFT_PX;
   hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3((P + PX - 1) / PX), dim3(16 * PX), 0, s, H, wt, out, P,
-                     shift);
+                     shift, gs, partials);
   return hipGetLastError();
 }
 
 template <int DIR, int EPI>
-static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, int shift, hipStream_t s) {
+static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, int shift, float gs,
+                              double* partials, hipStream_t s) {
   switch (T) {
-    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, s);
-    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, s);
-    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, s);
-    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, s);
-    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, s);
+    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
+    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
+    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
+    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
+    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool depth_fft_supported(int T) { return T == 16 || T == 32 || T == 64 || T == 128 || T == 256; }
 
+int depth_fft_blocks(int P) { return (P + SSOCT_DFFT_PX - 1) / SSOCT_DFFT_PX; }
+
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s, int shift) {
+                            hipStream_t s, int shift, int gamma_exp, double* partials) {
   if (P <= 0) return hipSuccess;
   if (dir > 0) {
-    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, s);
-    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, s);
+    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, 1.f, nullptr, s);
+    if (epi == EPI_GAMMA) {
+      if (!partials || shift != 0) return hipErrorInvalidValue;
+      return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, s);
+    }
+    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, 1.f, nullptr, s);
   }
-  if (epi != EPI_STORE) return hipErrorInvalidValue;
-  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, s);
+  if (epi != EPI_STORE || shift != 0) return hipErrorInvalidValue;
+  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, 1.f, nullptr, s);
 }
 
 // wt[k] = exp(-2 pi i k / T), k = 0..T-1, from FP64 (sincospi) rounded to FP32

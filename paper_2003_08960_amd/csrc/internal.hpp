@@ -133,10 +133,13 @@ hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in
 int depth_grid(int T, int P, int cu_count, bool general = false);
 
 // Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).
-// epi: EPI_STORE (complex64) or EPI_ABS (forward only).  wt: exp(-2 pi i k/T).
+// epi: EPI_STORE (complex64), EPI_ABS or EPI_GAMMA (forward only; the latter
+// writes Gamma = 4 |V 2^-gamma_exp|^2 V 2^-gamma_exp and one FP64 partial of
+// sum |V|^4 per workgroup, depth_fft_blocks(P) of them).  wt: exp(-2 pi i k/T).
 bool depth_fft_supported(int T);
+int depth_fft_blocks(int P);
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s, int shift = 0);
+                            hipStream_t s, int shift = 0, int gamma_exp = 0, double* partials = nullptr);
 hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,

@@ -40,63 +40,80 @@ hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, 
   return hipGetLastError();
 }
 
-// Single workgroup.  mono_partials[t][nblk][15] are per-block moments
-// M_ab = sum Im(conj(g) z) x^a y^b; zmat[j][k] expands Zernike j in the
-// monomials.  Gradients (chain of the sharpness loss):
+// Single workgroup of GF_THREADS.  mono_partials[t][nblk][15] are per-block
+// moments M_ab = sum Im(conj(g) z) x^a y^b; zmat[j][k] expands Zernike j in
+// the monomials.  Gradients (chain of the sharpness loss):
 //   dL/dphi_t = -M_00(t),  dL/dz = -sum_t (alpha_t / z) (N^2 / 2) (M_20 + M_02)(t),
 //   dL/dc_j   = -sum_t sum_k zmat[j][k] M_k(t),   all times grad_scale.
-__global__ void k_grad_finish(int T, int N, int nblk, const double* __restrict__ mono_partials,
-                              const double* __restrict__ loss_partials, int n_loss,
-                              const double* __restrict__ alpha_over_z, const double* __restrict__ zmat,
-                              double grad_scale, double* __restrict__ out) {
-  __shared__ double tot[N_MONO + 1][256];
+// Every sum runs in a fixed order (strided per thread, butterfly per wave,
+// waves in index order), so the result does not depend on timing.
+constexpr int GF_THREADS = 1024;
+
+__global__ __launch_bounds__(GF_THREADS) void k_grad_finish(int T, int N, int nblk,
+                                                            const double* __restrict__ mono_partials,
+                                                            const double* __restrict__ loss_partials, int n_loss,
+                                                            const double* __restrict__ alpha_over_z,
+                                                            const double* __restrict__ zmat, double grad_scale,
+                                                            double* __restrict__ out) {
+  constexpr int NWV = GF_THREADS / 64;
+  __shared__ double red[NWV][N_MONO + 2];
+  __shared__ double zs[15 * N_MONO];
   const int tid = threadIdx.x;
-  double mz[N_MONO];
-  double dz = 0.0;
-#pragma unroll
-  for (int k = 0; k < N_MONO; ++k) mz[k] = 0.0;
+  if (tid < 15 * N_MONO) zs[tid] = zmat[tid];   // in flight while the partials are summed
   const double half_n2 = 0.5 * (double)N * (double)N;
-  for (int t = tid; t < T; t += blockDim.x) {
-    double m[N_MONO];
-#pragma unroll
-    for (int k = 0; k < N_MONO; ++k) m[k] = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      const double* p = mono_partials + ((size_t)t * nblk + b) * N_MONO;
-#pragma unroll
-      for (int k = 0; k < N_MONO; ++k) m[k] += p[k];
-    }
-    out[1 + 1 + 15 + t] = -grad_scale * m[0];
-    dz += alpha_over_z[t] * half_n2 * (m[3] + m[5]);
-#pragma unroll
-    for (int k = 0; k < N_MONO; ++k) mz[k] += m[k];
+  for (int t = tid; t < T; t += GF_THREADS) {
+    double m0 = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) m0 += mono_partials[((size_t)t * nblk + b) * N_MONO];
+    out[1 + 1 + 15 + t] = -grad_scale * m0;
   }
+  double acc[N_MONO + 2];
 #pragma unroll
-  for (int k = 0; k < N_MONO; ++k) tot[k][tid] = mz[k];
-  tot[N_MONO][tid] = dz;
+  for (int k = 0; k < N_MONO + 2; ++k) acc[k] = 0.0;
+  const int rows = T * nblk;
+#pragma unroll 2
+  for (int i = tid; i < rows; i += GF_THREADS) {
+    const double* p = mono_partials + (size_t)i * N_MONO;
+    const double w = alpha_over_z[i / nblk] * half_n2;
+#pragma unroll
+    for (int k = 0; k < N_MONO; ++k) acc[k] += p[k];
+    acc[N_MONO] += w * (p[3] + p[5]);
+  }
+#pragma unroll 8
+  for (int i = tid; i < n_loss; i += GF_THREADS) acc[N_MONO + 1] += loss_partials[i];
+#pragma unroll
+  for (int k = 0; k < N_MONO + 2; ++k) {
+    double a = acc[k];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    acc[k] = a;
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < N_MONO + 2; ++k) red[tid >> 6][k] = acc[k];
+  }
   __syncthreads();
-  if (tid == 0) {
-    double M[N_MONO + 1];
-    for (int k = 0; k <= N_MONO; ++k) {
-      double s = 0.0;
-      for (int i = 0; i < (int)blockDim.x; ++i) s += tot[k][i];
-      M[k] = s;
-    }
-    double L = 0.0;
-    for (int i = 0; i < n_loss; ++i) L += loss_partials[i];
-    out[0] = L;
+  if (tid < N_MONO + 2) {
+    double s = 0.0;
+    for (int w = 0; w < NWV; ++w) s += red[w][tid];
+    red[0][tid] = s;
+  }
+  __syncthreads();
+  const double* M = red[0];
+  if (tid < 15) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < N_MONO; ++k) s += zs[tid * N_MONO + k] * M[k];
+    out[2 + tid] = -grad_scale * s;
+  } else if (tid == 15) {
+    out[0] = M[N_MONO + 1];
     out[1] = -grad_scale * M[N_MONO];
-    for (int j = 0; j < 15; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < N_MONO; ++k) s += zmat[j * N_MONO + k] * M[k];
-      out[2 + j] = -grad_scale * s;
-    }
   }
 }
 
 hipError_t launch_grad_finish(int T, int N, int nblk, const double* mono_partials, const double* loss_partials,
                               int n_loss, const double* alpha_over_z, const double* zmat, double grad_scale,
                               double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(256), 0, s, T, N, nblk, mono_partials, loss_partials, n_loss,
+  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(GF_THREADS), 0, s, T, N, nblk, mono_partials, loss_partials, n_loss,
                      alpha_over_z, zmat, grad_scale, out);
   return hipGetLastError();
 }

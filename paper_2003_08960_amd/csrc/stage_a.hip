@@ -36,10 +36,14 @@ namespace ssoct {
 #define SSOCT_ROW_NT 0           // row pass: non-temporal stores of the intermediate
 #endif
 #ifndef SSOCT_COL_NT
-#define SSOCT_COL_NT 1           // column pass: non-temporal stores of H (and of the adjoint's intermediate)
+#define SSOCT_COL_NT 1           // column pass: non-temporal stores of H
 #endif
 #ifndef SSOCT_COL_NT_LD
 #define SSOCT_COL_NT_LD 1        // column pass: non-temporal loads of the intermediate
+#endif
+#ifndef SSOCT_ADJ_NT
+#define SSOCT_ADJ_NT 0           // adjoint column pass: non-temporal stores of the intermediate the
+                                 // adjoint row pass reads back (a chunk sized to stay in MALL)
 #endif
 #ifndef SSOCT_ROW_WAVES_PER_EU
 #define SSOCT_ROW_WAVES_PER_EU 0  // > 0: ask the compiler to fit this many row-pass waves per SIMD
@@ -284,15 +288,15 @@ __device__ __forceinline__ uint32_t split_pack(float x) {
   }
 }
 
-template <int FMT>
+template <int FMT, int NT = SSOCT_COL_NT>
 __device__ __forceinline__ void store_h(void* __restrict__ H, long long idx, float2 val, float scale) {
   if constexpr (FMT == HF_F32) {
-    st_once<SSOCT_COL_NT>(reinterpret_cast<float2*>(H) + idx, val);
+    st_once<NT>(reinterpret_cast<float2*>(H) + idx, val);
   } else {
     uint2 w;
     w.x = split_pack<FMT>(val.x * scale);
     w.y = split_pack<FMT>(val.y * scale);
-    st_once<SSOCT_COL_NT>(reinterpret_cast<uint2*>(H) + idx, w);
+    st_once<NT>(reinterpret_cast<uint2*>(H) + idx, w);
   }
 }
 
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
       const int u = j + out_offset<N>(e);
       float2 val = v[e];
       if constexpr (EQ6) val = cmul(val, outfac[u]);
-      store_h<FMT>(dst, fo + (long long)u * N + col, val, scale);
+      store_h<FMT, (DIR > 0 ? SSOCT_COL_NT : SSOCT_ADJ_NT)>(dst, fo + (long long)u * N + col, val, scale);
     }
   }
 }

@@ -23,17 +23,21 @@ def small_case(T, N, seed):
     return frames, lam, rng.uniform(-2, 2, T), rng.normal(0, 0.4, 15)
 
 
-@pytest.mark.parametrize("T,N,exact,with_params", [(6, 32, False, True), (6, 32, True, True), (5, 64, False, False),
-                                                  (33, 128, True, True)])
-def test_vjp_random_cotangent(gpu_lib, T, N, exact, with_params):
+@pytest.mark.parametrize("T,N,exact,with_params,precision", [
+    (6, 32, False, True, "fp32"), (6, 32, True, True, "fp32"), (5, 64, False, False, "fp32"),
+    (33, 128, True, True, "fp32"),
+    # FFT-form plans run the adjoint depth transform as an inverse-direction radix FFT
+    (16, 32, False, True, "fp32_fft"), (32, 64, True, True, "fp32_fft"), (64, 16, False, False, "fp32_fft"),
+    (256, 32, False, True, "fp32_fft")])
+def test_vjp_random_cotangent(gpu_lib, T, N, exact, with_params, precision):
     from paper_2003_08960_amd.api import Plan
     frames, lam, phi, zc = small_case(T, N, seed=T * N)
     if not with_params:
         phi, zc = None, None
     rng = np.random.default_rng(9)
     G = (rng.standard_normal((T, N, N)) + 1j * rng.standard_normal((T, N, N))).astype(np.complex64)
-    print(f"\n[gpu] vjp T={T} N={N} exact={exact} params={with_params}", flush=True)
-    plan = Plan(T, N, backward=True, exact_chirp=exact)
+    print(f"\n[gpu] vjp T={T} N={N} exact={exact} params={with_params} {precision}", flush=True)
+    plan = Plan(T, N, backward=True, exact_chirp=exact, precision=precision)
     g = plan.backward(torch.from_numpy(frames).cuda(), lam, 20e-6, 0.05, torch.from_numpy(G).cuda(), phi, zc)
     g = g.cpu().numpy()
     dz, dc, dphi = O.vjp(frames, lam, 20e-6, 0.05, G.astype(np.complex128), phi, zc, exact)
@@ -49,7 +53,8 @@ def diff():
     return synth.make_config("diff")
 
 
-def test_sharpness_gradient_diff_workload(gpu_lib, diff):
+@pytest.mark.parametrize("precision", ["fp32", "fp32_fft"])
+def test_sharpness_gradient_diff_workload(gpu_lib, diff, precision):
     """T=128, N=512 with aberration and dispersion in the data; gradient at a random point."""
     from paper_2003_08960_amd.api import Plan
     T, N, _ = diff.frames.shape
@@ -57,8 +62,8 @@ def test_sharpness_gradient_diff_workload(gpu_lib, diff):
     zc = rng.normal(0, 0.3, 15)
     phi = rng.uniform(-1, 1, T)
     z = diff.z * 1.01
-    print(f"\n[gpu] sharpness T={T} N={N}", flush=True)
-    plan = Plan(T, N, backward=True)
+    print(f"\n[gpu] sharpness T={T} N={N} {precision}", flush=True)
+    plan = Plan(T, N, backward=True, precision=precision)
     fr = torch.from_numpy(diff.frames).cuda()
     g = plan.backward_sharpness(fr, diff.lam, diff.pitch, z, phi, zc).cpu().numpy()
     L, dz, dc, dphi = O.sharpness_grad(diff.frames, diff.lam, diff.pitch, z, phi, zc)
@@ -71,6 +76,28 @@ def test_sharpness_gradient_diff_workload(gpu_lib, diff):
     # global phase invariance holds for the GPU gradient too
     assert abs(np.sum(g[17:])) <= 1e-4 * np.max(np.abs(g[17:])) * np.sqrt(T)
     assert abs(g[2]) <= 1e-4 * np.max(np.abs(g[2:17]))
+
+
+def test_fft_and_dense_sharpness_agree_at_full_size(gpu_lib):
+    """Loss and gradient of the two depth forms at T=256, N=1024 (8192 FFT loss partials per call)."""
+    from paper_2003_08960_amd.api import Plan
+    T, N = 256, 1024
+    frames, lam, phi, zc = small_case(T, N, seed=6)
+    pitch, z = 20e-6, 0.3
+    fr = torch.from_numpy(frames).cuda()
+    print(f"\n[gpu] sharpness dense vs fft T={T} N={N}", flush=True)
+    out = {}
+    for prec in ("fp32", "fp32_fft"):
+        plan = Plan(T, N, backward=True, precision=prec)
+        out[prec] = plan.backward_sharpness(fr, lam, pitch, z, phi, zc).cpu().numpy()
+        plan.close()
+    a, b = out["fp32_fft"], out["fp32"]
+    print(f"L {a[0]:.9e} vs {b[0]:.9e}; dz {a[1]:.6e} vs {b[1]:.6e}; dc rel {rel(a[2:17], b[2:17]):.2e}; "
+          f"dphi rel {rel(a[17:], b[17:]):.2e}")
+    assert abs(a[0] - b[0]) <= 1e-5 * b[0]
+    assert abs(a[1] - b[1]) <= 1e-4 * abs(b[1])
+    assert rel(a[2:17], b[2:17]) <= 1e-4
+    assert rel(a[17:], b[17:]) <= 1e-4
 
 
 def test_sharpness_finite_difference_on_gpu(gpu_lib):

@@ -155,6 +155,20 @@ def test_deterministic_and_table_cache(gpu_lib, tiny):
     assert torch.equal(V1, V4)
 
 
+def test_zero_aberration_skips_the_screen(gpu_lib, tiny):
+    """All-zero Zernike coefficients give A = 1: bit-identical to no aberration, before and after a non-zero set."""
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = tiny.frames.shape
+    fr = torch.from_numpy(tiny.frames).cuda()
+    plan = Plan(T, N)
+    V0 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()
+    assert torch.equal(plan.render(fr, tiny.lam, tiny.pitch, tiny.z, None, np.zeros(15)), V0)
+    zc = np.random.default_rng(3).normal(0, 0.4, 15)
+    V1 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z, None, zc).clone()
+    assert rel_l2(V1.cpu().numpy(), O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, None, zc)) <= FP32_BAR
+    assert torch.equal(plan.render(fr, tiny.lam, tiny.pitch, tiny.z, None, -0.0 * zc), V0)
+
+
 def test_bad_arguments_raise(gpu_lib, tiny):
     from paper_2003_08960_amd import native
     from paper_2003_08960_amd.api import Plan
