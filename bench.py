@@ -45,13 +45,18 @@ def log(msg):
 
 
 def depth_products(form: str) -> int:
-    return 3 if form.endswith("_split") else 1
+    return 3 if form.removesuffix("_4step").endswith("_split") else 1
 
 
 def depth_flops(T: int, N: int, form: str) -> float:
     if form.endswith("_fft"):
         # nominal radix-FFT count: 5 T log2 T real flops per pixel
         return 5.0 * T * np.log2(T) * N * N
+    if form.endswith("_4step"):
+        # real-form products of the T/16-point and the 16-point DFT matrices, per product:
+        # (2 T2) x T2 x 16 x 4 + 32 x 16 x T2 x 4 real flops per pixel, T2 = T/16
+        T2 = T // 16
+        return (128.0 * T2 * T2 + 2048.0 * T2) * N * N * depth_products(form)
     # real form of the complex DFT matrix: 4 T^2 real flops per pixel per product
     return 4.0 * T * T * N * N * depth_products(form)
 
@@ -60,7 +65,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_08960_amd", "csrc")
     # device code only: the .hip kernels and the headers they include
-    for name in sorted(n for n in os.listdir(csrc) if n.endswith(".hip") or n in ("fft_engine.hpp", "internal.hpp")):
+    for name in sorted(n for n in os.listdir(csrc) if n.endswith(".hip") or (n.endswith(".hpp") and n != "plan.hpp")):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -134,7 +139,7 @@ def roofline(rec, form, T, N):
     sp = rec["fresnel_split_ms"]
     nch = -(-T // rec["tuning"]["frames_per_chunk"])
     prec = form.split("_")[0]
-    dname = "k_depth_fft" if form.endswith("_fft") else "k_depth"
+    dname = "k_depth_fft" if form.endswith("_fft") else ("k_depth_4step" if form.endswith("_4step") else "k_depth")
     # The per-launch events of the split pass add a gap after every launch; the
     # split is rescaled to the event-free Fresnel-stage time of the timed steps.
     scale = st["fresnel"] / (sp["row_pass"] + sp["col_pass"]) if sp["row_pass"] > 0 and sp["col_pass"] > 0 else 0.0
@@ -159,7 +164,8 @@ def roofline(rec, form, T, N):
         kernels[name] = k
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     k = kernels[dom]
-    if dom == "k_depth" and k["flops_per_launch"] / MFMA_PEAK[prec] >= k["bytes_per_launch"] / HBM_PEAK:
+    if dom in ("k_depth", "k_depth_4step") and \
+            k["flops_per_launch"] / MFMA_PEAK[prec] >= k["bytes_per_launch"] / HBM_PEAK:
         # a dense depth product in FP32 is bound by the MFMA rate, not by its 16 B/voxel
         roof = {"bound": "mfma", "achieved": k["achieved_tflop_s"], "peak": MFMA_PEAK[prec] / 1e12,
                 "unit": "TFLOP/s"}
@@ -494,7 +500,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp32,fp32_fft,fp16_split,bf16_split,fp16,bf16")
+    ap.add_argument("--forms", default="fp32,fp32_fft,fp32_4step,fp16_split,bf16_split,bf16_split_4step,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming form")
@@ -594,7 +600,7 @@ def main():
 
     def ok(f):
         r = forms[f]
-        return "rel_l2_sampled" not in r or r["rel_l2_sampled"] <= (FP32_BAR if f == "fp32" else SPLIT_BAR)
+        return "rel_l2_sampled" not in r or r["rel_l2_sampled"] <= (FP32_BAR if f.startswith("fp32") else SPLIT_BAR)
 
     eligible = [f for f in forms if ok(f)] or list(forms)
     head = max(eligible, key=lambda f: forms[f]["gvoxel_s"])
@@ -613,8 +619,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32" if head in ("fp32", "fp32_fft") else
-                  f"{prec}{'-split' if head.endswith('_split') else ''} depth DFT, f32 acc; f32 Fresnel stage"),
+        "dtype": ("f32" if head.startswith("fp32") else
+                  f"{prec}{'-split' if depth_products(head) == 3 else ''} depth DFT, f32 acc; f32 Fresnel stage"),
         "data": "synthetic",
         "config": {"workload": f"paper-shaped sweep: T={T} uint16 frames of {N}x{N}, 200 scatterers + speckle, "
                                "one rectangular depth gate of all frames, complex64 volume + 3 cuts",
@@ -630,7 +636,7 @@ def main():
         stream_form = "bf16_split" if "bf16_split" in forms else head
         out["streaming"] = bench_stream(sw, stream_form, paced=not args.no_paced)
     if not args.no_slide:
-        out["sliding"] = bench_slide(sw, head if head in ("fp32", "fp32_fft") else "fp32_fft",
+        out["sliding"] = bench_slide(sw, head if head.startswith("fp32") else "fp32_fft",
                                      paced=not args.no_paced)
     if not args.no_nonuniform:
         out["nonuniform_k"] = bench_nonuniform(sw, accuracy=not args.no_accuracy)

@@ -82,6 +82,10 @@ extern "C" {
                                       the uniform depth grid of a sweep not linear in k (dense forms only) */
 #define SSOCT_DEPTH_FFT 1024u     /* FP32 depth transform as a radix FFT along the sweep (T in {16..256},
                                       powers of two) instead of the dense DFT-matrix product */
+#define SSOCT_DEPTH_4STEP 8192u   /* depth transform of Eq. 7 factored as T = 16 (T/16): two small DFT-matrix
+                                      products on MFMA with a twiddle between them, in the precision the
+                                      other flags select (T in {32, 64, 128, 256}; not with SSOCT_DEPTH_FFT
+                                      or SSOCT_NONUNIFORM_K; gradients use the dense FP32 adjoint) */
 
 typedef struct ssoct_plan ssoct_plan;
 
@@ -176,7 +180,9 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  * Launch-shape parameters of a plan, int tuning[4]: tuning[0] frames per
  * chunk of the Fresnel stage (1 .. the chunk the workspace was sized for),
  * tuning[1] persistent column-pass workgroups (0 = default), tuning[2]
- * persistent depth-transform workgroups (0 = default), tuning[3] evaluation
+ * persistent workgroups of the dense depth transform (0 = default; the
+ * SSOCT_DEPTH_FFT and SSOCT_DEPTH_4STEP forms launch one workgroup per pixel
+ * tile and ignore it), tuning[3] evaluation
  * order of the SSOCT_DEPTH_FFT form (0 = default: Fresnel transform of every
  * frame, then the depth transform; 1 = depth transform of the rescaled real
  * frames first, then one Fresnel transform per bin, which by linearity is the

@@ -15,6 +15,12 @@ PRECISIONS = {
     "bf16": native.PREC_BF16,
     "fp16_split": native.PREC_FP16 | native.SPLIT,
     "bf16_split": native.PREC_BF16 | native.SPLIT,
+    # the depth transform factored 16 x T/16 on MFMA, per operand precision
+    "fp32_4step": native.PREC_FP32 | native.DEPTH_4STEP,
+    "fp16_4step": native.PREC_FP16 | native.DEPTH_4STEP,
+    "bf16_4step": native.PREC_BF16 | native.DEPTH_4STEP,
+    "fp16_split_4step": native.PREC_FP16 | native.SPLIT | native.DEPTH_4STEP,
+    "bf16_split_4step": native.PREC_BF16 | native.SPLIT | native.DEPTH_4STEP,
 }
 
 

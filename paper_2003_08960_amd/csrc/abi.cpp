@@ -316,6 +316,10 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
                                shift));
     return SSOCT_OK;
   }
+  if (p->flags & SSOCT_DEPTH_4STEP) {
+    SSOCT_HIP(launch_depth_4step(p->T, p->N * p->N, prec, epi, ws + L.H, p->dtw, vol, p->sigma, s, shift));
+    return SSOCT_OK;
+  }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
                          depth_grid_for(p), s, p->dtw, shift, p->general));
   return SSOCT_OK;
@@ -459,6 +463,10 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
     return fail(SSOCT_EINVAL, "SSOCT_NONUNIFORM_K needs the dense depth transform (no SSOCT_DEPTH_FFT)");
   if ((flags & SSOCT_DEPTH_FFT) && !depth_fft_supported(T))
     return fail(SSOCT_EUNSUPPORTED, "SSOCT_DEPTH_FFT needs T in {16, 32, 64, 128, 256}");
+  if ((flags & SSOCT_DEPTH_4STEP) && (flags & (SSOCT_DEPTH_FFT | SSOCT_NONUNIFORM_K)))
+    return fail(SSOCT_EINVAL, "SSOCT_DEPTH_4STEP excludes SSOCT_DEPTH_FFT and SSOCT_NONUNIFORM_K");
+  if ((flags & SSOCT_DEPTH_4STEP) && !depth_4step_supported(T))
+    return fail(SSOCT_EUNSUPPORTED, "SSOCT_DEPTH_4STEP needs T in {32, 64, 128, 256}");
   ssoct_plan* p = new (std::nothrow) ssoct_plan();
   if (!p) return fail(SSOCT_ENOMEM, "host allocation failed");
   p->T = T;

@@ -21,6 +21,7 @@
 // always with FP32 accumulation.
 #include "access.hpp"
 #include "internal.hpp"
+#include "mfma.hpp"
 
 #ifndef SSOCT_DEPTH_NT
 #define SSOCT_DEPTH_NT 0         // non-temporal loads of H and stores of the volume
@@ -28,33 +29,7 @@
 
 namespace ssoct {
 
-typedef float v16f __attribute__((ext_vector_type(16)));
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
 constexpr int PT = 32;  // pixels per tile
-
-template <int PREC>
-struct PrecTraits {
-  static constexpr bool F32 = PREC == DP_F32;
-  static constexpr bool SPLIT = PREC == DP_F16_SPLIT || PREC == DP_BF16_SPLIT;
-  static constexpr bool BF = PREC == DP_BF16 || PREC == DP_BF16_SPLIT;
-};
-
-template <bool BF>
-__device__ __forceinline__ v16f mfma_x16(uint4 a, uint4 b, v16f c) {
-  if constexpr (BF) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
-                                                   0, 0);
-  } else {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0,
-                                                  0);
-  }
-}
-
-// lo 16 bits of x0, x1 packed, and hi 16 bits packed
-__device__ __forceinline__ uint32_t pack_lo(uint32_t x0, uint32_t x1) { return __builtin_amdgcn_perm(x1, x0, 0x05040100u); }
-__device__ __forceinline__ uint32_t pack_hi(uint32_t x0, uint32_t x1) { return __builtin_amdgcn_perm(x1, x0, 0x07060302u); }
 
 template <int PREC, int KC, int WAVES, int DIR, int EPI>
 __global__ __launch_bounds__(WAVES * 64) void k_depth(const uint2* __restrict__ in, const void* __restrict__ amat,

@@ -1,0 +1,317 @@
+// Depth transform of Eq. 7 as a two-factor DFT on MFMA (T = 16 T2,
+// T2 = 2..16).  With t = t1 + 16 t2 and q = q2 + T2 q1,
+//   V[q2 + T2 q1] = sum_t1 W16[q1][t1] wT^(q2 t1) sum_t2 WT2[q2][t2] h[t1 + 16 t2],
+// W_n[a][b] = exp(-2 pi i a b / n), wT = exp(-2 pi i / T).  Each inner sum
+// is the product of a small DFT matrix in real form (row 2k = Re W[k],
+// row 2k + 1 = Im W[k], padded to 32 rows) with the stack viewed as reals,
+// on v_mfma_f32_32x32x2_f32 (FP32) or v_mfma_f32_32x32x16_{f16,bf16} (hi
+// only, or split hi*hi + hi*lo + lo*hi), always with FP32 accumulation:
+// 2 x 32 x (T2 + 16) x 16 x 2 flops per pixel (65536 at T = 256, 8x fewer
+// than the dense real-form product), so every precision is bound by the
+// 16 B/voxel of the stack and the volume.
+//
+// A workgroup (8 waves) owns 32 pixels and all T frames.  Stage A: each
+// wave takes 32-column MFMA tiles of columns (t1, pixel), K = t2, loading
+// its operands from HBM straight into registers (each half-wave load is 32
+// consecutive pixels of one frame); the products, times the twiddle
+// wT^(q2 t1), cross LDS once as [q2][t1][pixel] (split into hi/lo for the
+// 16-bit forms).  Stage B: tiles of columns (q2, pixel), K = t1; the
+// accumulator holds V for 32 consecutive pixels of each bin, written with
+// non-temporal stores.
+#include "access.hpp"
+#include "fft_engine.hpp"
+#include "internal.hpp"
+#include "mfma.hpp"
+#include "split.hpp"
+
+#ifndef SSOCT_F4_NT
+#define SSOCT_F4_NT 1            // non-temporal loads of H and stores of the volume (both touched once)
+#endif
+
+namespace ssoct {
+
+#ifndef SSOCT_F4_PX
+#define SSOCT_F4_PX 32           // pixels per tile: 128-byte (16) or 256-byte (32) rows of each frame
+#endif
+#ifndef SSOCT_F4_THREADS
+#define SSOCT_F4_THREADS 512     // workgroup size (waves take 32-column MFMA tiles in turn)
+#endif
+constexpr int F4_THREADS = SSOCT_F4_THREADS;
+constexpr int F4_PX = SSOCT_F4_PX;
+
+// element (row k, column lane) of the real-form DFT matrix of size n:
+// row 2a = Re W_n[a][k], row 2a + 1 = Im W_n[a][k]; zero outside a < n, k < n
+__device__ __forceinline__ double dft_real_form(int row, int k, int n) {
+  const int a = row >> 1;
+  if (a >= n || k >= n) return 0.0;
+  double s, c;
+  sincospi(-2.0 * (double)((a * k) % n) / (double)n, &s, &c);
+  return (row & 1) ? s : c;
+}
+
+// hi | lo << 16 of an FP64 value in FP16 or BF16 (hi = RNE(x), lo = RNE(x - hi))
+template <bool BF>
+__device__ __forceinline__ uint32_t split_pack64(double x) {
+  if constexpr (BF) {
+    const uint16_t h = bf16_rne((float)x);
+    const uint16_t l = bf16_rne((float)(x - (double)bf16_val(h)));
+    return (uint32_t)h | ((uint32_t)l << 16);
+  } else {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (double)(float)h);
+    return (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
+  }
+}
+
+// A operand of a 32x32x16 product for real-form rows `row` and k = k0..k0+7:
+// hi halves in hi, lo halves in lo
+template <bool BF>
+__device__ __forceinline__ void a_operand16(int row, int k0, int n, uint4& hi, uint4& lo) {
+  uint32_t p[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) p[i] = split_pack64<BF>(dft_real_form(row, k0 + i, n));
+  hi = make_uint4(pack_lo(p[0], p[1]), pack_lo(p[2], p[3]), pack_lo(p[4], p[5]), pack_lo(p[6], p[7]));
+  lo = make_uint4(pack_hi(p[0], p[1]), pack_hi(p[2], p[3]), pack_hi(p[4], p[5]), pack_hi(p[6], p[7]));
+}
+
+// acc_re/acc_im += A * (re, im of the 8 elements e) for the 16-bit forms
+template <int PREC>
+__device__ __forceinline__ void mfma16_step(const uint2 (&e)[8], uint4 ahi, uint4 alo, v16f& acc_re, v16f& acc_im) {
+  using PT_ = PrecTraits<PREC>;
+  uint4 re_hi, im_hi;
+  re_hi.x = pack_lo(e[0].x, e[1].x); re_hi.y = pack_lo(e[2].x, e[3].x);
+  re_hi.z = pack_lo(e[4].x, e[5].x); re_hi.w = pack_lo(e[6].x, e[7].x);
+  im_hi.x = pack_lo(e[0].y, e[1].y); im_hi.y = pack_lo(e[2].y, e[3].y);
+  im_hi.z = pack_lo(e[4].y, e[5].y); im_hi.w = pack_lo(e[6].y, e[7].y);
+  if constexpr (PT_::SPLIT) {
+    uint4 re_lo, im_lo;
+    re_lo.x = pack_hi(e[0].x, e[1].x); re_lo.y = pack_hi(e[2].x, e[3].x);
+    re_lo.z = pack_hi(e[4].x, e[5].x); re_lo.w = pack_hi(e[6].x, e[7].x);
+    im_lo.x = pack_hi(e[0].y, e[1].y); im_lo.y = pack_hi(e[2].y, e[3].y);
+    im_lo.z = pack_hi(e[4].y, e[5].y); im_lo.w = pack_hi(e[6].y, e[7].y);
+    acc_re = mfma_x16<PT_::BF>(alo, re_hi, acc_re);
+    acc_im = mfma_x16<PT_::BF>(alo, im_hi, acc_im);
+    acc_re = mfma_x16<PT_::BF>(ahi, re_lo, acc_re);
+    acc_im = mfma_x16<PT_::BF>(ahi, im_lo, acc_im);
+  }
+  acc_re = mfma_x16<PT_::BF>(ahi, re_hi, acc_re);
+  acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
+}
+
+// Per-lane A operands: the real-form T2-point (stage A) and 16-point (stage B) DFT matrices, row lc
+template <int T2, int PREC>
+struct AOps {
+  float a[PrecTraits<PREC>::F32 ? T2 / 2 : 1], b[PrecTraits<PREC>::F32 ? 8 : 1];
+  uint4 ahi, alo, bhi, blo;
+  __device__ __forceinline__ void init(int lc, int lh) {
+    if constexpr (PrecTraits<PREC>::F32) {
+#pragma unroll
+      for (int s = 0; s < T2 / 2; ++s) a[s] = (float)dft_real_form(lc, 2 * s + lh, T2);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) b[s] = (float)dft_real_form(lc, 2 * s + lh, 16);
+    } else {
+      a_operand16<PrecTraits<PREC>::BF>(lc, 8 * lh, T2, ahi, alo);
+      a_operand16<PrecTraits<PREC>::BF>(lc, 8 * lh, 16, bhi, blo);
+    }
+  }
+};
+
+// Stage-A products of column tile j times the twiddle wT^(q2 t1), into the [q2][t1][pixel] tile `dst`
+template <int T2, int PREC, int PX>
+__device__ __forceinline__ void stage_a_store(uint2* dst, int j, int lc, int lh, const v16f& ar, const v16f& ai,
+                                              const float2* __restrict__ wt, float mid_scale) {
+  constexpr int T = 16 * T2;
+  constexpr int HFMT = PrecTraits<PREC>::BF ? HF_BF16 : HF_F16;
+  const int t1 = (32 * j + lc) / PX, px = (32 * j + lc) % PX;
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const int q2 = (8 * (r >> 2) + 4 * lh + (r & 3)) >> 1;
+    if (q2 >= T2) continue;
+    const float2 a = make_float2(ar[r] - ai[r + 1], ai[r] + ar[r + 1]);
+    const float2 b = q2 == 0 ? a : cmul(a, wt[(q2 * t1) % T]);
+    uint2 v;
+    if constexpr (PrecTraits<PREC>::F32) {
+      v = make_uint2(__float_as_uint(b.x), __float_as_uint(b.y));
+    } else {
+      v = make_uint2(split_pack<HFMT>(b.x * mid_scale), split_pack<HFMT>(b.y * mid_scale));
+    }
+    dst[(q2 * 16 + t1) * PX + px] = v;
+  }
+}
+
+// Stage B for column tile j (columns 32 j + lc of (q2, pixel)) of the [q2][t1][pixel] tile `in`,
+// and the volume epilogue for pixels p0 + pixel
+template <int T2, int PREC, int EPI, int PX>
+__device__ __forceinline__ void stage_b(const uint2* in, int j, int lc, int lh, const AOps<T2, PREC>& A,
+                                        const float2* __restrict__ wt, void* __restrict__ out, int P, int p0,
+                                        float out_scale, int shift) {
+  constexpr int T = 16 * T2;
+  const int q2 = (32 * j + lc) / PX, px = (32 * j + lc) % PX;
+  v16f br, bi;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    br[r] = 0.f;
+    bi[r] = 0.f;
+  }
+  if constexpr (PrecTraits<PREC>::F32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const uint2 b = in[(q2 * 16 + 2 * s + lh) * PX + px];
+      br = __builtin_amdgcn_mfma_f32_32x32x2f32(A.b[s], __uint_as_float(b.x), br, 0, 0, 0);
+      bi = __builtin_amdgcn_mfma_f32_32x32x2f32(A.b[s], __uint_as_float(b.y), bi, 0, 0, 0);
+    }
+  } else {
+    uint2 e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) e[i] = in[(q2 * 16 + 8 * lh + i) * PX + px];
+    mfma16_step<PREC>(e, A.bhi, A.blo, br, bi);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const int q1 = (8 * (r >> 2) + 4 * lh + (r & 3)) >> 1;
+    const int q = q2 + T2 * q1;
+    float2 V = make_float2((br[r] - bi[r + 1]) * out_scale, (bi[r] + br[r + 1]) * out_scale);
+    const size_t idx = (size_t)q * P + p0 + px;
+    if constexpr (EPI == EPI_ABS) {
+      st_once<SSOCT_F4_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(V.x * V.x + V.y * V.y));
+    } else {
+      if (shift != 0) V = cmulc(V, wt[(q * shift) % T]);   // window starting `shift` slots into a ring
+      st_once<SSOCT_F4_NT>(reinterpret_cast<float2*>(out) + idx, V);
+    }
+  }
+}
+
+template <int T2, int PX>
+struct F4Shape {
+  static constexpr int T = 16 * T2;
+  static constexpr int NW = F4_THREADS / 64;
+  static constexpr int TA = 16 * PX / 32;                       // stage-A column tiles (t1, pixel)
+  static constexpr int TB = (T2 * PX + 31) / 32;                // stage-B column tiles (q2, pixel)
+  static constexpr int TA_W = (TA + NW - 1) / NW, TB_W = (TB + NW - 1) / NW;
+  static_assert(PX == 16 || PX == 32, "16 or 32 pixels per tile");
+  static_assert(T2 >= 2 && T2 <= 16, "T = 32 .. 256");
+};
+
+// Stage-A operands of column tile j loaded straight from the stack: lane
+// (lc, lh) takes frame t1 + 16 t2 at pixel p0 + px for its k values, so each
+// half-wave load is PX consecutive pixels of one frame.
+template <int T2, int PREC, int PX>
+__device__ __forceinline__ void load_stage_a(const uint2* __restrict__ H, int P, int p0, int j, int lc, int lh,
+                                             uint2 (&e)[8]) {
+  const int t1 = (32 * j + lc) / PX, px = (32 * j + lc) % PX;
+  const uint2* src = H + p0 + px;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    // FP32: k = 2 i + lh (i < T2/2); 16-bit: k = 8 lh + i (k < T2)
+    const int t2 = PrecTraits<PREC>::F32 ? 2 * i + lh : 8 * lh + i;
+    const bool ok = PrecTraits<PREC>::F32 ? i < T2 / 2 : t2 < T2;
+    e[i] = ok ? ld_once<SSOCT_F4_NT>(src + (size_t)(t1 + 16 * t2) * P) : make_uint2(0u, 0u);
+  }
+}
+
+template <int T2, int PREC>
+__device__ __forceinline__ void stage_a_regs(const uint2 (&e)[8], const AOps<T2, PREC>& A, v16f& ar, v16f& ai) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    ar[r] = 0.f;
+    ai[r] = 0.f;
+  }
+  if constexpr (PrecTraits<PREC>::F32) {
+#pragma unroll
+    for (int s = 0; s < T2 / 2; ++s) {
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[s], __uint_as_float(e[s].x), ar, 0, 0, 0);
+      ai = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[s], __uint_as_float(e[s].y), ai, 0, 0, 0);
+    }
+  } else {
+    mfma16_step<PREC>(e, A.ahi, A.alo, ar, ai);
+  }
+}
+
+// One workgroup per tile of PX pixels and all T frames: the stage-A
+// operands go from HBM to registers, the stage-A products cross LDS once,
+// stage B writes the volume.
+template <int T2, int PREC, int EPI>
+__global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restrict__ H,
+                                                                   const float2* __restrict__ wt,
+                                                                   void* __restrict__ out, int P, float mid_scale,
+                                                                   float out_scale, int shift) {
+  constexpr int PX = F4_PX;
+  using S = F4Shape<T2, PX>;
+  __shared__ uint2 buf[S::T * PX];   // [q2][t1][pixel]
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lc = l & 31, lh = l >> 5;
+  const int p0 = blockIdx.x * PX;    // grid = P / PX
+  uint2 e[S::TA_W][8];
+#pragma unroll
+  for (int jj = 0; jj < S::TA_W; ++jj) {
+    const int j = w + S::NW * jj;
+    if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, e[jj]);
+  }
+  AOps<T2, PREC> A;
+  A.init(lc, lh);
+#pragma unroll
+  for (int jj = 0; jj < S::TA_W; ++jj) {
+    const int j = w + S::NW * jj;
+    if (j >= S::TA) break;
+    v16f ar, ai;
+    stage_a_regs<T2, PREC>(e[jj], A, ar, ai);
+    stage_a_store<T2, PREC, PX>(buf, j, lc, lh, ar, ai, wt, mid_scale);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < S::TB_W; ++jj) {
+    const int j = w + S::NW * jj;
+    if (j < S::TB) stage_b<T2, PREC, EPI, PX>(buf, j, lc, lh, A, wt, out, P, p0, out_scale, shift);
+  }
+}
+
+template <int T2, int PREC, int EPI>
+static hipError_t go_4step(int P, const void* H, const float2* wt, void* out, float mid, float os, int shift,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((k_depth_4step<T2, PREC, EPI>), dim3(P / F4_PX), dim3(F4_THREADS), 0, s,
+                     reinterpret_cast<const uint2*>(H), wt, out, P, mid, os, shift);
+  return hipGetLastError();
+}
+
+template <int T2, int PREC>
+static hipError_t go_4step_epi(int epi, int P, const void* H, const float2* wt, void* out, float mid, float os,
+                               int shift, hipStream_t s) {
+  if (epi == EPI_ABS) return go_4step<T2, PREC, EPI_ABS>(P, H, wt, out, mid, os, shift, s);
+  return go_4step<T2, PREC, EPI_STORE>(P, H, wt, out, mid, os, shift, s);
+}
+
+template <int T2>
+static hipError_t go_4step_prec(int prec, int epi, int P, const void* H, const float2* wt, void* out, float mid,
+                                float os, int shift, hipStream_t s) {
+  switch (prec) {
+    case DP_F32: return go_4step_epi<T2, DP_F32>(epi, P, H, wt, out, mid, os, shift, s);
+    case DP_F16: return go_4step_epi<T2, DP_F16>(epi, P, H, wt, out, mid, os, shift, s);
+    case DP_BF16: return go_4step_epi<T2, DP_BF16>(epi, P, H, wt, out, mid, os, shift, s);
+    case DP_F16_SPLIT: return go_4step_epi<T2, DP_F16_SPLIT>(epi, P, H, wt, out, mid, os, shift, s);
+    case DP_BF16_SPLIT: return go_4step_epi<T2, DP_BF16_SPLIT>(epi, P, H, wt, out, mid, os, shift, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool depth_4step_supported(int T) { return T == 32 || T == 64 || T == 128 || T == 256; }
+
+hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, void* out,
+                              int sigma, hipStream_t s, int shift) {
+  if (P <= 0) return hipSuccess;
+  if (P % F4_PX != 0 || (epi != EPI_STORE && epi != EPI_ABS) || (epi == EPI_ABS && shift != 0))
+    return hipErrorInvalidValue;
+  const int T2 = T / 16;
+  // FP16 stage-B operands: the stage-A sums grow by up to T2, scaled back by an exact power of two
+  const bool f16 = prec == DP_F16 || prec == DP_F16_SPLIT;
+  const float mid = f16 ? 1.0f / (float)T2 : 1.0f;
+  const float os = ldexpf(f16 ? (float)T2 : 1.0f, sigma);
+  switch (T) {
+    case 32: return go_4step_prec<2>(prec, epi, P, H, wt, out, mid, os, shift, s);
+    case 64: return go_4step_prec<4>(prec, epi, P, H, wt, out, mid, os, shift, s);
+    case 128: return go_4step_prec<8>(prec, epi, P, H, wt, out, mid, os, shift, s);
+    case 256: return go_4step_prec<16>(prec, epi, P, H, wt, out, mid, os, shift, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ssoct

@@ -142,6 +142,13 @@ hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, con
                             hipStream_t s, int shift = 0, int gamma_exp = 0, double* partials = nullptr);
 hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 
+// Depth transform as a two-factor (16 x T/16) DFT on MFMA, forward only, in
+// any operand precision (H in the format of that precision, scaled by
+// 2^-sigma for FP16); epi EPI_STORE (with the ring shift) or EPI_ABS.
+bool depth_4step_supported(int T);
+hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, void* out,
+                              int sigma, hipStream_t s, int shift = 0);
+
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,
                        float* cut_xy, float* cut_xz, float* cut_yz, hipStream_t s);
 

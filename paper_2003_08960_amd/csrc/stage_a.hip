@@ -16,6 +16,7 @@
 #include "access.hpp"
 #include "fft_engine.hpp"
 #include "internal.hpp"
+#include "split.hpp"
 
 namespace ssoct {
 
@@ -267,27 +268,6 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
 }
 
 // ------------------------------------------------------------------ H storage formats
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// hi + lo split of one real value, packed as hi | lo << 16
-template <int FMT>
-__device__ __forceinline__ uint32_t split_pack(float x) {
-  if constexpr (FMT == HF_F16) {
-    const _Float16 h = (_Float16)x;
-    const _Float16 l = (_Float16)(x - (float)h);
-    return (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
-  } else {
-    const uint16_t h = bf16_rne(x);
-    const uint16_t l = bf16_rne(x - bf16_val(h));
-    return (uint32_t)h | ((uint32_t)l << 16);
-  }
-}
-
 template <int FMT, int NT = SSOCT_COL_NT>
 __device__ __forceinline__ void store_h(void* __restrict__ H, long long idx, float2 val, float scale) {
   if constexpr (FMT == HF_F32) {

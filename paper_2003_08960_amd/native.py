@@ -37,6 +37,7 @@ PROFILE_KERNELS = 512
 DEPTH_FFT = 1024
 NONUNIFORM_K = 2048
 ANGULAR_SPECTRUM = 4096
+DEPTH_4STEP = 8192
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",

@@ -77,6 +77,11 @@ def test_plan_create_rejects_bad_sizes(lib):
     assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, fft | native.NONUNIFORM_K, None) == native.EINVAL
     for f in (native.EQ6_PHASE, native.CHIRP_EXACT):
         assert lib.ssoct_plan_create(ctypes.byref(h), 16, 64, native.ANGULAR_SPECTRUM | f, None) == native.EINVAL
+    f4 = native.DEPTH_4STEP
+    for T in (16, 48, 512):
+        assert lib.ssoct_plan_create(ctypes.byref(h), T, 64, f4, None) == native.EUNSUPPORTED
+    assert lib.ssoct_plan_create(ctypes.byref(h), 64, 64, f4 | fft, None) == native.EINVAL
+    assert lib.ssoct_plan_create(ctypes.byref(h), 64, 64, f4 | native.NONUNIFORM_K, None) == native.EINVAL
     assert not h.value
     g = (ctypes.c_double * 4)(1, 1, 1, 1)
     assert lib.ssoct_plan_set_gate(None, g) == native.EINVAL

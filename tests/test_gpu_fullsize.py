@@ -26,7 +26,8 @@ def case():
 
 
 @pytest.mark.parametrize("precision,bar", [("fp32_fft", 1e-5), ("fp32", 1e-5), ("bf16_split", 1e-4),
-                                           ("fp16_split", 1e-4)])
+                                           ("fp16_split", 1e-4), ("fp32_4step", 1e-5), ("bf16_split_4step", 1e-4),
+                                           ("fp16_split_4step", 1e-4)])
 def test_paper_size_sampled_columns(gpu_lib, case, precision, bar):
     from paper_2003_08960_amd.api import Plan
     frames, lam, ref, e_j = case

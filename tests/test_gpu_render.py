@@ -192,7 +192,10 @@ def test_bad_arguments_raise(gpu_lib, tiny):
 # ---------------------------------------------------------------- mid workload (T=128, N=512)
 
 @pytest.mark.parametrize("precision,bar", [("fp32", FP32_BAR), ("fp32_fft", FP32_BAR), ("fp16_split", SPLIT_BAR),
-                                           ("bf16_split", SPLIT_BAR), ("fp16", PLAIN_SANITY), ("bf16", PLAIN_SANITY)])
+                                           ("bf16_split", SPLIT_BAR), ("fp16", PLAIN_SANITY), ("bf16", PLAIN_SANITY),
+                                           ("fp32_4step", FP32_BAR), ("fp16_split_4step", SPLIT_BAR),
+                                           ("bf16_split_4step", SPLIT_BAR), ("fp16_4step", PLAIN_SANITY),
+                                           ("bf16_4step", PLAIN_SANITY)])
 def test_mid_precisions(gpu_lib, mid, precision, bar):
     _, _, V = gpu_render(mid.frames, mid.lam, mid.pitch, mid.z, precision=precision)
     ref = _mid_ref(mid)
@@ -333,3 +336,55 @@ def test_depth_first_large_frames(gpu_lib, T, N):
     err = rel_l2(got, ref)
     print(f"T={T} N={N} sampled rel-L2 {err:.3e}")
     assert err <= FP32_BAR
+
+
+# ---------------------------------------------------------------- factored (16 x T/16) MFMA depth transform
+
+FOURSTEP = [("fp32_4step", FP32_BAR), ("fp16_split_4step", SPLIT_BAR), ("bf16_split_4step", SPLIT_BAR),
+            ("fp16_4step", PLAIN_SANITY), ("bf16_4step", PLAIN_SANITY)]
+
+
+@pytest.mark.parametrize("precision,bar", FOURSTEP)
+@pytest.mark.parametrize("T,N", [(32, 64), (64, 32), (128, 16), (256, 32)])
+def test_4step_every_supported_length(gpu_lib, T, N, precision, bar):
+    """Every T the factored form takes (T2 = T/16 = 2, 4, 8, 16), several 16-pixel tiles per workgroup."""
+    from paper_2003_08960_amd.api import Plan
+    frames, lam = random_case(T, N, seed=7 * T + N)
+    print(f"\n[gpu] 4-step depth T={T} N={N} {precision}", flush=True)
+    plan = Plan(T, N, precision=precision)
+    V = plan.render(torch.from_numpy(frames).cuda(), lam, 20e-6, 0.05)
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"T={T} N={N} {precision} rel-L2 {err:.3e}")
+    assert err <= bar
+
+
+def test_4step_options_abs_and_agreement_with_fft(gpu_lib, tiny):
+    """Dispersion, aberration, Eq. 6 phase and the |V| output through the factored form; equal to the FFT form."""
+    from paper_2003_08960_amd.api import Plan
+    T, N, _ = tiny.frames.shape
+    rng = np.random.default_rng(12)
+    disp = rng.normal(0, 1.0, T)
+    zern = rng.normal(0, 0.3, 15)
+    ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+    fr = torch.from_numpy(tiny.frames).cuda()
+    for prec, bar in (("fp32_4step", FP32_BAR), ("bf16_split_4step", SPLIT_BAR)):
+        V = Plan(T, N, precision=prec).render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+        assert rel_l2(V.cpu().numpy(), ref) <= bar
+        M = Plan(T, N, precision=prec, write_abs=True).render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+        assert rel_l2(M.cpu().numpy(), np.abs(ref)) <= bar
+    ref6 = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z, disp, zern, eq6_phase=True)
+    V6 = Plan(T, N, precision="fp16_split_4step", eq6_phase=True).render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+    assert rel_l2(V6.cpu().numpy(), ref6) <= SPLIT_BAR
+    Vf = Plan(T, N, precision="fp32_fft").render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+    V4 = Plan(T, N, precision="fp32_4step").render(fr, tiny.lam, tiny.pitch, tiny.z, disp, zern)
+    assert rel_l2(V4.cpu().numpy(), Vf.cpu().numpy()) <= 2e-6
+
+
+def test_4step_rejections(gpu_lib):
+    from paper_2003_08960_amd.api import Plan
+    for T in (16, 48, 512):
+        with pytest.raises(native.SsoctError):
+            Plan(T, 32, precision="fp32_4step")
+    with pytest.raises(native.SsoctError):
+        Plan(64, 32, precision="fp32_4step", nonuniform_k=True)

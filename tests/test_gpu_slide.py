@@ -57,7 +57,8 @@ def run_host_fed(plan, frames, lam, hop, disp=None, zern=None, chunk=None):
     return out
 
 
-@pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("fp32_fft", 1e-5), ("bf16_split", 1e-4)])
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("fp32_fft", 1e-5), ("bf16_split", 1e-4),
+                                           ("fp32_4step", 1e-5), ("bf16_split_4step", 1e-4)])
 def test_every_window_matches_the_oracle(gpu_lib, stream_frames, precision, bar):
     from paper_2003_08960_amd.api import Plan
     frames, lam = stream_frames
