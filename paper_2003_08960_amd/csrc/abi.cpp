@@ -313,7 +313,7 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
   if (p->flags & SSOCT_DEPTH_FFT) {
     SSOCT_HIP(launch_depth_fft(p->T, p->N * p->N, +1, epi, reinterpret_cast<const float2*>(ws + L.H), p->dtw, vol, s,
-                               shift));
+                               shift, 0, nullptr, depth_fft_grid(p->cu)));
     return SSOCT_OK;
   }
   if (p->flags & SSOCT_DEPTH_4STEP) {
@@ -403,7 +403,8 @@ static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, c
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   double* mono = reinterpret_cast<double*>(ws + L.mono);
   if (p->flags & SSOCT_DEPTH_FFT)
-    SSOCT_HIP(launch_depth_fft(T, N * N, -1, EPI_STORE, static_cast<const float2*>(G), p->dtw, beta, p->stream));
+    SSOCT_HIP(launch_depth_fft(T, N * N, -1, EPI_STORE, static_cast<const float2*>(G), p->dtw, beta, p->stream, 0, 0,
+                               nullptr, depth_fft_grid(p->cu)));
   else
     SSOCT_HIP(launch_depth(T, N * N, DP_F32, -1, EPI_STORE, G, p->a_f32, beta, 0, 0, nullptr, depth_grid_for(p),
                            p->stream));

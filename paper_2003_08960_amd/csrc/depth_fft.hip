@@ -22,22 +22,20 @@ namespace ssoct {
 #ifndef SSOCT_XCDS
 #define SSOCT_XCDS 8             // accelerator complex dies of an MI355X (one L2 each)
 #endif
+#ifndef SSOCT_DFFT_WGCU
+#define SSOCT_DFFT_WGCU 0        // > 0: that many resident workgroups per CU walk the tiles; 0: one per tile
+#endif
 #ifndef SSOCT_DFFT_NT
 #define SSOCT_DFFT_NT 1          // non-temporal loads of H and stores of the volume (both touched once)
 #endif
 
-template <int T2, int DIR, int EPI, int PX>
-__global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict__ H, const float2* __restrict__ wt,
-                                                        void* __restrict__ out, int P, int shift, float gamma_scale,
-                                                        double* __restrict__ loss_partials) {
+// stage A for the tile of pixels base..base+PX-1: DFT over t2 of h[r + 16 t2],
+// times the twiddles, into lds as [q2][t1][px]
+template <int T2, int DIR, int PX>
+__device__ __forceinline__ void fft_stage_a(const float2* __restrict__ H, const float2* __restrict__ wt, float2* lds,
+                                            int P, int base, int px, int r, bool live) {
   constexpr int T = 16 * T2;
   constexpr int ED = -DIR;           // engine sign: forward depth DFT has exponent -2 pi i q t / T
-  __shared__ float2 lds[T * PX];     // [q2][t1][px]
-  const int px = threadIdx.x % PX, r = threadIdx.x / PX;   // r = t1 in stage A, q2 in stage B
-  const int base = blockIdx.x * PX;
-  const bool live = base + px < P;
-
-  // stage A: DFT over t2 of h[r + 16 t2]
   float2 a[T2];
 #pragma unroll
   for (int t2 = 0; t2 < T2; ++t2)
@@ -49,55 +47,95 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
     if constexpr (DIR < 0) w = cconj(w);
     lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], w);
   }
-  __syncthreads();
-  if constexpr (EPI == EPI_GAMMA) {
-    // sharpness loss: every thread stays for the workgroup's loss reduction
-    double loss = 0.0;
-    if (r < T2 && live) {
+}
+
+// stage B for bin column q2 = r: 16-point DFT over t1 of the LDS tile
+template <int T2, int DIR, int PX>
+__device__ __forceinline__ void fft_stage_b(const float2* lds, int px, int r, float2 (&b)[16]) {
+#pragma unroll
+  for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+  dft16<-DIR>(b);
+}
+
+// EPI_STORE / EPI_ABS: workgroups walk the PX-pixel tiles with stride
+// gridDim.x (one tile each when the grid covers them all).
+template <int T2, int DIR, int EPI, int PX>
+__global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict__ H, const float2* __restrict__ wt,
+                                                        void* __restrict__ out, int P_, int shift) {
+  constexpr int T = 16 * T2;
+  __shared__ float2 lds[T * PX];     // [q2][t1][px]
+  const int px = threadIdx.x % PX, r_ = threadIdx.x / PX;   // r = t1 in stage A, q2 in stage B
+  const int ntiles = (P_ + PX - 1) / PX;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int P = P_, r = r_;
+    if (SSOCT_DFFT_WGCU > 0) {
+      if (tile != (int)blockIdx.x) __syncthreads();   // the previous tile's stage-B reads are done
+      // P and r opaque per tile: their offset and twiddle products are recomputed,
+      // not held in registers across the loop
+      asm volatile("" : "+s"(P));
+      asm volatile("" : "+v"(r));
+    }
+    const int base = tile * PX;
+    const bool live = base + px < P;
+    fft_stage_a<T2, DIR, PX>(H, wt, lds, P, base, px, r, live);
+    __syncthreads();
+    if (r < T2) {
       float2 b[16];
+      fft_stage_b<T2, DIR, PX>(lds, px, r, b);
+      if (live) {
 #pragma unroll
-      for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
-      dft16<ED>(b);
-#pragma unroll
-      for (int q1 = 0; q1 < 16; ++q1) {
-        const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
-        const double a2 = (double)b[q1].x * b[q1].x + (double)b[q1].y * b[q1].y;
-        loss += a2 * a2;
-        // Gamma = 4 |V~|^2 V~ with V~ = V 2^-e, finite in FP32
-        const float sx = b[q1].x * gamma_scale, sy = b[q1].y * gamma_scale;
-        const float m2 = 4.0f * (sx * sx + sy * sy);
-        reinterpret_cast<float2*>(out)[idx] = make_float2(m2 * sx, m2 * sy);
+        for (int q1 = 0; q1 < 16; ++q1) {
+          const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
+          if constexpr (EPI == EPI_ABS)
+            st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
+          else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
+            st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
+          else
+            st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
+        }
       }
     }
-    __shared__ double red[16 * PX / 64];
-    for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
-    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = loss;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sum = 0.0;
-      for (int i = 0; i < 16 * PX / 64; ++i) sum += red[i];
-      loss_partials[blockIdx.x] = sum;
-    }
-    return;
-  } else {
-    if (r >= T2) return;
+    if (SSOCT_DFFT_WGCU == 0) break;   // one tile per workgroup
+  }
+}
 
-    // stage B: DFT over t1 for bin column q2 = r
+// EPI_GAMMA (forward): Gamma = 4 |V~|^2 V~ with V~ = V 2^-e and one FP64
+// partial of sum |V|^4 per workgroup, one tile per workgroup.
+template <int T2, int PX>
+__global__ __launch_bounds__(16 * PX) void k_depth_fft_gamma(const float2* __restrict__ H,
+                                                              const float2* __restrict__ wt, float2* __restrict__ out,
+                                                              int P, float gamma_scale,
+                                                              double* __restrict__ loss_partials) {
+  constexpr int T = 16 * T2;
+  __shared__ float2 lds[T * PX];
+  __shared__ double red[16 * PX / 64];
+  const int px = threadIdx.x % PX, r = threadIdx.x / PX;
+  const int base = blockIdx.x * PX;
+  const bool live = base + px < P;
+  fft_stage_a<T2, +1, PX>(H, wt, lds, P, base, px, r, live);
+  __syncthreads();
+  double loss = 0.0;   // every thread stays for the workgroup's loss reduction
+  if (r < T2 && live) {
     float2 b[16];
-#pragma unroll
-    for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
-    dft16<ED>(b);
-    if (!live) return;
+    fft_stage_b<T2, +1, PX>(lds, px, r, b);
 #pragma unroll
     for (int q1 = 0; q1 < 16; ++q1) {
       const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
-      if constexpr (EPI == EPI_ABS)
-        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
-      else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
-        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
-      else
-        st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
+      const double a2 = (double)b[q1].x * b[q1].x + (double)b[q1].y * b[q1].y;
+      loss += a2 * a2;
+      const float sx = b[q1].x * gamma_scale, sy = b[q1].y * gamma_scale;
+      const float m2 = 4.0f * (sx * sx + sy * sy);
+      out[idx] = make_float2(m2 * sx, m2 * sy);
     }
+  }
+  for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = loss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < 16 * PX / 64; ++i) sum += red[i];
+    loss_partials[blockIdx.x] = sum;
   }
 }
 
@@ -302,22 +340,28 @@ hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTa
 
 template <int T2, int DIR, int EPI>
 static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, int shift, float gs,
-                              double* partials, hipStream_t s) {
+                              double* partials, int grid, hipStream_t s) {
   constexpr int PX = SSOCT_DFFT_PX;
-  hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3((P + PX - 1) / PX), dim3(16 * PX), 0, s, H, wt, out, P,
-                     shift, gs, partials);
+  const int ntiles = (P + PX - 1) / PX;
+  if constexpr (EPI == EPI_GAMMA) {
+    hipLaunchKernelGGL((k_depth_fft_gamma<T2, PX>), dim3(ntiles), dim3(16 * PX), 0, s, H, wt,
+                       static_cast<float2*>(out), P, gs, partials);
+  } else {
+    const int g = grid > 0 && grid < ntiles ? grid : ntiles;
+    hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3(g), dim3(16 * PX), 0, s, H, wt, out, P, shift);
+  }
   return hipGetLastError();
 }
 
 template <int DIR, int EPI>
 static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, int shift, float gs,
-                              double* partials, hipStream_t s) {
+                              double* partials, int grid, hipStream_t s) {
   switch (T) {
-    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
-    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
-    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
-    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
-    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, gs, partials, s);
+    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
+    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
+    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
+    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
+    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -326,19 +370,21 @@ bool depth_fft_supported(int T) { return T == 16 || T == 32 || T == 64 || T == 1
 
 int depth_fft_blocks(int P) { return (P + SSOCT_DFFT_PX - 1) / SSOCT_DFFT_PX; }
 
+int depth_fft_grid(int cu_count) { return SSOCT_DFFT_WGCU > 0 ? SSOCT_DFFT_WGCU * cu_count : 0; }
+
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s, int shift, int gamma_exp, double* partials) {
+                            hipStream_t s, int shift, int gamma_exp, double* partials, int grid) {
   if (P <= 0) return hipSuccess;
   if (dir > 0) {
-    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, 1.f, nullptr, s);
+    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, 1.f, nullptr, grid, s);
     if (epi == EPI_GAMMA) {
       if (!partials || shift != 0) return hipErrorInvalidValue;
-      return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, s);
+      return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, 0, s);
     }
-    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, 1.f, nullptr, s);
+    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, 1.f, nullptr, grid, s);
   }
   if (epi != EPI_STORE || shift != 0) return hipErrorInvalidValue;
-  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, 1.f, nullptr, s);
+  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, 1.f, nullptr, grid, s);
 }
 
 // wt[k] = exp(-2 pi i k / T), k = 0..T-1, from FP64 (sincospi) rounded to FP32

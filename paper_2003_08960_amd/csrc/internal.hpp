@@ -136,10 +136,14 @@ int depth_grid(int T, int P, int cu_count, bool general = false);
 // epi: EPI_STORE (complex64), EPI_ABS or EPI_GAMMA (forward only; the latter
 // writes Gamma = 4 |V 2^-gamma_exp|^2 V 2^-gamma_exp and one FP64 partial of
 // sum |V|^4 per workgroup, depth_fft_blocks(P) of them).  wt: exp(-2 pi i k/T).
+// grid: workgroups of the EPI_STORE / EPI_ABS kernels walking the tiles
+// (0 = one per tile; depth_fft_grid(cu) gives the tuned value).
 bool depth_fft_supported(int T);
 int depth_fft_blocks(int P);
+int depth_fft_grid(int cu_count);
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s, int shift = 0, int gamma_exp = 0, double* partials = nullptr);
+                            hipStream_t s, int shift = 0, int gamma_exp = 0, double* partials = nullptr,
+                            int grid = 0);
 hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 
 // Depth transform as a two-factor (16 x T/16) DFT on MFMA, forward only, in
