@@ -225,6 +225,28 @@ def test_stream_with_fft_depth_form(gpu_lib, sweeps):
     st.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16_split_4step", "fp32_4step"])
+def test_stream_with_factored_depth_form(gpu_lib, sweeps, precision):
+    """The factored MFMA form inside the per-slot graphs: every volume bitwise equal to an eager render."""
+    from paper_2003_08960_amd.api import Plan, Stream
+    plan = Plan(T, N, precision=precision)
+    refs = [eager(plan, s) for s in sweeps[:3]]
+    sw = sweeps[0]
+    st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=3)
+    allframes = np.concatenate([s.frames for s in sweeps[:3]])
+    for j in range(0, allframes.shape[0], 7):
+        assert st.push_frames(np.ascontiguousarray(allframes[j:j + 7]), j) == native.OK
+    got = 0
+    while True:
+        r = st.pop(wait=True)
+        if r is None:
+            break
+        assert torch.equal(st.slot_volume(r["slot"]), refs[r["seq"]][0])
+        got += 1
+    assert got == 3 and st.stats()["dropped_sweeps"] == 0
+    st.close()
+
+
 def test_binding_guards(gpu_lib, sweeps):
     """Buffers of the wrong shape, dtype or device are refused before any launch, and a plan cannot
     be released while a stream uses it."""
