@@ -85,7 +85,7 @@ extern "C" {
 #define SSOCT_DEPTH_4STEP 8192u   /* depth transform of Eq. 7 factored as T = 16 (T/16): two small DFT-matrix
                                       products on MFMA with a twiddle between them, in the precision the
                                       other flags select (T in {32, 64, 128, 256}; not with SSOCT_DEPTH_FFT
-                                      or SSOCT_NONUNIFORM_K; gradients use the dense FP32 adjoint) */
+                                      or SSOCT_NONUNIFORM_K) */
 
 typedef struct ssoct_plan ssoct_plan;
 
@@ -142,9 +142,9 @@ int ssoct_cuts(ssoct_plan* plan, const void* vol, int x0, int y0, int q0, float*
  * convention G = 2 dL/d conj(V)).  Writes device double grad_out[2 + 15 + T]:
  * [0] = 0, [1] = dL/dz, [2..16] = dL/dc_j, [17..17+T) = dL/dphi_t.
  * The forward transform is not needed: the rescaled, chirped frames are
- * recomputed inside the adjoint.  Any precision (the adjoint always runs in
- * FP32: a plan with SSOCT_DEPTH_FFT takes the adjoint depth transform as a
- * radix FFT, any other plan as the dense FP32 product); a workspace sized with
+ * recomputed inside the adjoint.  Any precision and depth form (the adjoint
+ * always runs in FP32: its depth transforms are radix FFTs for T in {16, 32,
+ * 64, 128, 256}, else dense FP32 products); a workspace sized with
  * SSOCT_BACKWARD; SSOCT_EQ6_PHASE is not supported (SSOCT_EUNSUPPORTED). */
 int ssoct_backward(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                    const double* disp_phase, const double* zernike, const void* grad_vol, void* workspace,

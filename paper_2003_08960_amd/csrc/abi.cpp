@@ -396,13 +396,17 @@ int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, 
   return SSOCT_OK;
 }
 
+// The gradient runs in FP32 whatever the plan's depth form: as radix FFTs
+// along the sweep when T allows, else as the dense FP32 product.
+static bool adjoint_by_fft(const ssoct_plan* p) { return depth_fft_supported(p->T) && !p->general; }
+
 static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
                          const double* loss_partials, int n_loss, double grad_scale, double* out) {
   const int T = p->T, N = p->N, F = p->F_run;
   float2* beta = reinterpret_cast<float2*>(ws + L.H);
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   double* mono = reinterpret_cast<double*>(ws + L.mono);
-  if (p->flags & SSOCT_DEPTH_FFT)
+  if (adjoint_by_fft(p))
     SSOCT_HIP(launch_depth_fft(T, N * N, -1, EPI_STORE, static_cast<const float2*>(G), p->dtw, beta, p->stream, 0, 0,
                                nullptr, depth_fft_grid(p->cu)));
   else
@@ -630,7 +634,7 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   int e = (int)std::ceil(std::log2(bound)) - 40;
   if (e < 0) e = 0;
   int n_loss;
-  if (p->flags & SSOCT_DEPTH_FFT) {
+  if (adjoint_by_fft(p)) {
     n_loss = depth_fft_blocks(N * N);
     SSOCT_HIP(launch_depth_fft(T, N * N, +1, EPI_GAMMA, static_cast<const float2*>(H), p->dtw, gam, p->stream, 0, e,
                                loss));
