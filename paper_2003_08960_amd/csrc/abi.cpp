@@ -121,7 +121,8 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->cols);
   (void)hipFree(p->tw);
   (void)hipFree(p->outfac);
-  (void)hipFree(p->aberr);
+  (void)hipFree(p->apoly);
+  (void)hipFree(p->screen);
   (void)hipFree(p->params);
   (void)hipFree(p->a_f32);
   (void)hipFree(p->a_f16);
@@ -243,7 +244,7 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     g[ParamLayout::G_HAS_ABERR] = 1.0;
   }
   std::memcpy(&h[ParamLayout::count(T) + T], &p->zmat[0][0], sizeof(double) * 15 * N_MONO);
-  if (zern_on && !p->aberr) SSOCT_HIP(hipMalloc(&p->aberr, (size_t)N * N * sizeof(float2)));
+  if (zern_on && !p->apoly) SSOCT_HIP(hipMalloc(&p->apoly, (size_t)N * APOLY_STRIDE * sizeof(float)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
   if (as) {
@@ -270,8 +271,9 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     SSOCT_HIP(hipMemcpyAsync(p->kappa, kap.data(), (size_t)T * sizeof(double), hipMemcpyHostToDevice, p->stream));
     SSOCT_HIP(launch_depth_tables(T, p->kappa, p->a_f32, p->a_f16, p->a_bf16, p->stream));
   }
-  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern_on ? p->aberr : nullptr, p->stream));
+  SSOCT_HIP(launch_misc_tables(p->params, T, N, p->outfac, zern_on ? p->apoly : nullptr, p->stream));
   p->have_aberr = zern_on;
+  p->screen_ok = false;
   // depth-first order: the chirp and the per-frame row factor must not depend on the frame
   bool no_disp = true;
   for (int t = 0; disp && t < T; ++t) no_disp = no_disp && disp[t] == 0.0;
@@ -302,7 +304,7 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
     return SSOCT_OK;
   }
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
-  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  const float* ab = p->have_aberr ? p->apoly : nullptr;
   SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
   SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, p->col_grid, s));
   return SSOCT_OK;
@@ -345,7 +347,7 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
   float2* G = reinterpret_cast<float2*>(ws + L.H);
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   float2* V = static_cast<float2*>(vol);
-  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  const float* ab = p->have_aberr ? p->apoly : nullptr;
   const int nb = T / 2 + 1;                     // bins of G
   const int nconj = (T + 1) / 2;                // bins q < nconj have a partner T - q (q >= 1)
   const int fh = p->F_run / 2 > 0 ? p->F_run / 2 : 1;   // bins per chunk: 2 fh transforms fit the chunk buffer
@@ -377,7 +379,7 @@ int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, 
   if (kev) {  // the two passes launched one by one with an event after each
     const int fmt = h_format(depth_prec(p->flags));
     float2* inter = reinterpret_cast<float2*>(ws + L.inter);
-    const float2* ab = p->have_aberr ? p->aberr : nullptr;
+    const float* ab = p->have_aberr ? p->apoly : nullptr;
     for (int t0 = 0, c = 0; t0 < T; t0 += F, ++c) {
       const int Fc = T - t0 < F ? T - t0 : F;
       SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
@@ -403,6 +405,11 @@ static bool adjoint_by_fft(const ssoct_plan* p) { return depth_fft_supported(p->
 static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
                          const double* loss_partials, int n_loss, double grad_scale, double* out) {
   const int T = p->T, N = p->N, F = p->F_run;
+  if (p->have_aberr && !p->screen_ok) {   // the adjoint row pass reads the screen as N x N factors
+    if (!p->screen) SSOCT_HIP(hipMalloc(&p->screen, (size_t)N * N * sizeof(float2)));
+    SSOCT_HIP(launch_aberr_screen(p->params, T, N, p->screen, p->stream));
+    p->screen_ok = true;
+  }
   float2* beta = reinterpret_cast<float2*>(ws + L.H);
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   double* mono = reinterpret_cast<double*>(ws + L.mono);
@@ -415,7 +422,7 @@ static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, c
   for (int t0 = 0; t0 < T; t0 += F) {
     const int Fc = T - t0 < F ? T - t0 : F;
     SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->col_grid, p->stream));
-    SSOCT_HIP(launch_row_pass_adj(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->aberr : nullptr,
+    SSOCT_HIP(launch_row_pass_adj(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->screen : nullptr,
                                   inter, mono, p->stream));
   }
   const double* aoz = p->params + ParamLayout::count(T);
@@ -623,7 +630,7 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   double* loss = reinterpret_cast<double*>(ws + L.loss);
   // Fresnel stage in FP32 whatever the plan's depth precision: the loss and its adjoint run in FP32
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
-  const float2* ab = p->have_aberr ? p->aberr : nullptr;
+  const float* ab = p->have_aberr ? p->apoly : nullptr;
   for (int t0 = 0; t0 < T; t0 += p->F_run) {
     const int Fc = T - t0 < p->F_run ? T - t0 : p->F_run;
     SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));

@@ -76,7 +76,13 @@ DepthLayout depth_layout(int T, bool general = false);   // general: 2T rows (sw
 // ---------------------------------------------------------------- launchers
 hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows, AxisTab* cols,
                               hipStream_t s);
-hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float2* aberr, hipStream_t s);
+// Aberration screen as per-row polynomials: row m (FFT position) holds, at
+// apoly[m * APOLY_STRIDE + a], the FP32 coefficient (cycles) of x^a, a = 0..4,
+// of the phase sum_k c_k Z_k at x = centred original column * sqrt 2 / N.
+constexpr int APOLY_STRIDE = 8;
+hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float* apoly, hipStream_t s);
+// The same screen as N x N complex factors (FP64 phases), for the adjoint row pass
+hipError_t launch_aberr_screen(const double* params, int T, int N, float2* screen, hipStream_t s);
 // FFT engine twiddles (per-thread layout), FP64 -> FP32; size in float2 entries
 hipError_t launch_twiddles(int N, float2* tw, hipStream_t s);
 size_t twiddle_table_size(int N);
@@ -87,7 +93,7 @@ hipError_t launch_depth_tables(int T, const double* kappa, float* a_f32, uint4* 
 // Forward Fresnel stage on frames [t0, t0 + F): rescale + chirp + row DFT into
 // `inter` ([F][N][N] complex64), then column DFT into H (format `fmt`).
 hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
-                           const AxisTab* cols, const float2* tw, const float2* aberr,
+                           const AxisTab* cols, const float2* tw, const float* apoly,
                            const float2* outfac, float2* inter, hipStream_t s);
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
                            const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
@@ -108,7 +114,7 @@ hipError_t launch_as_stage(int N, int F, int t0, const uint16_t* frames, const f
 hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
                               const double* params, const float2* wt, float2* G, hipStream_t s);
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
-                             const AxisTab* cols0, const float2* tw, const float2* aberr, const float2* outfac,
+                             const AxisTab* cols0, const float2* tw, const float* apoly, const float2* outfac,
                              float2* inter, int Fh, hipStream_t s);
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
                              int fstride, int grid, hipStream_t s);
@@ -119,7 +125,7 @@ hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw
 hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const float2* tw,
                                float2* inter, int grid, hipStream_t s);
 hipError_t launch_row_pass_adj(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
-                               const AxisTab* cols, const float2* tw, const float2* aberr,
+                               const AxisTab* cols, const float2* tw, const float2* screen,
                                const float2* inter, double* partials, hipStream_t s);
 int row_adj_blocks(int N);
 

@@ -43,7 +43,9 @@ struct ssoct_plan {
   ssoct::AxisTab* cols = nullptr;
   float2* tw = nullptr;
   float2* outfac = nullptr;
-  float2* aberr = nullptr;
+  float* apoly = nullptr;       // aberration screen, per-row polynomials [N][APOLY_STRIDE]
+  float2* screen = nullptr;     // the same screen as N x N factors, built for the gradient entry points
+  bool screen_ok = false;       // screen matches the current tables
   double* params = nullptr;    // ParamLayout + alpha/z [T] + zmat [15 x 15]
   float* a_f32 = nullptr;
   uint4* a_f16 = nullptr;

@@ -121,16 +121,44 @@ __device__ __forceinline__ void lerp_rows(const RowSrc& s, float fy, float* rbuf
   }
 }
 
+// Aberration phase of one row as a quartic in x (cycles), from the per-row table
+struct ARow {
+  float p0, p1, p2, p3, p4;
+};
+
+template <bool ABERR>
+__device__ __forceinline__ ARow load_arow(const float* __restrict__ apoly, int m) {
+  ARow a{0.f, 0.f, 0.f, 0.f, 0.f};
+  if constexpr (ABERR) {
+    const float4 lo = *reinterpret_cast<const float4*>(apoly + (size_t)m * APOLY_STRIDE);
+    a = ARow{lo.x, lo.y, lo.z, lo.w, apoly[(size_t)m * APOLY_STRIDE + 4]};
+  }
+  return a;
+}
+
+// exp(2 pi i phase) of the aberration at FFT column n: Horner in FP32, the
+// phase reduced to one cycle, then the hardware sine and cosine, which take
+// their argument in cycles (measured on gfx950 over [-1/2, 1/2]: at most
+// 1.3e-7 from the FP64 values)
+template <int N>
+__device__ __forceinline__ float2 aberr_factor(const ARow& a, int n) {
+  constexpr float inv = 1.41421356237309505f / (float)N;   // rho = r / (N / sqrt 2)
+  const float x = (float)(((n + N / 2) & (N - 1)) - N / 2) * inv;
+  const float ph = fmaf(fmaf(fmaf(fmaf(a.p4, x, a.p3), x, a.p2), x, a.p1), x, a.p0);
+  const float f = ph - rintf(ph);
+  return make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+}
+
 // Row input z[m][n] of the DFT at FFT position n (x-lerp of the y-lerped row,
 // times the separable chirp, dispersion, sign and optional aberration).
 template <int N, bool ABERR>
-__device__ __forceinline__ float2 row_input(const float* rbuf, const AxisTab& ct, float2 rowfac,
-                                            const float2* __restrict__ aberr_row, int n) {
+__device__ __forceinline__ float2 row_input(const float* rbuf, const AxisTab& ct, float2 rowfac, const ARow& ar,
+                                            int n) {
   const int x0 = ct.i0;
   const float r0 = rbuf[x0], r1 = rbuf[x0 + 1];   // rbuf[N] is a zero pad
   const float J = r0 + ct.f * (r1 - r0);
   float2 fac = cmul(ct.fac, rowfac);
-  if constexpr (ABERR) fac = cmul(fac, aberr_row[n]);
+  if constexpr (ABERR) fac = cmul(fac, aberr_factor<N>(ar, n));
   return make_float2(J * fac.x, J * fac.y);
 }
 
@@ -151,7 +179,7 @@ __device__ __forceinline__ void stage_ctab(AxisTab* ctab, const AxisTab* __restr
 template <int N, bool ABERR, bool EQ6>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
     const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
-    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float* __restrict__ apoly,
     const float2* __restrict__ outfac, float2* __restrict__ inter) {
   using S = FFTShape<N>;
   using R = RowCfg<N>;
@@ -168,25 +196,27 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
 
   AxisTab rt = rtab[m0];
   RowSrc src = load_rows<N>(I, rt.i0, j);
+  ARow an = load_arow<ABERR>(apoly, m0);
   __syncthreads();  // column table visible
 #pragma unroll 1
   for (int i = 0; i < R::RPG; ++i) {
     const int m = m0 + i;
     const RowSrc cur = src;
     const AxisTab rc = rt;
+    const ARow ar = an;
     if (i + 1 < R::RPG) {  // prefetch the next row of this group
       rt = rtab[m + 1];
       src = load_rows<N>(I, rt.i0, j);
+      an = load_arow<ABERR>(apoly, m + 1);
     }
     exchange_sync<R::WAVE>();  // previous row's FFT reads are done
     lerp_rows<N>(cur, rc.f, rbuf, j);
     exchange_sync<R::WAVE>();
-    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
     float2 v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int n = j + k * G;
-      v[k] = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, arow, n);
+      v[k] = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, ar, n);
     }
     fft_group<N, +1, 1, R::WAVE>(v, j, lds.xbuf[g], tw);
     float2* dst = inter + ((size_t)f * N + m) * N;
@@ -210,7 +240,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
 template <int N, bool ABERR, bool EQ6>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g(
     const float2* __restrict__ Gq, int qa, int T, const AxisTab* __restrict__ rows0,
-    const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float* __restrict__ apoly,
     const float2* __restrict__ outfac, float2* __restrict__ inter, int Fh) {
   using S = FFTShape<N>;
   using R = RowCfg<N>;
@@ -242,7 +272,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
       for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
     }
     const float2 rowfac = rows0[m].fac;
-    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
+    const ARow ar = load_arow<ABERR>(apoly, m);
 #pragma unroll 1
     for (int h = 0; h < (both ? 2 : 1); ++h) {
       float2 v[16];
@@ -250,7 +280,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
       for (int k = 0; k < 16; ++k) {
         const int n = j + k * G;
         float2 fac = cmul(ctab[n].fac, rowfac);
-        if constexpr (ABERR) fac = cmul(fac, arow[n]);
+        if constexpr (ABERR) fac = cmul(fac, aberr_factor<N>(ar, n));
         v[k] = cmul(fac, h == 0 ? gv[k] : cconj(gv[k]));
       }
       exchange_sync<R::WAVE>();  // the previous transform's exchange reads are done
@@ -463,7 +493,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
 template <int N, bool ABERR>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     const uint16_t* __restrict__ frames, int t0, const AxisTab* __restrict__ rows,
-    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ aberr,
+    const AxisTab* __restrict__ cols, const float2* __restrict__ tw, const float2* __restrict__ screen,
     const float2* __restrict__ inter, double* __restrict__ partials) {
   using S = FFTShape<N>;
   using R = RowCfg<N>;
@@ -491,6 +521,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     const int m = m0 + i;
     const AxisTab rc = rtab[m];
     const RowSrc cur = load_rows<N>(I, rc.i0, j);
+    const float2* srow_ab = ABERR ? screen + (size_t)m * N : nullptr;
     const float2* srow = inter + ((size_t)f * N + m) * N;
     float2 v[16];
 #pragma unroll
@@ -499,13 +530,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
     exchange_sync<R::WAVE>();   // FFT reads of xbuf done before rbuf (aliased) is written
     lerp_rows<N>(cur, rc.f, rbuf, j);
     exchange_sync<R::WAVE>();
-    const float2* arow = ABERR ? aberr + (size_t)m * N : nullptr;
     const double y = (double)(m < half ? m : m - N) * inv;
     const double y2 = y * y;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int n = j + out_offset<N>(e);
-      const float2 z = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, arow, n);
+      float2 z = row_input<N, false>(rbuf, lds.ctab[n], rc.fac, ARow{}, n);
+      if constexpr (ABERR) z = cmul(z, srow_ab[n]);
       const float2 gg = v[e];
       const double u = (double)gg.x * (double)z.y - (double)gg.y * (double)z.x;  // Im(conj(g) z)
       const double x = (double)(n < half ? n : n - N) * inv;
@@ -552,18 +583,18 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_pass_adj(
 // ------------------------------------------------------------------ launchers
 template <int N>
 static hipError_t row_pass_n(int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
-                             const float2* tw, const float2* aberr, const float2* outfac, float2* inter,
+                             const float2* tw, const float* apoly, const float2* outfac, float2* inter,
                              hipStream_t s) {
   using R = RowCfg<N>;
   dim3 grid(N / R::ROWS, F), block(R::THREADS);
-  if (aberr && outfac)
-    hipLaunchKernelGGL((k_row_pass<N, true, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
-  else if (aberr)
-    hipLaunchKernelGGL((k_row_pass<N, true, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+  if (apoly && outfac)
+    hipLaunchKernelGGL((k_row_pass<N, true, true>), grid, block, 0, s, frames, t0, rows, cols, tw, apoly, outfac, inter);
+  else if (apoly)
+    hipLaunchKernelGGL((k_row_pass<N, true, false>), grid, block, 0, s, frames, t0, rows, cols, tw, apoly, outfac, inter);
   else if (outfac)
-    hipLaunchKernelGGL((k_row_pass<N, false, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+    hipLaunchKernelGGL((k_row_pass<N, false, true>), grid, block, 0, s, frames, t0, rows, cols, tw, apoly, outfac, inter);
   else
-    hipLaunchKernelGGL((k_row_pass<N, false, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, outfac, inter);
+    hipLaunchKernelGGL((k_row_pass<N, false, false>), grid, block, 0, s, frames, t0, rows, cols, tw, apoly, outfac, inter);
   return hipGetLastError();
 }
 
@@ -606,14 +637,14 @@ static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* t
 
 template <int N>
 static hipError_t row_pass_adj_n(int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
-                                 const float2* tw, const float2* aberr, const float2* inter, double* partials,
+                                 const float2* tw, const float2* screen, const float2* inter, double* partials,
                                  hipStream_t s) {
   using R = RowCfg<N>;
   dim3 grid(N / R::ROWS, F), block(R::THREADS);
-  if (aberr)
-    hipLaunchKernelGGL((k_row_pass_adj<N, true>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, inter, partials);
+  if (screen)
+    hipLaunchKernelGGL((k_row_pass_adj<N, true>), grid, block, 0, s, frames, t0, rows, cols, tw, screen, inter, partials);
   else
-    hipLaunchKernelGGL((k_row_pass_adj<N, false>), grid, block, 0, s, frames, t0, rows, cols, tw, aberr, inter, partials);
+    hipLaunchKernelGGL((k_row_pass_adj<N, false>), grid, block, 0, s, frames, t0, rows, cols, tw, screen, inter, partials);
   return hipGetLastError();
 }
 
@@ -632,15 +663,15 @@ static hipError_t row_pass_adj_n(int F, int t0, const uint16_t* frames, const Ax
 
 template <int N>
 static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const AxisTab* rows0, const AxisTab* cols0,
-                               const float2* tw, const float2* aberr, const float2* outfac, float2* inter, int Fh,
+                               const float2* tw, const float* apoly, const float2* outfac, float2* inter, int Fh,
                                hipStream_t s) {
   using R = RowCfg<N>;
   dim3 grid(N / R::ROWS, nb), block(R::THREADS);
 #define SSOCT_RG(A, E)                                                                                            \
-  hipLaunchKernelGGL((k_row_pass_g<N, A, E>), grid, block, 0, s, G, qa, T, rows0, cols0, tw, aberr, outfac, inter, \
+  hipLaunchKernelGGL((k_row_pass_g<N, A, E>), grid, block, 0, s, G, qa, T, rows0, cols0, tw, apoly, outfac, inter, \
                      Fh)
-  if (aberr && outfac) SSOCT_RG(true, true);
-  else if (aberr) SSOCT_RG(true, false);
+  if (apoly && outfac) SSOCT_RG(true, true);
+  else if (apoly) SSOCT_RG(true, false);
   else if (outfac) SSOCT_RG(false, true);
   else SSOCT_RG(false, false);
 #undef SSOCT_RG
@@ -663,9 +694,9 @@ static hipError_t col_pass_v_n(int F, const float2* inter, const float2* tw, con
 }
 
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
-                             const AxisTab* cols0, const float2* tw, const float2* aberr, const float2* outfac,
+                             const AxisTab* cols0, const float2* tw, const float* apoly, const float2* outfac,
                              float2* inter, int Fh, hipStream_t s) {
-#define CALL(n) row_pass_g_n<n>(nb, qa, T, G, rows0, cols0, tw, aberr, outfac, inter, Fh, s)
+#define CALL(n) row_pass_g_n<n>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
@@ -704,8 +735,8 @@ hipError_t launch_as_stage(int N, int F, int t0, const uint16_t* frames, const f
 }
 
 hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
-                           const float2* tw, const float2* aberr, const float2* outfac, float2* inter, hipStream_t s) {
-#define CALL(n) row_pass_n<n>(F, t0, frames, rows, cols, tw, aberr, outfac, inter, s)
+                           const float2* tw, const float* apoly, const float2* outfac, float2* inter, hipStream_t s) {
+#define CALL(n) row_pass_n<n>(F, t0, frames, rows, cols, tw, apoly, outfac, inter, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
@@ -725,9 +756,9 @@ hipError_t launch_col_pass_adj(int N, int F, int t0, const float2* B, const floa
 }
 
 hipError_t launch_row_pass_adj(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
-                               const AxisTab* cols, const float2* tw, const float2* aberr, const float2* inter,
+                               const AxisTab* cols, const float2* tw, const float2* screen, const float2* inter,
                                double* partials, hipStream_t s) {
-#define CALL(n) row_pass_adj_n<n>(F, t0, frames, rows, cols, tw, aberr, inter, partials, s)
+#define CALL(n) row_pass_adj_n<n>(F, t0, frames, rows, cols, tw, screen, inter, partials, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }

@@ -51,6 +51,11 @@ __global__ void k_axis_tables(const double* __restrict__ params, int T, int N,
   rows[(size_t)t * N + i] = a;
 }
 
+__device__ __forceinline__ int mono_a(int k) {
+  const int A[N_MONO] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
+  return A[k];
+}
+
 __device__ __forceinline__ double mono(int k, double x, double y) {
   // (a, b) in the fixed monomial order
   const int A[N_MONO] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
@@ -121,25 +126,50 @@ size_t twiddle_table_size(int N) {
 }
 
 __global__ void k_misc_tables(const double* __restrict__ params, int T, int N, float2* __restrict__ outfac,
-                              float2* __restrict__ aberr) {
+                              float* __restrict__ apoly) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;   // column (Eq. 6 output phase) or row (screen)
+  if (n >= N) return;
+  const double* g = params + ParamLayout::globals(T);
+  if (outfac) {
+    const double cu = (double)(n - (N >> 1));
+    outfac[n] = expi_cycles(frac_cycles(-g[ParamLayout::G_KAPPA_OUT] * cu * cu), 1.0);
+  }
+  if (apoly && g[ParamLayout::G_HAS_ABERR] != 0.0) {
+    // aberration phase on FFT row n as a quartic in x: sum_a p_a x^a with
+    // p_a = sum_b poly(a, b) y^b, in cycles; p_0 reduced to one cycle (exact
+    // in FP64); x, y = centred original index * sqrt 2 / N (rho = r / (N / sqrt 2))
+    const int half = N >> 1;
+    const double y = (double)(((n + half) & (N - 1)) - half) * (1.4142135623730950488 / (double)N);
+    double pa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < N_MONO; ++k) pa[mono_a(k)] += g[ParamLayout::G_POLY + k] * mono(k, 1.0, y);
+    float* dst = apoly + (size_t)n * APOLY_STRIDE;
+    for (int a = 0; a < 5; ++a) {
+      const double c = pa[a] * 0.15915494309189533577;
+      dst[a] = (float)(a == 0 ? frac_cycles(c) : c);
+    }
+    for (int a = 5; a < APOLY_STRIDE; ++a) dst[a] = 0.0f;
+  }
+}
+
+// Aberration screen exp(i sum_k c_k Z_k) at every FFT position (FP64 phase,
+// reduced in cycles), read by the adjoint row pass
+__global__ void k_aberr_screen(const double* __restrict__ params, int T, int N, float2* __restrict__ screen) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;   // column (FFT position)
   const int m = blockIdx.y;                              // row (FFT position)
   if (n >= N || m >= N) return;
   const double* g = params + ParamLayout::globals(T);
-  if (m == 0 && outfac) {
-    const double cu = (double)(n - (N >> 1));
-    outfac[n] = expi_cycles(frac_cycles(-g[ParamLayout::G_KAPPA_OUT] * cu * cu), 1.0);
-  }
-  if (aberr && g[ParamLayout::G_HAS_ABERR] != 0.0) {
-    const int half = N >> 1;
-    const double inv = 1.4142135623730950488 / (double)N;   // rho = r / (N / sqrt 2)
-    const double x = (double)(((n + half) & (N - 1)) - half) * inv;
-    const double y = (double)(((m + half) & (N - 1)) - half) * inv;
-    double ph = 0.0;
-    for (int k = 0; k < N_MONO; ++k) ph += g[ParamLayout::G_POLY + k] * mono(k, x, y);
-    const double cyc = frac_cycles(ph * 0.15915494309189533577);
-    aberr[(size_t)m * N + n] = expi_cycles(cyc, 1.0);
-  }
+  const int half = N >> 1;
+  const double inv = 1.4142135623730950488 / (double)N;   // rho = r / (N / sqrt 2)
+  const double x = (double)(((n + half) & (N - 1)) - half) * inv;
+  const double y = (double)(((m + half) & (N - 1)) - half) * inv;
+  double ph = 0.0;
+  for (int k = 0; k < N_MONO; ++k) ph += g[ParamLayout::G_POLY + k] * mono(k, x, y);
+  screen[(size_t)m * N + n] = expi_cycles(frac_cycles(ph * 0.15915494309189533577), 1.0);
+}
+
+hipError_t launch_aberr_screen(const double* params, int T, int N, float2* screen, hipStream_t s) {
+  hipLaunchKernelGGL(k_aberr_screen, dim3((N + 255) / 256, N), dim3(256), 0, s, params, T, N, screen);
+  return hipGetLastError();
 }
 
 DepthLayout depth_layout(int T, bool general) {
@@ -248,10 +278,9 @@ hipError_t launch_axis_tables(const double* params, int T, int N, AxisTab* rows,
   return hipGetLastError();
 }
 
-hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float2* aberr, hipStream_t s) {
-  if (!outfac && !aberr) return hipSuccess;
-  dim3 block(256), grid((N + 255) / 256, aberr ? N : 1);
-  hipLaunchKernelGGL(k_misc_tables, grid, block, 0, s, params, T, N, outfac, aberr);
+hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float* apoly, hipStream_t s) {
+  if (!outfac && !apoly) return hipSuccess;
+  hipLaunchKernelGGL(k_misc_tables, dim3((N + 255) / 256), dim3(256), 0, s, params, T, N, outfac, apoly);
   return hipGetLastError();
 }
 
