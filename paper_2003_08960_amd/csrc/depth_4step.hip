@@ -232,9 +232,8 @@ __device__ __forceinline__ void stage_a_regs(const uint2 (&e)[8], const AOps<T2,
 // stage B writes the volume.
 template <int T2, int PREC, int EPI>
 __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restrict__ H,
-                                                                   const float2* __restrict__ wt,
-                                                                   void* __restrict__ out, int P, float mid_scale,
-                                                                   float out_scale, int shift) {
+                                                            const float2* __restrict__ wt, void* __restrict__ out,
+                                                            int P, float mid_scale, float out_scale, int shift) {
   constexpr int PX = F4_PX;
   using S = F4Shape<T2, PX>;
   __shared__ uint2 buf[S::T * PX];   // [q2][t1][pixel]
