@@ -123,6 +123,7 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->outfac);
   (void)hipFree(p->apoly);
   (void)hipFree(p->screen);
+  (void)hipFree(p->f4ops);
   (void)hipFree(p->params);
   (void)hipFree(p->a_f32);
   (void)hipFree(p->a_f16);
@@ -319,7 +320,7 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
     return SSOCT_OK;
   }
   if (p->flags & SSOCT_DEPTH_4STEP) {
-    SSOCT_HIP(launch_depth_4step(p->T, p->N * p->N, prec, epi, ws + L.H, p->dtw, vol, p->sigma, s, shift));
+    SSOCT_HIP(launch_depth_4step(p->T, p->N * p->N, prec, epi, ws + L.H, p->dtw, p->f4ops, vol, p->sigma, s, shift));
     return SSOCT_OK;
   }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
@@ -519,6 +520,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
   if (e == hipSuccess) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
   if (e == hipSuccess) e = launch_depth_twiddles(T, p->dtw, stream);
+  if (e == hipSuccess && (flags & SSOCT_DEPTH_4STEP)) e = hipMalloc(&p->f4ops, depth_4step_ops_bytes());
+  if (e == hipSuccess && (flags & SSOCT_DEPTH_4STEP)) e = launch_4step_operands(T, depth_prec(flags), p->f4ops, stream);
   if (e != hipSuccess) {
     const int rc = (e == hipErrorOutOfMemory) ? fail(SSOCT_ENOMEM, "device allocation failed")
                                               : hip_fail(e, "ssoct_plan_create");

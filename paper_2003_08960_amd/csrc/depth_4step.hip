@@ -98,12 +98,17 @@ __device__ __forceinline__ void mfma16_step(const uint2 (&e)[8], uint4 ahi, uint
   acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
 }
 
-// Per-lane A operands: the real-form T2-point (stage A) and 16-point (stage B) DFT matrices, row lc
+// Per-lane A operands: the real-form T2-point (stage A) and 16-point (stage B)
+// DFT matrices, row lc, as 16 dwords per lane: FP32 a[0..T2/2) at 0, b[0..8)
+// at 8; 16-bit ahi, alo, bhi, blo at 0, 4, 8, 12.  Built once per plan from
+// FP64 (F4_OPS_DWORDS per lane, 64 lanes) and loaded by every workgroup.
+constexpr int F4_OPS_DWORDS = 16;
+
 template <int T2, int PREC>
 struct AOps {
   float a[PrecTraits<PREC>::F32 ? T2 / 2 : 1], b[PrecTraits<PREC>::F32 ? 8 : 1];
   uint4 ahi, alo, bhi, blo;
-  __device__ __forceinline__ void init(int lc, int lh) {
+  __device__ __forceinline__ void build(int lc, int lh) {
     if constexpr (PrecTraits<PREC>::F32) {
 #pragma unroll
       for (int s = 0; s < T2 / 2; ++s) a[s] = (float)dft_real_form(lc, 2 * s + lh, T2);
@@ -114,7 +119,46 @@ struct AOps {
       a_operand16<PrecTraits<PREC>::BF>(lc, 8 * lh, 16, bhi, blo);
     }
   }
+  __device__ __forceinline__ void store(uint32_t* dst) const {
+    uint4 q[4];
+    if constexpr (PrecTraits<PREC>::F32) {
+      uint32_t w[16] = {};
+#pragma unroll
+      for (int s = 0; s < T2 / 2; ++s) w[s] = __float_as_uint(a[s]);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) w[8 + s] = __float_as_uint(b[s]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+    } else {
+      q[0] = ahi; q[1] = alo; q[2] = bhi; q[3] = blo;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(dst)[i] = q[i];
+  }
+  __device__ __forceinline__ void load(const uint32_t* __restrict__ src) {
+    uint4 q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = reinterpret_cast<const uint4*>(src)[i];
+    if constexpr (PrecTraits<PREC>::F32) {
+      const uint32_t w[16] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w,
+                              q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+#pragma unroll
+      for (int s = 0; s < T2 / 2; ++s) a[s] = __uint_as_float(w[s]);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) b[s] = __uint_as_float(w[8 + s]);
+    } else {
+      ahi = q[0]; alo = q[1]; bhi = q[2]; blo = q[3];
+    }
+  }
 };
+
+template <int T2, int PREC>
+__global__ void k_4step_operands(uint32_t* __restrict__ ops) {
+  const int l = threadIdx.x;   // 64 lanes
+  AOps<T2, PREC> A;
+  A.build(l & 31, l >> 5);
+  A.store(ops + (size_t)l * F4_OPS_DWORDS);
+}
 
 // Stage-A products of column tile j times the twiddle wT^(q2 t1), into the [q2][t1][pixel] tile `dst`
 template <int T2, int PREC, int PX>
@@ -232,7 +276,8 @@ __device__ __forceinline__ void stage_a_regs(const uint2 (&e)[8], const AOps<T2,
 // stage B writes the volume.
 template <int T2, int PREC, int EPI>
 __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restrict__ H,
-                                                            const float2* __restrict__ wt, void* __restrict__ out,
+                                                            const float2* __restrict__ wt,
+                                                            const uint32_t* __restrict__ ops, void* __restrict__ out,
                                                             int P, float mid_scale, float out_scale, int shift) {
   constexpr int PX = F4_PX;
   using S = F4Shape<T2, PX>;
@@ -247,7 +292,7 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
     if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, e[jj]);
   }
   AOps<T2, PREC> A;
-  A.init(lc, lh);
+  A.load(ops + (size_t)l * F4_OPS_DWORDS);
 #pragma unroll
   for (int jj = 0; jj < S::TA_W; ++jj) {
     const int j = w + S::NW * jj;
@@ -265,38 +310,64 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
 }
 
 template <int T2, int PREC, int EPI>
-static hipError_t go_4step(int P, const void* H, const float2* wt, void* out, float mid, float os, int shift,
-                           hipStream_t s) {
+static hipError_t go_4step(int P, const void* H, const float2* wt, const uint32_t* ops, void* out, float mid,
+                           float os, int shift, hipStream_t s) {
   hipLaunchKernelGGL((k_depth_4step<T2, PREC, EPI>), dim3(P / F4_PX), dim3(F4_THREADS), 0, s,
-                     reinterpret_cast<const uint2*>(H), wt, out, P, mid, os, shift);
+                     reinterpret_cast<const uint2*>(H), wt, ops, out, P, mid, os, shift);
   return hipGetLastError();
 }
 
 template <int T2, int PREC>
-static hipError_t go_4step_epi(int epi, int P, const void* H, const float2* wt, void* out, float mid, float os,
-                               int shift, hipStream_t s) {
-  if (epi == EPI_ABS) return go_4step<T2, PREC, EPI_ABS>(P, H, wt, out, mid, os, shift, s);
-  return go_4step<T2, PREC, EPI_STORE>(P, H, wt, out, mid, os, shift, s);
+static hipError_t go_4step_epi(int epi, int P, const void* H, const float2* wt, const uint32_t* ops, void* out,
+                               float mid, float os, int shift, hipStream_t s) {
+  if (epi == EPI_ABS) return go_4step<T2, PREC, EPI_ABS>(P, H, wt, ops, out, mid, os, shift, s);
+  return go_4step<T2, PREC, EPI_STORE>(P, H, wt, ops, out, mid, os, shift, s);
 }
 
 template <int T2>
-static hipError_t go_4step_prec(int prec, int epi, int P, const void* H, const float2* wt, void* out, float mid,
-                                float os, int shift, hipStream_t s) {
+static hipError_t go_4step_prec(int prec, int epi, int P, const void* H, const float2* wt, const uint32_t* ops,
+                                void* out, float mid, float os, int shift, hipStream_t s) {
   switch (prec) {
-    case DP_F32: return go_4step_epi<T2, DP_F32>(epi, P, H, wt, out, mid, os, shift, s);
-    case DP_F16: return go_4step_epi<T2, DP_F16>(epi, P, H, wt, out, mid, os, shift, s);
-    case DP_BF16: return go_4step_epi<T2, DP_BF16>(epi, P, H, wt, out, mid, os, shift, s);
-    case DP_F16_SPLIT: return go_4step_epi<T2, DP_F16_SPLIT>(epi, P, H, wt, out, mid, os, shift, s);
-    case DP_BF16_SPLIT: return go_4step_epi<T2, DP_BF16_SPLIT>(epi, P, H, wt, out, mid, os, shift, s);
+    case DP_F32: return go_4step_epi<T2, DP_F32>(epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_F16: return go_4step_epi<T2, DP_F16>(epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_BF16: return go_4step_epi<T2, DP_BF16>(epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_F16_SPLIT: return go_4step_epi<T2, DP_F16_SPLIT>(epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_BF16_SPLIT: return go_4step_epi<T2, DP_BF16_SPLIT>(epi, P, H, wt, ops, out, mid, os, shift, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 bool depth_4step_supported(int T) { return T == 32 || T == 64 || T == 128 || T == 256; }
 
-hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, void* out,
-                              int sigma, hipStream_t s, int shift) {
+size_t depth_4step_ops_bytes() { return (size_t)64 * F4_OPS_DWORDS * sizeof(uint32_t); }
+
+template <int T2>
+static hipError_t ops_prec(int prec, uint32_t* ops, hipStream_t s) {
+  switch (prec) {
+    case DP_F32: hipLaunchKernelGGL((k_4step_operands<T2, DP_F32>), dim3(1), dim3(64), 0, s, ops); break;
+    case DP_F16: hipLaunchKernelGGL((k_4step_operands<T2, DP_F16>), dim3(1), dim3(64), 0, s, ops); break;
+    case DP_BF16: hipLaunchKernelGGL((k_4step_operands<T2, DP_BF16>), dim3(1), dim3(64), 0, s, ops); break;
+    case DP_F16_SPLIT: hipLaunchKernelGGL((k_4step_operands<T2, DP_F16_SPLIT>), dim3(1), dim3(64), 0, s, ops); break;
+    case DP_BF16_SPLIT: hipLaunchKernelGGL((k_4step_operands<T2, DP_BF16_SPLIT>), dim3(1), dim3(64), 0, s, ops); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_4step_operands(int T, int prec, uint32_t* ops, hipStream_t s) {
+  switch (T) {
+    case 32: return ops_prec<2>(prec, ops, s);
+    case 64: return ops_prec<4>(prec, ops, s);
+    case 128: return ops_prec<8>(prec, ops, s);
+    case 256: return ops_prec<16>(prec, ops, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, const uint32_t* ops,
+                              void* out, int sigma, hipStream_t s, int shift) {
   if (P <= 0) return hipSuccess;
+  if (!ops) return hipErrorInvalidValue;
   if (P % F4_PX != 0 || (epi != EPI_STORE && epi != EPI_ABS) || (epi == EPI_ABS && shift != 0))
     return hipErrorInvalidValue;
   const int T2 = T / 16;
@@ -305,10 +376,10 @@ hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, co
   const float mid = f16 ? 1.0f / (float)T2 : 1.0f;
   const float os = ldexpf(f16 ? (float)T2 : 1.0f, sigma);
   switch (T) {
-    case 32: return go_4step_prec<2>(prec, epi, P, H, wt, out, mid, os, shift, s);
-    case 64: return go_4step_prec<4>(prec, epi, P, H, wt, out, mid, os, shift, s);
-    case 128: return go_4step_prec<8>(prec, epi, P, H, wt, out, mid, os, shift, s);
-    case 256: return go_4step_prec<16>(prec, epi, P, H, wt, out, mid, os, shift, s);
+    case 32: return go_4step_prec<2>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 64: return go_4step_prec<4>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 128: return go_4step_prec<8>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 256: return go_4step_prec<16>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
     default: return hipErrorInvalidValue;
   }
 }

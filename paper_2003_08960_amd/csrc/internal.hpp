@@ -155,9 +155,13 @@ hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 // Depth transform as a two-factor (16 x T/16) DFT on MFMA, forward only, in
 // any operand precision (H in the format of that precision, scaled by
 // 2^-sigma for FP16); epi EPI_STORE (with the ring shift) or EPI_ABS.
+// ops: the per-lane DFT-matrix operands of the plan's (T, precision),
+// depth_4step_ops_bytes() of device memory filled by launch_4step_operands.
 bool depth_4step_supported(int T);
-hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, void* out,
-                              int sigma, hipStream_t s, int shift = 0);
+size_t depth_4step_ops_bytes();
+hipError_t launch_4step_operands(int T, int prec, uint32_t* ops, hipStream_t s);
+hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, const uint32_t* ops,
+                              void* out, int sigma, hipStream_t s, int shift = 0);
 
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,
                        float* cut_xy, float* cut_xz, float* cut_yz, hipStream_t s);

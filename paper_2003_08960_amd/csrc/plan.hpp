@@ -45,6 +45,7 @@ struct ssoct_plan {
   float2* outfac = nullptr;
   float* apoly = nullptr;       // aberration screen, per-row polynomials [N][APOLY_STRIDE]
   float2* screen = nullptr;     // the same screen as N x N factors, built for the gradient entry points
+  uint32_t* f4ops = nullptr;    // DFT-matrix operands of the factored depth form
   bool screen_ok = false;       // screen matches the current tables
   double* params = nullptr;    // ParamLayout + alpha/z [T] + zmat [15 x 15]
   float* a_f32 = nullptr;

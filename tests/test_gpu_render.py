@@ -74,6 +74,19 @@ def test_fp32_ragged_sweeps(gpu_lib, T):
     assert err <= FP32_BAR
 
 
+@pytest.mark.parametrize("precision,bar", [("fp32", FP32_BAR), ("bf16_split", SPLIT_BAR), ("fp16_split", SPLIT_BAR)])
+@pytest.mark.parametrize("T", [1000, 1024])
+def test_longest_sweeps(gpu_lib, T, precision, bar):
+    """The largest sweep the plan takes (T = 1024) and a ragged one below it, on the dense depth product."""
+    N = 16
+    frames, lam = random_case(T, N, seed=T)
+    _, _, V = gpu_render(frames, lam, 20e-6, 0.05, precision=precision)
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    err = rel_l2(V.cpu().numpy(), ref)
+    print(f"T={T} {precision} rel-L2 {err:.3e}")
+    assert err <= bar
+
+
 # ---------------------------------------------------------------- tiny workload (T=32, N=128)
 
 def test_tiny_fp32_and_cuts(gpu_lib, tiny):
