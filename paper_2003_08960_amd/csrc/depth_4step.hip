@@ -187,9 +187,7 @@ __device__ __forceinline__ void stage_a_store(uint2* dst, int j, int lc, int lh,
 // and the volume epilogue for pixels p0 + pixel
 template <int T2, int PREC, int EPI, int PX>
 __device__ __forceinline__ void stage_b(const uint2* in, int j, int lc, int lh, const AOps<T2, PREC>& A,
-                                        const float2* __restrict__ wt, void* __restrict__ out, int P, int p0,
-                                        float out_scale, int shift) {
-  constexpr int T = 16 * T2;
+                                        void* __restrict__ out, int P, int p0, float out_scale) {
   const int q2 = (32 * j + lc) / PX, px = (32 * j + lc) % PX;
   v16f br, bi;
 #pragma unroll
@@ -216,12 +214,10 @@ __device__ __forceinline__ void stage_b(const uint2* in, int j, int lc, int lh, 
     const int q = q2 + T2 * q1;
     float2 V = make_float2((br[r] - bi[r + 1]) * out_scale, (bi[r] + br[r + 1]) * out_scale);
     const size_t idx = (size_t)q * P + p0 + px;
-    if constexpr (EPI == EPI_ABS) {
+    if constexpr (EPI == EPI_ABS)
       st_once<SSOCT_F4_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(V.x * V.x + V.y * V.y));
-    } else {
-      if (shift != 0) V = cmulc(V, wt[(q * shift) % T]);   // window starting `shift` slots into a ring
+    else
       st_once<SSOCT_F4_NT>(reinterpret_cast<float2*>(out) + idx, V);
-    }
   }
 }
 
@@ -241,7 +237,8 @@ struct F4Shape {
 // half-wave load is PX consecutive pixels of one frame.
 template <int T2, int PREC, int PX>
 __device__ __forceinline__ void load_stage_a(const uint2* __restrict__ H, int P, int p0, int j, int lc, int lh,
-                                             uint2 (&e)[8]) {
+                                             int shift, uint2 (&e)[8]) {
+  constexpr int T = 16 * T2;
   const int t1 = (32 * j + lc) / PX, px = (32 * j + lc) % PX;
   const uint2* src = H + p0 + px;
 #pragma unroll
@@ -249,7 +246,8 @@ __device__ __forceinline__ void load_stage_a(const uint2* __restrict__ H, int P,
     // FP32: k = 2 i + lh (i < T2/2); 16-bit: k = 8 lh + i (k < T2)
     const int t2 = PrecTraits<PREC>::F32 ? 2 * i + lh : 8 * lh + i;
     const bool ok = PrecTraits<PREC>::F32 ? i < T2 / 2 : t2 < T2;
-    e[i] = ok ? ld_once<SSOCT_F4_NT>(src + (size_t)(t1 + 16 * t2) * P) : make_uint2(0u, 0u);
+    const int slot = (t1 + 16 * t2 + shift) & (T - 1);   // a ring window starting `shift` slots in
+    e[i] = ok ? ld_once<SSOCT_F4_NT>(src + (size_t)slot * P) : make_uint2(0u, 0u);
   }
 }
 
@@ -289,7 +287,7 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
 #pragma unroll
   for (int jj = 0; jj < S::TA_W; ++jj) {
     const int j = w + S::NW * jj;
-    if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, e[jj]);
+    if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, shift, e[jj]);
   }
   AOps<T2, PREC> A;
   A.load(ops + (size_t)l * F4_OPS_DWORDS);
@@ -305,7 +303,7 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
 #pragma unroll
   for (int jj = 0; jj < S::TB_W; ++jj) {
     const int j = w + S::NW * jj;
-    if (j < S::TB) stage_b<T2, PREC, EPI, PX>(buf, j, lc, lh, A, wt, out, P, p0, out_scale, shift);
+    if (j < S::TB) stage_b<T2, PREC, EPI, PX>(buf, j, lc, lh, A, out, P, p0, out_scale);
   }
 }
 
@@ -368,8 +366,7 @@ hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, co
                               void* out, int sigma, hipStream_t s, int shift) {
   if (P <= 0) return hipSuccess;
   if (!ops) return hipErrorInvalidValue;
-  if (P % F4_PX != 0 || (epi != EPI_STORE && epi != EPI_ABS) || (epi == EPI_ABS && shift != 0))
-    return hipErrorInvalidValue;
+  if (P % F4_PX != 0 || (epi != EPI_STORE && epi != EPI_ABS) || shift < 0 || shift >= T) return hipErrorInvalidValue;
   const int T2 = T / 16;
   // FP16 stage-B operands: the stage-A sums grow by up to T2, scaled back by an exact power of two
   const bool f16 = prec == DP_F16 || prec == DP_F16_SPLIT;

@@ -30,16 +30,19 @@ namespace ssoct {
 #endif
 
 // stage A for the tile of pixels base..base+PX-1: DFT over t2 of h[r + 16 t2],
-// times the twiddles, into lds as [q2][t1][px]
+// times the twiddles, into lds as [q2][t1][px].  With shift > 0 the stack is
+// a ring whose window starts `shift` slots in: h[t] is ring slot (t + shift) mod T.
 template <int T2, int DIR, int PX>
 __device__ __forceinline__ void fft_stage_a(const float2* __restrict__ H, const float2* __restrict__ wt, float2* lds,
-                                            int P, int base, int px, int r, bool live) {
+                                            int P, int base, int px, int r, bool live, int shift = 0) {
   constexpr int T = 16 * T2;
   constexpr int ED = -DIR;           // engine sign: forward depth DFT has exponent -2 pi i q t / T
   float2 a[T2];
 #pragma unroll
-  for (int t2 = 0; t2 < T2; ++t2)
-    a[t2] = live ? ld_once<SSOCT_DFFT_NT>(H + (size_t)(r + 16 * t2) * P + base + px) : make_float2(0.f, 0.f);
+  for (int t2 = 0; t2 < T2; ++t2) {
+    const int slot = (r + 16 * t2 + shift) & (T - 1);
+    a[t2] = live ? ld_once<SSOCT_DFFT_NT>(H + (size_t)slot * P + base + px) : make_float2(0.f, 0.f);
+  }
   if constexpr (T2 > 1) dft_small<T2, ED>(a);
 #pragma unroll
   for (int q2 = 0; q2 < T2; ++q2) {
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
     }
     const int base = tile * PX;
     const bool live = base + px < P;
-    fft_stage_a<T2, DIR, PX>(H, wt, lds, P, base, px, r, live);
+    fft_stage_a<T2, DIR, PX>(H, wt, lds, P, base, px, r, live, shift);
     __syncthreads();
     if (r < T2) {
       float2 b[16];
@@ -89,8 +92,6 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
           const size_t idx = (size_t)(r + T2 * q1) * P + base + px;
           if constexpr (EPI == EPI_ABS)
             st_once<SSOCT_DFFT_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(b[q1].x * b[q1].x + b[q1].y * b[q1].y));
-          else if (DIR > 0 && shift != 0)   // window starting `shift` slots into a ring: exp(+2 pi i q shift / T)
-            st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, cmulc(b[q1], wt[((r + T2 * q1) * shift) % T]));
           else
             st_once<SSOCT_DFFT_NT>(reinterpret_cast<float2*>(out) + idx, b[q1]);
         }
@@ -375,8 +376,9 @@ int depth_fft_grid(int cu_count) { return SSOCT_DFFT_WGCU > 0 ? SSOCT_DFFT_WGCU 
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
                             hipStream_t s, int shift, int gamma_exp, double* partials, int grid) {
   if (P <= 0) return hipSuccess;
+  if (shift < 0 || shift >= T) return hipErrorInvalidValue;
   if (dir > 0) {
-    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, 0, 1.f, nullptr, grid, s);
+    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, shift, 1.f, nullptr, grid, s);
     if (epi == EPI_GAMMA) {
       if (!partials || shift != 0) return hipErrorInvalidValue;
       return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, 0, s);

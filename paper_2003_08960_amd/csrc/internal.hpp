@@ -139,6 +139,8 @@ hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in
 int depth_grid(int T, int P, int cu_count, bool general = false);
 
 // Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).
+// shift (forward): the stack is a ring whose window starts at slot `shift`;
+// frame t of the window is read from slot (t + shift) mod T.
 // epi: EPI_STORE (complex64), EPI_ABS or EPI_GAMMA (forward only; the latter
 // writes Gamma = 4 |V 2^-gamma_exp|^2 V 2^-gamma_exp and one FP64 partial of
 // sum |V|^4 per workgroup, depth_fft_blocks(P) of them).  wt: exp(-2 pi i k/T).

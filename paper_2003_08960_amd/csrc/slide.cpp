@@ -37,7 +37,8 @@ struct OutSlot {
   float2* vol = nullptr;     // device volume of one window
   float* cuts = nullptr;     // device cuts xy | xz | yz
   float* hcuts = nullptr;    // pinned host copy of the cuts
-  hipEvent_t done = nullptr;
+  hipEvent_t ready = nullptr;  // volume and device cuts complete (compute stream)
+  hipEvent_t done = nullptr;   // host cuts complete too (copy stream)
   bool busy = false;
   uint64_t start = 0;        // first frame of the window
   int64_t t_submit = 0;
@@ -51,7 +52,8 @@ void slide_stamp(void* arg) { static_cast<OutSlot*>(arg)->t_done.store(slide_now
 struct ssoct_slide {
   ssoct_plan* plan = nullptr;
   int hop = 1, nslot = 0, x0 = 0, y0 = 0, q0 = 0;
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr;    // transfers of frames and all kernels
+  hipStream_t cs = nullptr;   // copies of the cuts to the host, overlapping the next window
   uint16_t* ring = nullptr;  // raw frames [T][N][N] by sweep position
   char* ws = nullptr;        // workspace: hologram ring (H) and chunk buffer
   WsLayout L{};
@@ -69,9 +71,11 @@ namespace {
 void slide_free(ssoct_slide* sl) {
   if (!sl) return;
   if (sl->s) (void)hipStreamSynchronize(sl->s);
+  if (sl->cs) (void)hipStreamSynchronize(sl->cs);
   if (sl->out) {
     for (int k = 0; k < sl->nslot; ++k) {
       OutSlot& o = sl->out[k];
+      if (o.ready) (void)hipEventDestroy(o.ready);
       if (o.done) (void)hipEventDestroy(o.done);
       (void)hipFree(o.vol);
       (void)hipFree(o.cuts);
@@ -81,6 +85,7 @@ void slide_free(ssoct_slide* sl) {
   (void)hipFree(sl->ring);
   (void)hipFree(sl->ws);
   if (sl->s) (void)hipStreamDestroy(sl->s);
+  if (sl->cs) (void)hipStreamDestroy(sl->cs);
   if (sl->plan) sl->plan->streaming = false;
   delete sl;
 }
@@ -109,9 +114,12 @@ int emit(ssoct_slide* sl, uint64_t j) {
   const size_t ncut = (size_t)N * N + 2 * (size_t)T * N;
   SSOCT_HIP(launch_cuts(T, N, o.vol, sl->x0, sl->y0, sl->q0, (p->flags & SSOCT_CUT_POWER) ? 1 : 0, c,
                         c + (size_t)N * N, c + (size_t)N * N + (size_t)T * N, sl->s));
-  SSOCT_HIP(hipMemcpyAsync(o.hcuts, c, ncut * sizeof(float), hipMemcpyDeviceToHost, sl->s));
-  SSOCT_HIP(hipLaunchHostFunc(sl->s, slide_stamp, &o));
-  SSOCT_HIP(hipEventRecord(o.done, sl->s));
+  // the host copy runs on the copy stream while the next window is transformed
+  SSOCT_HIP(hipEventRecord(o.ready, sl->s));
+  SSOCT_HIP(hipStreamWaitEvent(sl->cs, o.ready, 0));
+  SSOCT_HIP(hipMemcpyAsync(o.hcuts, c, ncut * sizeof(float), hipMemcpyDeviceToHost, sl->cs));
+  SSOCT_HIP(hipLaunchHostFunc(sl->cs, slide_stamp, &o));
+  SSOCT_HIP(hipEventRecord(o.done, sl->cs));
   sl->inflight.push_back(k);
   return SSOCT_OK;
 }
@@ -198,6 +206,7 @@ int ssoct_slide_create(ssoct_slide** out, ssoct_plan* p, const double* lambda, d
   sl->L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
   const size_t ncut = (size_t)N * N + 2 * (size_t)T * N;
   hipError_t e = hipStreamCreateWithFlags(&sl->s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl->cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&sl->ring, (size_t)T * N * N * sizeof(uint16_t));
   if (e == hipSuccess) e = hipMalloc(&sl->ws, sl->L.total);
   for (int k = 0; k < slots && e == hipSuccess; ++k) {
@@ -205,6 +214,7 @@ int ssoct_slide_create(ssoct_slide** out, ssoct_plan* p, const double* lambda, d
     e = hipMalloc(&o.vol, (size_t)T * N * N * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&o.cuts, ncut * sizeof(float));
     if (e == hipSuccess) e = hipHostMalloc(&o.hcuts, ncut * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&o.ready, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&o.done, hipEventDisableTiming);
   }
   if (e != hipSuccess) {
