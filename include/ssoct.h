@@ -266,13 +266,15 @@ int ssoct_stream_destroy(ssoct_stream* stream);
  * (the paper's real-time mode: hop ~13 turns 512 frames/s into ~38 volumes
  * per second).  Every frame is rescaled and Fresnel-transformed once into
  * slot seq % T of a ring of holograms (sweep position seq % T selects
- * lambda, disp_phase and the tables); the window starting at frame j is
- * transformed from the ring with bin q multiplied by exp(+2 pi i q (j % T) / T),
- * which makes it exactly the DFT of frames j .. j + T - 1 in time order.  A
- * window is emitted every `hop` frames once T consecutive frames have
- * arrived: depth transform, cuts and copy of the cuts to pinned host memory,
- * into one of `slots` output volumes.  All work runs in order on one stream
- * owned by the object.  Windows never span a gap in the frame sequence: a gap
+ * lambda, disp_phase and the tables); the window starting at frame j is the
+ * DFT of frames j .. j + T - 1 in time order, read from the ring in rotated
+ * order (or, for the dense depth product, transformed in slot order with bin
+ * q multiplied by exp(+2 pi i q (j % T) / T), the same thing for a circular
+ * DFT).  A window is emitted every `hop` frames once T consecutive frames
+ * have arrived: depth transform, cuts and copy of the cuts to pinned host
+ * memory, into one of `slots` output volumes.  Frames and kernels run in
+ * order on one stream owned by the object, the copies of the cuts on a
+ * second one.  Windows never span a gap in the frame sequence: a gap
  * restarts the run (the call returns SSOCT_EDROPPED), and a window that finds
  * every output volume still held is dropped and counted.  The plan's
  * parameters are fixed while the object exists; the SSOCT_DEPTH_FFT form

@@ -51,7 +51,7 @@ struct ssoct_plan {
   float* a_f32 = nullptr;
   uint4* a_f16 = nullptr;
   uint4* a_bf16 = nullptr;
-  float2* dtw = nullptr;       // exp(-2 pi i k / T): FFT depth twiddles and window phase
+  float2* dtw = nullptr;       // exp(-2 pi i k / T): FFT depth twiddles, dense window phase
   bool general = false;        // SSOCT_NONUNIFORM_K: general depth matrix from kappa_t
   double* kappa = nullptr;     // device kappa_t (general matrix)
   std::vector<double> gate;    // apodising gate g_t (empty: rectangular)
@@ -95,7 +95,8 @@ int render_core(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char*
 int render_chunk(ssoct_plan* p, hipStream_t stream, const uint16_t* frames, char* ws, const WsLayout& L, int t0,
                  int Fc);
 // shift: the stack is a ring of frames by sweep position and the window
-// starts at slot `shift` (bin q gains exp(+2 pi i q shift / T)); 0 otherwise
+// starts at slot `shift` (read in rotated order, or bin q multiplied by
+// exp(+2 pi i q shift / T) for the dense product); 0 otherwise
 int render_depth(ssoct_plan* p, hipStream_t stream, char* ws, const WsLayout& L, void* vol, int shift = 0);
 // Fresnel-stage launches per render (chunks of frames, or of bins in the depth-first order)
 int fresnel_chunks(const ssoct_plan* p);

@@ -5,14 +5,15 @@
 // Every frame is rescaled and Fresnel-transformed once, into slot
 // seq mod T of a ring of holograms (the tables are indexed by sweep
 // position, so slot p always holds a frame recorded at lambda_p).  A window
-// starting at frame j holds slots j mod T .. j mod T - 1 in time order; the
-// DFT is circular, so the depth transform of the ring in slot order equals
-// the window's transform up to the factor exp(+2 pi i q (j mod T) / T) on bin
-// q, which the depth kernels apply in their epilogue.  A depth transform,
-// the cuts and their copy to pinned host memory are launched every `hop`
-// frames into one of `slots` output volumes.  All work runs in order on one
-// stream, so a ring slot is never overwritten before the transforms that
-// read it.
+// starting at frame j holds slots j mod T .. j mod T - 1 in time order: the
+// FFT and factored depth kernels read slot (t + j) mod T as frame t; the
+// dense product transforms the ring in slot order and multiplies bin q by
+// exp(+2 pi i q (j mod T) / T) (the same for a circular DFT).  A depth
+// transform and the cuts are launched every `hop` frames into one of `slots`
+// output volumes; the cuts' copy to pinned host memory runs on a second
+// stream after an event, overlapping the next window.  Frames and kernels
+// run in order on the first stream, so a ring slot is never overwritten
+// before the transforms that read it.
 #include <atomic>
 #include <chrono>
 #include <cstring>
