@@ -33,23 +33,37 @@ namespace ssoct {
 // times the twiddles, into lds as [q2][t1][px].  With shift > 0 the stack is
 // a ring whose window starts `shift` slots in: h[t] is ring slot (t + shift) mod T.
 template <int T2, int DIR, int PX>
-__device__ __forceinline__ void fft_stage_a(const float2* __restrict__ H, const float2* __restrict__ wt, float2* lds,
-                                            int P, int base, int px, int r, bool live, int shift = 0) {
+__device__ __forceinline__ void fft_stage_a_regs(const float2* __restrict__ H, float2 (&a)[T2], int P, int base,
+                                                 int px, int r, bool live, int shift) {
   constexpr int T = 16 * T2;
-  constexpr int ED = -DIR;           // engine sign: forward depth DFT has exponent -2 pi i q t / T
-  float2 a[T2];
 #pragma unroll
   for (int t2 = 0; t2 < T2; ++t2) {
     const int slot = (r + 16 * t2 + shift) & (T - 1);
     a[t2] = live ? ld_once<SSOCT_DFFT_NT>(H + (size_t)slot * P + base + px) : make_float2(0.f, 0.f);
   }
-  if constexpr (T2 > 1) dft_small<T2, ED>(a);
+  if constexpr (T2 > 1) dft_small<T2, -DIR>(a);   // engine sign: forward depth DFT has exponent -2 pi i q t / T
+}
+
+// bins q2 = q0 .. q0 + NQ - 1 of stage A, times the twiddles, into lds as [q2 - q0][t1][px]
+template <int T2, int DIR, int PX, int NQ>
+__device__ __forceinline__ void fft_stage_a_publish(const float2 (&a)[T2], const float2* __restrict__ wt,
+                                                    float2* lds, int q0, int px, int r) {
+  constexpr int T = 16 * T2;
 #pragma unroll
-  for (int q2 = 0; q2 < T2; ++q2) {
+  for (int ql = 0; ql < NQ; ++ql) {
+    const int q2 = q0 + ql;
     float2 w = wt[(q2 * r) % T];     // exp(-2 pi i q2 t1 / T), FP64-derived
     if constexpr (DIR < 0) w = cconj(w);
-    lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], w);
+    lds[(ql * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], w);
   }
+}
+
+template <int T2, int DIR, int PX>
+__device__ __forceinline__ void fft_stage_a(const float2* __restrict__ H, const float2* __restrict__ wt, float2* lds,
+                                            int P, int base, int px, int r, bool live, int shift = 0) {
+  float2 a[T2];
+  fft_stage_a_regs<T2, DIR, PX>(H, a, P, base, px, r, live, shift);
+  fft_stage_a_publish<T2, DIR, PX, T2>(a, wt, lds, 0, px, r);
 }
 
 // stage B for bin column q2 = r: 16-point DFT over t1 of the LDS tile
@@ -83,7 +97,7 @@ __global__ __launch_bounds__(16 * PX) void k_depth_fft(const float2* __restrict_
     const bool live = base + px < P;
     fft_stage_a<T2, DIR, PX>(H, wt, lds, P, base, px, r, live, shift);
     __syncthreads();
-    if (r < T2) {
+    if (r < T2) {   // stage B for bin column q2 = r
       float2 b[16];
       fft_stage_b<T2, DIR, PX>(lds, px, r, b);
       if (live) {
