@@ -49,6 +49,20 @@ __device__ __forceinline__ double dft_real_form(int row, int k, int n) {
   return (row & 1) ? s : c;
 }
 
+// Paired real form of the n-point DFT matrix (n = 2..16, 16 rows): row 0 =
+// W_0, row 1 = W_{n/2} (both real), rows 2k, 2k + 1 = Re W_k, Im W_k for
+// k = 1 .. n/2 - 1; rows >= n and columns >= n are zero.  With the products
+// A = R h_re and B = R h_im, V[k] = (A_2k - B_2k+1, B_2k + A_2k+1) and
+// V[n - k] = (A_2k + B_2k+1, B_2k - A_2k+1): n real rows give all n outputs.
+__device__ __forceinline__ double dft_pair_form(int row, int k, int n) {
+  if (row >= n || k >= n) return 0.0;
+  if (row == 0) return 1.0;
+  if (row == 1) return (k & 1) ? -1.0 : 1.0;
+  double s, c;
+  sincospi(-2.0 * (double)(((row >> 1) * k) % n) / (double)n, &s, &c);
+  return (row & 1) ? s : c;
+}
+
 // hi | lo << 16 of an FP64 value in FP16 or BF16 (hi = RNE(x), lo = RNE(x - hi))
 template <bool BF>
 __device__ __forceinline__ uint32_t split_pack64(double x) {
@@ -98,25 +112,33 @@ __device__ __forceinline__ void mfma16_step(const uint2 (&e)[8], uint4 ahi, uint
   acc_im = mfma_x16<PT_::BF>(ahi, im_hi, acc_im);
 }
 
-// Per-lane A operands: the real-form T2-point (stage A) and 16-point (stage B)
-// DFT matrices, row lc, as 16 dwords per lane: FP32 a[0..T2/2) at 0, b[0..8)
-// at 8; 16-bit ahi, alo, bhi, blo at 0, 4, 8, 12.  Built once per plan from
-// FP64 (F4_OPS_DWORDS per lane, 64 lanes) and loaded by every workgroup.
+// Per-lane A operands of the T2-point (stage A) and 16-point (stage B) DFT
+// matrices, as 16 dwords per lane.  FP32 (v_mfma_f32_16x16x4_f32, lane l
+// holds A[l % 16][l / 16] of each K-step of 4): the paired form, a[s] at s,
+// b[s] at 8 + s.  16-bit (32x32x16 tiles): the real form, row l % 32,
+// ahi, alo, bhi, blo at 0, 4, 8, 12.  Built once per plan from FP64
+// (F4_OPS_DWORDS per lane, 64 lanes) and loaded by every workgroup.
 constexpr int F4_OPS_DWORDS = 16;
+
+template <int T2>
+struct PairSteps {
+  static constexpr int KA = (T2 + 3) / 4;   // K-steps of stage A (K = T2, zero-padded to 4)
+  static constexpr int KB = 4;              // K-steps of stage B (K = 16)
+};
 
 template <int T2, int PREC>
 struct AOps {
-  float a[PrecTraits<PREC>::F32 ? T2 / 2 : 1], b[PrecTraits<PREC>::F32 ? 8 : 1];
+  float a[PrecTraits<PREC>::F32 ? PairSteps<T2>::KA : 1], b[PrecTraits<PREC>::F32 ? 4 : 1];
   uint4 ahi, alo, bhi, blo;
-  __device__ __forceinline__ void build(int lc, int lh) {
+  __device__ __forceinline__ void build(int l) {
     if constexpr (PrecTraits<PREC>::F32) {
 #pragma unroll
-      for (int s = 0; s < T2 / 2; ++s) a[s] = (float)dft_real_form(lc, 2 * s + lh, T2);
+      for (int s = 0; s < PairSteps<T2>::KA; ++s) a[s] = (float)dft_pair_form(l % 16, 4 * s + l / 16, T2);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) b[s] = (float)dft_real_form(lc, 2 * s + lh, 16);
+      for (int s = 0; s < 4; ++s) b[s] = (float)dft_pair_form(l % 16, 4 * s + l / 16, 16);
     } else {
-      a_operand16<PrecTraits<PREC>::BF>(lc, 8 * lh, T2, ahi, alo);
-      a_operand16<PrecTraits<PREC>::BF>(lc, 8 * lh, 16, bhi, blo);
+      a_operand16<PrecTraits<PREC>::BF>(l & 31, 8 * (l >> 5), T2, ahi, alo);
+      a_operand16<PrecTraits<PREC>::BF>(l & 31, 8 * (l >> 5), 16, bhi, blo);
     }
   }
   __device__ __forceinline__ void store(uint32_t* dst) const {
@@ -124,9 +146,9 @@ struct AOps {
     if constexpr (PrecTraits<PREC>::F32) {
       uint32_t w[16] = {};
 #pragma unroll
-      for (int s = 0; s < T2 / 2; ++s) w[s] = __float_as_uint(a[s]);
+      for (int s = 0; s < PairSteps<T2>::KA; ++s) w[s] = __float_as_uint(a[s]);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) w[8 + s] = __float_as_uint(b[s]);
+      for (int s = 0; s < 4; ++s) w[8 + s] = __float_as_uint(b[s]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) q[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
     } else {
@@ -143,9 +165,9 @@ struct AOps {
       const uint32_t w[16] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w,
                               q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
 #pragma unroll
-      for (int s = 0; s < T2 / 2; ++s) a[s] = __uint_as_float(w[s]);
+      for (int s = 0; s < PairSteps<T2>::KA; ++s) a[s] = __uint_as_float(w[s]);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) b[s] = __uint_as_float(w[8 + s]);
+      for (int s = 0; s < 4; ++s) b[s] = __uint_as_float(w[8 + s]);
     } else {
       ahi = q[0]; alo = q[1]; bhi = q[2]; blo = q[3];
     }
@@ -156,7 +178,7 @@ template <int T2, int PREC>
 __global__ void k_4step_operands(uint32_t* __restrict__ ops) {
   const int l = threadIdx.x;   // 64 lanes
   AOps<T2, PREC> A;
-  A.build(l & 31, l >> 5);
+  A.build(l);
   A.store(ops + (size_t)l * F4_OPS_DWORDS);
 }
 
@@ -173,13 +195,7 @@ __device__ __forceinline__ void stage_a_store(uint2* dst, int j, int lc, int lh,
     if (q2 >= T2) continue;
     const float2 a = make_float2(ar[r] - ai[r + 1], ai[r] + ar[r + 1]);
     const float2 b = q2 == 0 ? a : cmul(a, wt[(q2 * t1) % T]);
-    uint2 v;
-    if constexpr (PrecTraits<PREC>::F32) {
-      v = make_uint2(__float_as_uint(b.x), __float_as_uint(b.y));
-    } else {
-      v = make_uint2(split_pack<HFMT>(b.x * mid_scale), split_pack<HFMT>(b.y * mid_scale));
-    }
-    dst[(q2 * 16 + t1) * PX + px] = v;
+    dst[(q2 * 16 + t1) * PX + px] = make_uint2(split_pack<HFMT>(b.x * mid_scale), split_pack<HFMT>(b.y * mid_scale));
   }
 }
 
@@ -195,19 +211,10 @@ __device__ __forceinline__ void stage_b(const uint2* in, int j, int lc, int lh, 
     br[r] = 0.f;
     bi[r] = 0.f;
   }
-  if constexpr (PrecTraits<PREC>::F32) {
+  uint2 e[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const uint2 b = in[(q2 * 16 + 2 * s + lh) * PX + px];
-      br = __builtin_amdgcn_mfma_f32_32x32x2f32(A.b[s], __uint_as_float(b.x), br, 0, 0, 0);
-      bi = __builtin_amdgcn_mfma_f32_32x32x2f32(A.b[s], __uint_as_float(b.y), bi, 0, 0, 0);
-    }
-  } else {
-    uint2 e[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) e[i] = in[(q2 * 16 + 8 * lh + i) * PX + px];
-    mfma16_step<PREC>(e, A.bhi, A.blo, br, bi);
-  }
+  for (int i = 0; i < 8; ++i) e[i] = in[(q2 * 16 + 8 * lh + i) * PX + px];
+  mfma16_step<PREC>(e, A.bhi, A.blo, br, bi);
 #pragma unroll
   for (int r = 0; r < 16; r += 2) {
     const int q1 = (8 * (r >> 2) + 4 * lh + (r & 3)) >> 1;
@@ -228,6 +235,8 @@ struct F4Shape {
   static constexpr int TA = 16 * PX / 32;                       // stage-A column tiles (t1, pixel)
   static constexpr int TB = (T2 * PX + 31) / 32;                // stage-B column tiles (q2, pixel)
   static constexpr int TA_W = (TA + NW - 1) / NW, TB_W = (TB + NW - 1) / NW;
+  static constexpr int TA16 = PX, TB16 = T2 * PX / 16;       // 16-column tiles (FP32 paired form)
+  static constexpr int TA16_W = (TA16 + NW - 1) / NW, TB16_W = (TB16 + NW - 1) / NW;
   static_assert(PX == 16 || PX == 32, "16 or 32 pixels per tile");
   static_assert(T2 >= 2 && T2 <= 16, "T = 32 .. 256");
 };
@@ -243,11 +252,9 @@ __device__ __forceinline__ void load_stage_a(const uint2* __restrict__ H, int P,
   const uint2* src = H + p0 + px;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    // FP32: k = 2 i + lh (i < T2/2); 16-bit: k = 8 lh + i (k < T2)
-    const int t2 = PrecTraits<PREC>::F32 ? 2 * i + lh : 8 * lh + i;
-    const bool ok = PrecTraits<PREC>::F32 ? i < T2 / 2 : t2 < T2;
+    const int t2 = 8 * lh + i;   // k = 8 lh + i of the 32x32x16 step
     const int slot = (t1 + 16 * t2 + shift) & (T - 1);   // a ring window starting `shift` slots in
-    e[i] = ok ? ld_once<SSOCT_F4_NT>(src + (size_t)slot * P) : make_uint2(0u, 0u);
+    e[i] = t2 < T2 ? ld_once<SSOCT_F4_NT>(src + (size_t)slot * P) : make_uint2(0u, 0u);
   }
 }
 
@@ -258,15 +265,85 @@ __device__ __forceinline__ void stage_a_regs(const uint2 (&e)[8], const AOps<T2,
     ar[r] = 0.f;
     ai[r] = 0.f;
   }
-  if constexpr (PrecTraits<PREC>::F32) {
+  mfma16_step<PREC>(e, A.ahi, A.alo, ar, ai);
+}
+
+// ------------------------------------------------------------------ FP32: paired form on 16x16x4 tiles
+// A 16-column tile: lane l is column c = l % 16 of the tile and K-row
+// l / 16 of every step; the accumulator rows 4 (l / 16) + r, r = 0..3, are
+// two row pairs of the paired form.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// outputs of the paired form held by lane group g = l / 16 for an n-point
+// matrix: f(k, value) for each DFT index k it completes
+template <typename F>
+__device__ __forceinline__ void pair_outputs(const v4f& re, const v4f& im, int g, int n, F&& f) {
 #pragma unroll
-    for (int s = 0; s < T2 / 2; ++s) {
-      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[s], __uint_as_float(e[s].x), ar, 0, 0, 0);
-      ai = __builtin_amdgcn_mfma_f32_32x32x2f32(A.a[s], __uint_as_float(e[s].y), ai, 0, 0, 0);
+  for (int h = 0; h < 2; ++h) {
+    const float Ar = re[2 * h], Br = re[2 * h + 1], Ai = im[2 * h], Bi = im[2 * h + 1];
+    if (g == 0 && h == 0) {          // rows W_0 and W_{n/2}
+      f(0, make_float2(Ar, Ai));
+      f(n / 2, make_float2(Br, Bi));
+    } else {
+      const int k = 2 * g + h;       // rows Re W_k, Im W_k
+      if (k < n / 2) {
+        f(k, make_float2(Ar - Bi, Ai + Br));
+        f(n - k, make_float2(Ar + Bi, Ai - Br));
+      }
     }
-  } else {
-    mfma16_step<PREC>(e, A.ahi, A.alo, ar, ai);
   }
+}
+
+// stage A, 16-column tile j of (t1, pixel): operands straight from the stack
+template <int T2, int PX>
+__device__ __forceinline__ void load_stage_a_pair(const uint2* __restrict__ H, int P, int p0, int j, int l,
+                                                  int shift, uint2 (&e)[PairSteps<T2>::KA]) {
+  constexpr int T = 16 * T2;
+  const int t1 = (16 * j + l % 16) / PX, px = (16 * j + l % 16) % PX;
+  const uint2* src = H + p0 + px;
+#pragma unroll
+  for (int s = 0; s < PairSteps<T2>::KA; ++s) {
+    const int t2 = 4 * s + l / 16;
+    const int slot = (t1 + 16 * t2 + shift) & (T - 1);   // a ring window starting `shift` slots in
+    e[s] = t2 < T2 ? ld_once<SSOCT_F4_NT>(src + (size_t)slot * P) : make_uint2(0u, 0u);
+  }
+}
+
+template <int T2, int PX>
+__device__ __forceinline__ void stage_a_pair(const uint2 (&e)[PairSteps<T2>::KA], const AOps<T2, DP_F32>& A,
+                                             uint2* dst, int j, int l, const float2* __restrict__ wt) {
+  constexpr int T = 16 * T2;
+  v4f re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < PairSteps<T2>::KA; ++s) {
+    re = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[s], __uint_as_float(e[s].x), re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[s], __uint_as_float(e[s].y), im, 0, 0, 0);
+  }
+  const int t1 = (16 * j + l % 16) / PX, px = (16 * j + l % 16) % PX;
+  pair_outputs(re, im, l / 16, T2, [&](int q2, float2 a) {
+    const float2 b = q2 == 0 ? a : cmul(a, wt[(q2 * t1) % T]);
+    dst[(q2 * 16 + t1) * PX + px] = make_uint2(__float_as_uint(b.x), __float_as_uint(b.y));
+  });
+}
+
+template <int T2, int EPI, int PX>
+__device__ __forceinline__ void stage_b_pair(const uint2* in, int j, int l, const AOps<T2, DP_F32>& A,
+                                             void* __restrict__ out, int P, int p0) {
+  const int q2 = (16 * j + l % 16) / PX, px = (16 * j + l % 16) % PX;
+  v4f re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const uint2 b = in[(q2 * 16 + 4 * s + l / 16) * PX + px];
+    re = __builtin_amdgcn_mfma_f32_16x16x4f32(A.b[s], __uint_as_float(b.x), re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_16x16x4f32(A.b[s], __uint_as_float(b.y), im, 0, 0, 0);
+  }
+  pair_outputs(re, im, l / 16, 16, [&](int q1, float2 V) {
+    const size_t idx = (size_t)(q2 + T2 * q1) * P + p0 + px;
+    if constexpr (EPI == EPI_ABS)
+      st_once<SSOCT_F4_NT>(reinterpret_cast<float*>(out) + idx, sqrtf(V.x * V.x + V.y * V.y));
+    else
+      st_once<SSOCT_F4_NT>(reinterpret_cast<float2*>(out) + idx, V);
+  });
 }
 
 // One workgroup per tile of PX pixels and all T frames: the stage-A
@@ -283,27 +360,49 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lc = l & 31, lh = l >> 5;
   const int p0 = blockIdx.x * PX;    // grid = P / PX
-  uint2 e[S::TA_W][8];
-#pragma unroll
-  for (int jj = 0; jj < S::TA_W; ++jj) {
-    const int j = w + S::NW * jj;
-    if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, shift, e[jj]);
-  }
   AOps<T2, PREC> A;
-  A.load(ops + (size_t)l * F4_OPS_DWORDS);
+  if constexpr (PrecTraits<PREC>::F32) {
+    uint2 e[S::TA16_W][PairSteps<T2>::KA];
 #pragma unroll
-  for (int jj = 0; jj < S::TA_W; ++jj) {
-    const int j = w + S::NW * jj;
-    if (j >= S::TA) break;
-    v16f ar, ai;
-    stage_a_regs<T2, PREC>(e[jj], A, ar, ai);
-    stage_a_store<T2, PREC, PX>(buf, j, lc, lh, ar, ai, wt, mid_scale);
-  }
-  __syncthreads();
+    for (int jj = 0; jj < S::TA16_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j < S::TA16) load_stage_a_pair<T2, PX>(H, P, p0, j, l, shift, e[jj]);
+    }
+    A.load(ops + (size_t)l * F4_OPS_DWORDS);
 #pragma unroll
-  for (int jj = 0; jj < S::TB_W; ++jj) {
-    const int j = w + S::NW * jj;
-    if (j < S::TB) stage_b<T2, PREC, EPI, PX>(buf, j, lc, lh, A, out, P, p0, out_scale);
+    for (int jj = 0; jj < S::TA16_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j >= S::TA16) break;
+      stage_a_pair<T2, PX>(e[jj], A, buf, j, l, wt);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < S::TB16_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j < S::TB16) stage_b_pair<T2, EPI, PX>(buf, j, l, A, out, P, p0);
+    }
+  } else {
+    uint2 e[S::TA_W][8];
+#pragma unroll
+    for (int jj = 0; jj < S::TA_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j < S::TA) load_stage_a<T2, PREC, PX>(H, P, p0, j, lc, lh, shift, e[jj]);
+    }
+    A.load(ops + (size_t)l * F4_OPS_DWORDS);
+#pragma unroll
+    for (int jj = 0; jj < S::TA_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j >= S::TA) break;
+      v16f ar, ai;
+      stage_a_regs<T2, PREC>(e[jj], A, ar, ai);
+      stage_a_store<T2, PREC, PX>(buf, j, lc, lh, ar, ai, wt, mid_scale);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < S::TB_W; ++jj) {
+      const int j = w + S::NW * jj;
+      if (j < S::TB) stage_b<T2, PREC, EPI, PX>(buf, j, lc, lh, A, out, P, p0, out_scale);
+    }
   }
 }
 
