@@ -62,13 +62,20 @@ def depth_flops(T: int, N: int, form: str) -> float:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code (the .hip kernels and the headers they include),
+    comments and blank lines removed, so that editing a comment does not void
+    counters measured on the same code."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_08960_amd", "csrc")
-    # device code only: the .hip kernels and the headers they include
     for name in sorted(n for n in os.listdir(csrc) if n.endswith(".hip") or (n.endswith(".hpp") and n != "plan.hpp")):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(name.encode())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -2,22 +2,24 @@
 // T2 = 2..16).  With t = t1 + 16 t2 and q = q2 + T2 q1,
 //   V[q2 + T2 q1] = sum_t1 W16[q1][t1] wT^(q2 t1) sum_t2 WT2[q2][t2] h[t1 + 16 t2],
 // W_n[a][b] = exp(-2 pi i a b / n), wT = exp(-2 pi i / T).  Each inner sum
-// is the product of a small DFT matrix in real form (row 2k = Re W[k],
-// row 2k + 1 = Im W[k], padded to 32 rows) with the stack viewed as reals,
-// on v_mfma_f32_32x32x2_f32 (FP32) or v_mfma_f32_32x32x16_{f16,bf16} (hi
-// only, or split hi*hi + hi*lo + lo*hi), always with FP32 accumulation:
-// 2 x 32 x (T2 + 16) x 16 x 2 flops per pixel (65536 at T = 256, 8x fewer
-// than the dense real-form product), so every precision is bound by the
-// 16 B/voxel of the stack and the volume.
+// is the product of a small DFT matrix in real form with the stack viewed as
+// reals, always with FP32 accumulation:
+//  * FP16/BF16 (hi only, or split hi*hi + hi*lo + lo*hi): rows 2k, 2k + 1 =
+//    Re W[k], Im W[k], padded to 32 rows, on v_mfma_f32_32x32x16_{f16,bf16};
+//    2 x 32 x (T2 + 16) x 16 x 2 flops per pixel and product (65536 at
+//    T = 256, 8x fewer than the dense real-form product);
+//  * FP32: the paired form (16 rows: W_0, W_{n/2}, Re W_k and Im W_k for
+//    k = 1 .. n/2 - 1, which give V[k] and V[n - k]) on
+//    v_mfma_f32_16x16x4_f32, half that work again;
+// so every precision is bound by the 16 B/voxel of the stack and the volume.
 //
 // A workgroup (8 waves) owns 32 pixels and all T frames.  Stage A: each
-// wave takes 32-column MFMA tiles of columns (t1, pixel), K = t2, loading
-// its operands from HBM straight into registers (each half-wave load is 32
-// consecutive pixels of one frame); the products, times the twiddle
-// wT^(q2 t1), cross LDS once as [q2][t1][pixel] (split into hi/lo for the
-// 16-bit forms).  Stage B: tiles of columns (q2, pixel), K = t1; the
-// accumulator holds V for 32 consecutive pixels of each bin, written with
-// non-temporal stores.
+// wave takes MFMA tiles of columns (t1, pixel), K = t2, loading its operands
+// from HBM straight into registers (each load covers consecutive pixels of
+// one frame); the products, times the twiddle wT^(q2 t1), cross LDS once as
+// [q2][t1][pixel] (split into hi/lo for the 16-bit forms).  Stage B: tiles
+// of columns (q2, pixel), K = t1; the accumulator holds V for consecutive
+// pixels of each bin, written with non-temporal stores.
 #include "access.hpp"
 #include "fft_engine.hpp"
 #include "internal.hpp"
