@@ -171,6 +171,24 @@ def test_autograd_function_matches_fused_backward(gpu_lib):
     assert rel(gp.numpy(), ref[17:]) <= 1e-4
 
 
+def test_screen_built_for_gradient_after_render_with_cached_tables(gpu_lib):
+    """A render leaves the tables cached; a gradient call with the same parameters must still build the
+    adjoint's aberration screen: bitwise equal to the gradient of a fresh plan, and again after the
+    coefficients change and come back."""
+    from paper_2003_08960_amd.api import Plan
+    T, N = 32, 64
+    frames, lam, phi, zc = small_case(T, N, seed=31)
+    fr = torch.from_numpy(frames).cuda()
+    fresh = Plan(T, N, backward=True, precision="fp32_fft").backward_sharpness(fr, lam, 20e-6, 0.05, phi, zc).clone()
+    plan = Plan(T, N, backward=True, precision="fp32_fft")
+    plan.render(fr, lam, 20e-6, 0.05, phi, zc)
+    g1 = plan.backward_sharpness(fr, lam, 20e-6, 0.05, phi, zc).clone()
+    assert torch.equal(g1, fresh)
+    plan.backward_sharpness(fr, lam, 20e-6, 0.05, phi, 2.0 * zc)
+    g2 = plan.backward_sharpness(fr, lam, 20e-6, 0.05, phi, zc).clone()
+    assert torch.equal(g2, fresh)
+
+
 def test_backward_rejects_eq6(gpu_lib):
     from paper_2003_08960_amd import native
     from paper_2003_08960_amd.api import Plan
