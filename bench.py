@@ -525,7 +525,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the render of one sweep runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build); use --gpus 1", file=sys.stderr)
+              "(sharding a volume across GPUs is described in the design notes only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

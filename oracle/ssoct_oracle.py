@@ -18,7 +18,7 @@ Every step below is the plain definition, evaluated in float64/complex128.
 Library FFTs serve as the discrete Fourier sums; ``render_columns`` evaluates
 the same sums directly, term by term, for sampled outputs and brute-force pins.
 
-Readings of points the paper leaves open (each one also listed in the design doc):
+Readings of points the paper leaves open:
 
   * lambda_1 ("start wavelength", the longest of the sweep) is taken as
     lambda_ref = max(lambda).  Then s_t = lambda_t / lambda_ref <= 1 and every

@@ -21,7 +21,8 @@ HIP_SOURCES = ["tables.hip", "stage_a.hip", "depth.hip", "depth_fft.hip", "depth
 CPP_SOURCES = ["abi.cpp", "stream.cpp", "slide.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{os.path.join(ROOT, 'include')}"]
-# packed FP32 instructions are kept out of every kernel (build notes)
+# packed FP32 instructions are kept out of every kernel (the compiler would otherwise form them from
+# scalar and float2 code)
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast", "-munsafe-fp-atomics"]
 
