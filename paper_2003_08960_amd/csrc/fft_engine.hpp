@@ -194,13 +194,56 @@ __device__ __forceinline__ void exchange_sync() {
   }
 }
 
+// Twiddle sources of fft_group.  TwMem reads the table of TwPlan for thread
+// j at every use; TwRegs holds the same entries in registers, loaded once by
+// a kernel that runs many transforms per thread, so that its loads can be
+// completed before the transform loop starts.
+template <int N>
+struct TwMem {
+  const float2* __restrict__ tw;
+  int j;
+  __device__ __forceinline__ float2 w16(int p, int r) const {
+    return tw[TwPlan<N>::off16(p) + j * TwPlan<N>::E16 + r - 1];
+  }
+  __device__ __forceinline__ float2 wl(int i) const { return tw[TwPlan<N>::OFF_L + j * TwPlan<N>::EL + i]; }
+};
+
+template <int N>
+struct TwRegs {
+  using S = FFTShape<N>;
+  static constexpr int P = S::P16 > 1 ? S::P16 - 1 : 1;
+  static constexpr int E = TwPlan<N>::EL > 0 ? TwPlan<N>::EL : 1;
+  float2 a[P][15];
+  float2 b[E];
+  __device__ __forceinline__ float2 w16(int p, int r) const { return a[p - 1][r - 1]; }
+  __device__ __forceinline__ float2 wl(int i) const { return b[i]; }
+};
+
+template <int N>
+__device__ __forceinline__ TwRegs<N> load_tw_regs(const float2* __restrict__ tw, int j) {
+  using S = FFTShape<N>;
+  TwRegs<N> t;
+  const TwMem<N> m{tw, j};
+#pragma unroll
+  for (int p = 1; p < S::P16; ++p) {
+#pragma unroll
+    for (int r = 1; r < 16; ++r) t.a[p - 1][r - 1] = m.w16(p, r);
+  }
+  if constexpr (S::L > 1 && S::P16 > 0) {
+#pragma unroll
+    for (int i = 0; i < TwPlan<N>::EL; ++i) t.b[i] = m.wl(i);
+  }
+  return t;
+}
+
 // Full N-point FFT of one group.  `lds` points to this group's LDS region of
 // FFTShape<N>::LDS complex slots with element stride LS (1 for row FFTs, C
 // for a C-column tile; a compile-time constant so that every LDS address is a
 // base plus an immediate offset).  With WAVE = false every thread of the
 // workgroup must call this the same number of times (workgroup barriers).
-template <int N, int DIR, int LS, bool WAVE = false>
-__device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, const float2* __restrict__ tw) {
+// `tws` is a twiddle source (TwMem or TwRegs) for this thread.
+template <int N, int DIR, int LS, bool WAVE, class TW>
+__device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds, const TW& tws) {
   constexpr int ls = LS;
   using S = FFTShape<N>;
   constexpr int G = S::G;
@@ -208,9 +251,8 @@ __device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, c
 #pragma unroll
   for (int p = 0; p < S::P16; ++p) {
     if (p > 0) {
-      const float2* twj = tw + TwPlan<N>::off16(p) + j * TwPlan<N>::E16;
 #pragma unroll
-      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_dir<DIR>(twj[r - 1]));
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_dir<DIR>(tws.w16(p, r)));
     }
     dft16<DIR>(v);
     const bool last = (p == S::P16 - 1) && (S::L == 1);
@@ -242,16 +284,21 @@ __device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, c
       for (int k = 0; k < L; ++k) v[i * L + k] = lds[lds_slot(j + G * i + k * (N / L)) * ls];
     }
     if constexpr (S::P16 > 0) {
-      const float2* twj = tw + TwPlan<N>::OFF_L + j * TwPlan<N>::EL;
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
 #pragma unroll
-        for (int k = 1; k < L; ++k) v[i * L + k] = cmul(v[i * L + k], tw_dir<DIR>(twj[i * (L - 1) + k - 1]));
+        for (int k = 1; k < L; ++k) v[i * L + k] = cmul(v[i * L + k], tw_dir<DIR>(tws.wl(i * (L - 1) + k - 1)));
       }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) dft_small<L, DIR>(&v[i * L]);
   }
+}
+
+// The same with the twiddles read from the table at every use
+template <int N, int DIR, int LS, bool WAVE = false>
+__device__ __forceinline__ void fft_group(float2 (&v)[16], int j, float2* lds, const float2* __restrict__ tw) {
+  fft_group_tw<N, DIR, LS, WAVE>(v, j, lds, TwMem<N>{tw, j});
 }
 
 }  // namespace ssoct

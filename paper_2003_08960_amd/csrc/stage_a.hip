@@ -188,6 +188,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
   using R = RowCfg<N>;
   constexpr int G = S::G;
   __shared__ RowLds<N> lds;
+  __shared__ AxisTab rtab_s[R::ROWS];   // row table entries of this workgroup's rows
+  // output factor of Eq. 6, read between the row's stores; kept in LDS up to
+  // N = 1024 (at N = 2048 it would leave room for one workgroup per CU)
+  constexpr bool OFS = EQ6 && N <= 1024;
+  __shared__ float2 ofac_s[OFS ? N : 1];
   const int g = threadIdx.x / G, j = threadIdx.x % G;
   const int f = blockIdx.y;
   const int t = t0 + f;
@@ -195,12 +200,26 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
   const uint16_t* I = frames + (size_t)t * N * N;
   const AxisTab* rtab = rows + (size_t)t * N;
   float* rbuf = reinterpret_cast<float*>(lds.xbuf[g]);
-  stage_ctab<N>(lds.ctab, cols + (size_t)t * N);
-
+  // The first row's source loads, the twiddles and the table staging are in
+  // flight together.  The twiddles stay in registers and the staging waits
+  // complete their loads, so no twiddle load is outstanding inside the row
+  // loop.  Inside the loop the next row's table entry comes from LDS: a
+  // global load there would have to wait for the previous row's stores,
+  // which the vector memory counter counts together with the loads.
   AxisTab rt = rtab[m0];
   RowSrc src = load_rows<N>(I, rt.i0, j);
   ARow an = load_arow<ABERR>(apoly, m0);
-  __syncthreads();  // column table visible
+  const TwRegs<N> twr = load_tw_regs<N>(tw, j);
+  stage_ctab<N>(lds.ctab, cols + (size_t)t * N);
+  for (int i = threadIdx.x; i < R::ROWS; i += R::THREADS) rtab_s[i] = rtab[blockIdx.x * R::ROWS + i];
+  if constexpr (OFS) {
+    for (int i = threadIdx.x; i < N; i += R::THREADS) ofac_s[i] = outfac[i];
+  }
+  // Everything above has landed here (the first lerp needs it at once), so
+  // the loop is entered with no load outstanding and its header, shared with
+  // the back edge, does not wait for the stores of the previous row.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
+  __syncthreads();  // column and row tables visible
 #pragma unroll 1
   for (int i = 0; i < R::RPG; ++i) {
     const int m = m0 + i;
@@ -208,7 +227,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
     const AxisTab rc = rt;
     const ARow ar = an;
     if (i + 1 < R::RPG) {  // prefetch the next row of this group
-      rt = rtab[m + 1];
+      rt = rtab_s[g * R::RPG + i + 1];
       src = load_rows<N>(I, rt.i0, j);
       an = load_arow<ABERR>(apoly, m + 1);
     }
@@ -221,13 +240,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
       const int n = j + k * G;
       v[k] = row_input<N, ABERR>(rbuf, lds.ctab[n], rc.fac, ar, n);
     }
-    fft_group<N, +1, 1, R::WAVE>(v, j, lds.xbuf[g], tw);
+    fft_group_tw<N, +1, 1, R::WAVE>(v, j, lds.xbuf[g], twr);
     float2* dst = inter + ((size_t)f * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int vv = j + out_offset<N>(e);
       float2 val = v[e];
-      if constexpr (EQ6) val = cmul(val, outfac[vv]);
+      if constexpr (EQ6) val = cmul(val, OFS ? ofac_s[vv] : outfac[vv]);
       st_once<SSOCT_ROW_NT>(dst + vv, val);
     }
   }
@@ -250,32 +269,45 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
   constexpr int G = S::G;
   __shared__ AxisTab ctab[N];
   __shared__ float2 xbuf[R::GR][RowLds<N>::XS];
+  __shared__ float2 rfac_s[R::ROWS];   // row factors of this workgroup's rows
+  constexpr bool OFS = EQ6 && N <= 1024;  // output factor of Eq. 6 in LDS, as in k_row_pass
+  __shared__ float2 ofac_s[OFS ? N : 1];
   const int g = threadIdx.x / G, j = threadIdx.x % G;
   const int f = blockIdx.y;
   const int q = qa + f;
   const bool both = q >= 1 && 2 * q < T;
   const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
-  stage_ctab<N>(ctab, cols0);
   float2 nxt[16];
   {
     const float2* src = Gq + ((size_t)q * N + m0) * N;
 #pragma unroll
     for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
   }
-  __syncthreads();  // column table visible
+  // as in k_row_pass: twiddles in registers, per-row table entries in LDS,
+  // and no load outstanding when the loop is entered
+  const TwRegs<N> twr = load_tw_regs<N>(tw, j);
+  stage_ctab<N>(ctab, cols0);
+  for (int i = threadIdx.x; i < R::ROWS; i += R::THREADS) rfac_s[i] = rows0[blockIdx.x * R::ROWS + i].fac;
+  if constexpr (OFS) {
+    for (int i = threadIdx.x; i < N; i += R::THREADS) ofac_s[i] = outfac[i];
+  }
+  ARow an = load_arow<ABERR>(apoly, m0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
+  __syncthreads();  // column table and row factors visible
 #pragma unroll 1
   for (int i = 0; i < R::RPG; ++i) {
     const int m = m0 + i;
     float2 gv[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) gv[k] = nxt[k];
+    const ARow ar = an;
     if (i + 1 < R::RPG) {  // prefetch the next row of this group
       const float2* src = Gq + ((size_t)q * N + m + 1) * N;
 #pragma unroll
       for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
+      an = load_arow<ABERR>(apoly, m + 1);
     }
-    const float2 rowfac = rows0[m].fac;
-    const ARow ar = load_arow<ABERR>(apoly, m);
+    const float2 rowfac = rfac_s[g * R::RPG + i];
 #pragma unroll 1
     for (int h = 0; h < (both ? 2 : 1); ++h) {
       float2 v[16];
@@ -287,13 +319,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
         v[k] = cmul(fac, h == 0 ? gv[k] : cconj(gv[k]));
       }
       exchange_sync<R::WAVE>();  // the previous transform's exchange reads are done
-      fft_group<N, +1, 1, R::WAVE>(v, j, xbuf[g], tw);
+      fft_group_tw<N, +1, 1, R::WAVE>(v, j, xbuf[g], twr);
       float2* dst = inter + ((size_t)(h == 0 ? f : Fh + f) * N + m) * N;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int vv = j + out_offset<N>(e);
         float2 val = v[e];
-        if constexpr (EQ6) val = cmul(val, outfac[vv]);
+        if constexpr (EQ6) val = cmul(val, OFS ? ofac_s[vv] : outfac[vv]);
         st_once<SSOCT_ROW_NT>(dst + vv, val);
       }
     }
