@@ -290,6 +290,11 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   return status;
 }
 
+// Persistent column workgroups: the tuned count, else the default for N
+static int col_grid_of(const ssoct_plan* p) {
+  return p->col_grid > 0 ? p->col_grid : col_default_grid(p->N, p->cu);
+}
+
 // Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
 // row DFT) into the chunk buffer, then column DFT into H.
 static int depth_grid_for(const ssoct_plan* p) {
@@ -307,7 +312,7 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   const float* ab = p->have_aberr ? p->apoly : nullptr;
   SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
-  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, p->col_grid, s));
+  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p), s));
   return SSOCT_OK;
 }
 
@@ -360,12 +365,12 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
     const int n = nb - qa < fh ? nb - qa : fh;
     SSOCT_HIP(launch_row_pass_g(N, n, qa, T, G, p->rows, p->cols, p->tw, ab, p->outfac, inter, fh, s));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c], s));
-    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, p->col_grid, s));
+    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, col_grid_of(p), s));
     const int ca = qa > 1 ? qa : 1;
     const int cb = qa + n < nconj ? qa + n : nconj;
     if (cb > ca)
       SSOCT_HIP(launch_col_pass_v(N, cb - ca, inter + (size_t)(fh + ca - qa) * P, p->tw, p->outfac,
-                                  V + (size_t)(T - ca) * P, -1, p->col_grid, s));
+                                  V + (size_t)(T - ca) * P, -1, col_grid_of(p), s));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
   }
   if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
@@ -385,7 +390,7 @@ int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, 
       const int Fc = T - t0 < F ? T - t0 : F;
       SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
       SSOCT_HIP(hipEventRecord(kev[2 * c], s));
-      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, p->col_grid, s));
+      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p), s));
       SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
     }
   } else {
@@ -422,7 +427,7 @@ static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, c
                            p->stream));
   for (int t0 = 0; t0 < T; t0 += F) {
     const int Fc = T - t0 < F ? T - t0 : F;
-    SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, p->col_grid, p->stream));
+    SSOCT_HIP(launch_col_pass_adj(N, Fc, t0, beta, p->tw, inter, col_grid_of(p), p->stream));
     SSOCT_HIP(launch_row_pass_adj(N, Fc, t0, frames, p->rows, p->cols, p->tw, p->have_aberr ? p->screen : nullptr,
                                   inter, mono, p->stream));
   }
@@ -637,7 +642,7 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   for (int t0 = 0; t0 < T; t0 += p->F_run) {
     const int Fc = T - t0 < p->F_run ? T - t0 : p->F_run;
     SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));
-    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, HF_F32, 0, p->col_grid, p->stream));
+    SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, HF_F32, 0, col_grid_of(p), p->stream));
   }
   // |V| <= T N^2 65535: scale by 2^-e so that 4 |V^|^3 stays finite in FP32
   const double bound = (double)T * N * N * 65535.0;
@@ -764,7 +769,8 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
   int bestF = p->F_run, bestC = p->col_grid, bestD = p->depth_grid;
   float best = 1e30f, a, b;
   const int Fs[3] = {p->F, p->F / 2, p->F / 4};
-  const int Cs[3] = {0, 256, 1024};
+  const int c0 = col_default_grid(p->N, p->cu);
+  const int Cs[3] = {0, 2 * c0, 4 * c0};
   int rc = SSOCT_OK;
   for (int fi = 0; fi < 3 && rc == SSOCT_OK; ++fi) {
     if (Fs[fi] < 1 || (fi > 0 && Fs[fi] == Fs[fi - 1])) continue;

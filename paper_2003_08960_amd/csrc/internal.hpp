@@ -97,6 +97,9 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
                            const float2* outfac, float2* inter, hipStream_t s);
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
                            const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
+// Default persistent grid of the column passes (forward, adjoint, volume
+// output) on a device with `cu` compute units
+int col_default_grid(int N, int cu);
 
 // Angular-spectrum propagation of frames [t0, t0 + F) into H (format fmt):
 // row DFT^-, column DFT^- x transfer function x DFT^+, row DFT^+ (uncentred,

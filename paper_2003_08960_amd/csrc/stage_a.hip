@@ -34,7 +34,11 @@ namespace ssoct {
 #define SSOCT_COL_MIN 16         // minimum adjacent columns per column workgroup (128 B row segments)
 #endif
 #ifndef SSOCT_COL_PREFETCH
-#define SSOCT_COL_PREFETCH 0     // load the next column tile while transforming the current one
+#define SSOCT_COL_PREFETCH 0     // load the next column tile while transforming the current one (always on
+                                 // where the twiddles are in LDS, see SSOCT_COL_TWL)
+#endif
+#ifndef SSOCT_COL_TWL
+#define SSOCT_COL_TWL 1          // column pass: twiddles in LDS where the exchange buffer leaves room
 #endif
 #ifndef SSOCT_ROW_NT
 #define SSOCT_ROW_NT 0           // row pass: non-temporal stores of the intermediate
@@ -78,6 +82,16 @@ struct ColCfg {
   static constexpr int C1 = C0 < SSOCT_COL_MIN ? SSOCT_COL_MIN : (C0 > N ? N : C0);
   static constexpr int C = C1 * G > 1024 ? 1024 / G : C1;
   static constexpr int THREADS = C * G;
+};
+// LDS of the column pass: the exchange buffer of C columns, plus the twiddle
+// table where the two fit in one CU's 160 KB (every N <= 1024)
+template <int N>
+struct ColLds {
+  static constexpr int XB = FFTShape<N>::LDS * ColCfg<N>::C;
+  static constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
+  static constexpr bool TWL = SSOCT_COL_TWL && (XB + TWN) * 8 <= 163840;
+  static constexpr bool PF = TWL || SSOCT_COL_PREFETCH;    // next tile prefetched into registers
+  static constexpr int BYTES = (XB + (TWL ? TWN : 1)) * 8;
 };
 
 // Source rows y0 and y0 + 1 of Eq. 5 for one output row: thread j of a group
@@ -485,7 +499,15 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
   constexpr int G = S::G;
   constexpr int C = ColCfg<N>::C;
   constexpr int NCB = N / C;  // column blocks per frame
-  __shared__ float2 xbuf[S::LDS * C];
+  // The twiddle table goes to LDS where the exchange buffer leaves room for
+  // it (N <= 1024).  That frees the registers the twiddles would hold for a
+  // prefetch of the next tile, which then loads while the current one is
+  // transformed: one 1024-thread workgroup fills a CU, so without it the
+  // CU's memory and ALUs take turns.
+  constexpr bool TWL = ColLds<N>::TWL;
+  constexpr bool PF = ColLds<N>::PF;
+  __shared__ float2 xbuf[ColLds<N>::XB];
+  __shared__ float2 twl[TWL ? ColLds<N>::TWN : 1];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   float2 pf[16];
   auto issue = [&](int tile) {
@@ -495,11 +517,19 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
     for (int k = 0; k < 16; ++k) pf[k] = ld_once<SSOCT_COL_NT_LD>(s + (size_t)(j + k * G) * N);
   };
   int tile = blockIdx.x;
-  if (SSOCT_COL_PREFETCH && tile < ntiles) issue(tile);
+  if (PF && tile < ntiles) issue(tile);
+  if constexpr (TWL) {
+    for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += ColCfg<N>::THREADS) twl[i] = tw[i];
+    // the first tile has landed; the loop is entered with no load
+    // outstanding, so waiting for a prefetched tile inside it leaves the
+    // previous tile's stores in flight
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
+    __syncthreads();  // twiddles visible
+  }
 #pragma unroll 1
   for (; tile < ntiles; tile += gridDim.x) {
     float2 v[16];
-    if constexpr (SSOCT_COL_PREFETCH) {
+    if constexpr (PF) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) v[k] = pf[k];
       if (tile + (int)gridDim.x < ntiles) issue(tile + gridDim.x);
@@ -509,7 +539,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
       for (int k = 0; k < 16; ++k) v[k] = pf[k];
     }
     const int f = tile / NCB, col = (tile % NCB) * C + c;
-    fft_group<N, DIR, C>(v, j, xbuf + c, tw);
+    if constexpr (TWL) fft_group_tw<N, DIR, C, false>(v, j, xbuf + c, TwMem<N>{twl, j});
+    else fft_group<N, DIR, C>(v, j, xbuf + c, tw);
     const long long fo = (long long)f * fstride * N * N;   // output frame f at dst + f fstride N^2
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -637,6 +668,27 @@ static hipError_t row_pass_n(int F, int t0, const uint16_t* frames, const AxisTa
 static int col_grid(int ntiles, int req) {
   const int g = req > 0 ? req : 512;
   return ntiles < g ? ntiles : g;
+}
+
+template <int N>
+static int col_default_grid_n(int cu) {
+  // with the tile prefetch: one resident round of workgroups, each walking
+  // its tiles; without it, two rounds
+  constexpr int per_cu = 163840 / ColLds<N>::BYTES;
+  return ColLds<N>::PF ? cu * (per_cu > 0 ? per_cu : 1) : 512;
+}
+
+int col_default_grid(int N, int cu) {
+  switch (N) {
+    case 16: return col_default_grid_n<16>(cu);
+    case 32: return col_default_grid_n<32>(cu);
+    case 64: return col_default_grid_n<64>(cu);
+    case 128: return col_default_grid_n<128>(cu);
+    case 256: return col_default_grid_n<256>(cu);
+    case 512: return col_default_grid_n<512>(cu);
+    case 1024: return col_default_grid_n<1024>(cu);
+    default: return col_default_grid_n<2048>(cu);
+  }
 }
 
 template <int N>
