@@ -351,6 +351,29 @@ def test_depth_first_large_frames(gpu_lib, T, N):
     assert err <= FP32_BAR
 
 
+# Eq. 6 phase and aberration on large frames in both evaluation orders: the
+# row passes keep the Eq. 6 factor in LDS up to N = 1024 and read it from
+# memory at N = 2048; the column passes hold their twiddles in LDS and
+# prefetch the next tile up to N = 1024, and keep both in registers at 2048.
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("N", [512, 1024, 2048])
+def test_options_on_large_frames(gpu_lib, N, order):
+    from paper_2003_08960_amd.api import Plan
+    T = 16
+    frames, lam = random_case(T, N, seed=7 * N + order)
+    zern = np.random.default_rng(N).normal(0, 0.4, 15)
+    print(f"\n[gpu] Eq. 6 phase + aberration T={T} N={N} order={order}", flush=True)
+    plan = Plan(T, N, precision="fp32_fft", eq6_phase=True)
+    plan.set_tuning(plan.get_tuning()[:3] + [order])
+    V = plan.render(torch.from_numpy(frames).cuda(), lam, 12e-6, 0.3, None, zern)
+    pix = [(0, 0), (N // 2, N // 2), (N - 1, 3), (17, N - 5), (N // 3, 2 * N // 3)]
+    ref = O.render_columns(frames, lam, 12e-6, 0.3, pix, zernike_coeffs=zern, eq6_phase=True)
+    got = np.stack([V[:, u, v].cpu().numpy() for u, v in pix], axis=1)
+    err = rel_l2(got, ref)
+    print(f"N={N} order={order} sampled rel-L2 {err:.3e}")
+    assert err <= FP32_BAR
+
+
 # ---------------------------------------------------------------- factored (16 x T/16) MFMA depth transform
 
 FOURSTEP = [("fp32_4step", FP32_BAR), ("fp16_split_4step", SPLIT_BAR), ("bf16_split_4step", SPLIT_BAR),
