@@ -380,14 +380,29 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_fwd(const uint16_
   const int f = blockIdx.y;
   const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
   const uint16_t* I = frames + (size_t)(t0 + f) * N * N;
+  // As in k_row_pass: the next row loads while the current one is
+  // transformed, the twiddles stay in registers, and nothing is outstanding
+  // when the loop starts, so the loop waits for its prefetched row only
+  // (loaded before the previous row's stores, which stay in flight).
+  // held as 32-bit values: packing two samples per register would wait for
+  // the loads (and with them the previous row's stores) right after issue
+  uint32_t nx[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) nx[k] = I[(size_t)m0 * N + j + k * G];
+  const TwRegs<N> twr = load_tw_regs<N>(tw, j);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
 #pragma unroll 1
   for (int i = 0; i < R::RPG; ++i) {
     const int m = m0 + i;
     float2 v[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = make_float2((float)I[(size_t)m * N + j + k * G], 0.f);
+    for (int k = 0; k < 16; ++k) v[k] = make_float2((float)nx[k], 0.f);
+    if (i + 1 < R::RPG) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) nx[k] = I[(size_t)(m + 1) * N + j + k * G];
+    }
     exchange_sync<R::WAVE>();
-    fft_group<N, -1, 1, R::WAVE>(v, j, xbuf[g], tw);
+    fft_group_tw<N, -1, 1, R::WAVE>(v, j, xbuf[g], twr);
     float2* dst = inter + ((size_t)f * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) dst[j + out_offset<N>(e)] = v[e];
@@ -469,15 +484,28 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2*
   const int g = threadIdx.x / G, j = threadIdx.x % G;
   const int f = blockIdx.y;
   const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
+  // next row prefetched, twiddles in registers, empty entry state (k_as_row_fwd)
+  float2 nx[16];
+  {
+    const float2* src = inter + ((size_t)f * N + m0) * N;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) nx[k] = src[j + k * G];
+  }
+  const TwRegs<N> twr = load_tw_regs<N>(tw, j);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
 #pragma unroll 1
   for (int i = 0; i < R::RPG; ++i) {
     const int m = m0 + i;
-    const float2* src = inter + ((size_t)f * N + m) * N;
     float2 v[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = src[j + k * G];
+    for (int k = 0; k < 16; ++k) v[k] = nx[k];
+    if (i + 1 < R::RPG) {
+      const float2* src = inter + ((size_t)f * N + m + 1) * N;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) nx[k] = src[j + k * G];
+    }
     exchange_sync<R::WAVE>();
-    fft_group<N, +1, 1, R::WAVE>(v, j, xbuf[g], tw);
+    fft_group_tw<N, +1, 1, R::WAVE>(v, j, xbuf[g], twr);
     const long long base = ((long long)(t0 + f) * N + m) * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) store_h<FMT>(H, base + j + out_offset<N>(e), v[e], scale);
