@@ -179,9 +179,11 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
 /* ---------------------------------------------------------------- tuning
  * Launch-shape parameters of a plan, int tuning[4]: tuning[0] frames per
  * chunk of the Fresnel stage (1 .. the chunk the workspace was sized for),
- * tuning[1] persistent column-pass workgroups (0 = default: for N <= 1024,
- * where the column pass prefetches its next tile, as many as are resident at
- * once on the device; 512 for N = 2048), tuning[2]
+ * tuning[1] persistent column-pass workgroups (0 = default: as many as are
+ * resident at once on the device wherever the column pass prefetches its
+ * next tile, which is the angular-spectrum column pass at every N and the
+ * Fresnel column pass up to N = 1024; 512 for the Fresnel column pass at
+ * N = 2048), tuning[2]
  * persistent workgroups of the dense depth transform (0 = default; the
  * SSOCT_DEPTH_FFT and SSOCT_DEPTH_4STEP forms launch one workgroup per pixel
  * tile and ignore it), tuning[3] evaluation

@@ -306,7 +306,8 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
   const int fmt = h_format(depth_prec(p->flags));
   if (p->flags & SSOCT_ANGULAR_SPECTRUM) {
     SSOCT_HIP(launch_as_stage(N, Fc, t0, frames, p->tw, p->as_params, 1.0 / ((double)N * p->as_pitch), p->as_z,
-                              reinterpret_cast<float2*>(ws + L.inter), ws + L.H, fmt, p->sigma, p->col_grid, s));
+                              reinterpret_cast<float2*>(ws + L.inter), ws + L.H, fmt, p->sigma,
+                              p->col_grid > 0 ? p->col_grid : p->as_col_grid0, s));
     return SSOCT_OK;
   }
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
@@ -498,6 +499,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   zernike_monomials(p->zmat);
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e == hipSuccess && (flags & SSOCT_ANGULAR_SPECTRUM)) p->as_col_grid0 = as_col_default_grid(N, p->cu);
   const size_t axis = (size_t)T * N * sizeof(AxisTab);
   const size_t nparams = ParamLayout::count(T) + T + 15 * N_MONO;
   const size_t na32 = (size_t)p->dl.nrb * (p->dl.T_pad / 2) * 64;

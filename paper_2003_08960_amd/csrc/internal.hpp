@@ -100,6 +100,9 @@ hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const floa
 // Default persistent grid of the column passes (forward, adjoint, volume
 // output) on a device with `cu` compute units
 int col_default_grid(int N, int cu);
+// Default persistent grid of the angular-spectrum column pass (a host query
+// of the kernel's residency: call it outside stream capture)
+int as_col_default_grid(int N, int cu);
 
 // Angular-spectrum propagation of frames [t0, t0 + F) into H (format fmt):
 // row DFT^-, column DFT^- x transfer function x DFT^+, row DFT^+ (uncentred,

@@ -37,6 +37,7 @@ struct ssoct_plan {
   // launch shapes (ssoct_plan_tune / ssoct_plan_set_tuning)
   int F_run = 0;               // frames per chunk in use (1 .. F)
   int col_grid = 0;            // persistent column workgroups (0 = default)
+  int as_col_grid0 = 0;        // default of the angular-spectrum column pass (set at creation)
   int depth_grid = 0;          // persistent depth workgroups (0 = default)
   // device tables
   ssoct::AxisTab* rows = nullptr;

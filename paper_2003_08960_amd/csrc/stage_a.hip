@@ -428,16 +428,43 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
   constexpr int G = S::G;
   constexpr int C = AsColCfg<N>::C;
   constexpr int NCB = N / C;
+  // As in k_col_pass: where the twiddle table fits in LDS beside the
+  // exchange buffer, it goes there and the freed registers hold the next
+  // tile, loaded while the current one is transformed.  Tiles are disjoint
+  // and each belongs to one workgroup, so the prefetch never reads a column
+  // that is being written in place.
+  constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
+  constexpr bool TWL = SSOCT_COL_TWL && (S::LDS * C + TWN) * 8 <= 163840;
   __shared__ float2 xbuf[S::LDS * C];
+  __shared__ float2 twl[TWL ? TWN : 1];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
+  float2 pf[16];
+  auto issue = [&](int tl) {
+    const float2* cs = buf + (size_t)(tl / NCB) * N * N + (tl % NCB) * C + c;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pf[k] = cs[(size_t)(j + k * G) * N];
+  };
+  if constexpr (TWL) {
+    if ((int)blockIdx.x < ntiles) issue(blockIdx.x);
+    for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += AsColCfg<N>::THREADS) twl[i] = tw[i];
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop is entered with no load outstanding
+    __syncthreads();  // twiddles visible
+  }
+  const TwMem<N> twm{TWL ? static_cast<const float2*>(twl) : tw, j};
 #pragma unroll 1
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int f = tile / NCB, kx = (tile % NCB) * C + c;
     float2* col = buf + (size_t)f * N * N + kx;
     float2 v[16];
+    if constexpr (TWL) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = col[(size_t)(j + k * G) * N];
-    fft_group<N, -1, C>(v, j, xbuf + c, tw);
+      for (int k = 0; k < 16; ++k) v[k] = pf[k];
+      if (tile + (int)gridDim.x < ntiles) issue(tile + gridDim.x);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = col[(size_t)(j + k * G) * N];
+    }
+    fft_group_tw<N, -1, C, false>(v, j, xbuf + c, twm);
     const double* pf = asp + 3 * (size_t)(t0 + f);
     const double inv_l2 = pf[0], cyc0 = pf[1], amp = pf[2];
     const double fx = (double)(kx < N / 2 ? kx : kx - N) * inv_nd;
@@ -466,7 +493,7 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
 #pragma unroll
     for (int k = 0; k < 16; ++k) v[k] = xbuf[(size_t)lds_slot(j + k * G) * C + c];
     __syncthreads();
-    fft_group<N, +1, C>(v, j, xbuf + c, tw);
+    fft_group_tw<N, +1, C, false>(v, j, xbuf + c, twm);
 #pragma unroll
     for (int e = 0; e < 16; ++e) col[(size_t)(j + out_offset<N>(e)) * N] = v[e];
     __syncthreads();   // this tile's exchange reads are done before the next tile writes LDS
@@ -704,6 +731,31 @@ static int col_default_grid_n(int cu) {
   // its tiles; without it, two rounds
   constexpr int per_cu = 163840 / ColLds<N>::BYTES;
   return ColLds<N>::PF ? cu * (per_cu > 0 ? per_cu : 1) : 512;
+}
+
+// Default persistent grid of the transfer-function column pass: one resident
+// round of workgroups (its next tile is prefetched, so a second round only
+// adds a tail), with the per-CU residency of the compiled kernel
+template <int N>
+static int as_col_default_grid_n(int cu) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_as_col<N>),
+                                                   AsColCfg<N>::THREADS, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return cu * nb;
+}
+
+int as_col_default_grid(int N, int cu) {
+  switch (N) {
+    case 16: return as_col_default_grid_n<16>(cu);
+    case 32: return as_col_default_grid_n<32>(cu);
+    case 64: return as_col_default_grid_n<64>(cu);
+    case 128: return as_col_default_grid_n<128>(cu);
+    case 256: return as_col_default_grid_n<256>(cu);
+    case 512: return as_col_default_grid_n<512>(cu);
+    case 1024: return as_col_default_grid_n<1024>(cu);
+    default: return as_col_default_grid_n<2048>(cu);
+  }
 }
 
 int col_default_grid(int N, int cu) {
