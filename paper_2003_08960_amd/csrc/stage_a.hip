@@ -38,7 +38,8 @@ namespace ssoct {
                                  // where the twiddles are in LDS, see SSOCT_COL_TWL)
 #endif
 #ifndef SSOCT_COL_TWL
-#define SSOCT_COL_TWL 1          // column pass: twiddles in LDS where the exchange buffer leaves room
+#define SSOCT_COL_TWL 1          // column passes (Fresnel and angular-spectrum): twiddles in LDS where the
+                                 // exchange buffer leaves room, and the next tile prefetched into registers
 #endif
 #ifndef SSOCT_ROW_NT
 #define SSOCT_ROW_NT 0           // row pass: non-temporal stores of the intermediate
