@@ -56,10 +56,16 @@ Readings of points the paper leaves open:
     for a k-linear sweep).
   * Angular-spectrum propagation (the alternative the paper contrasts with
     the Fresnel transform; it keeps the sensor pitch for every wavelength, so
-    no rescale): h_t = F^-1{ F{I_t} exp(2 pi i z sqrt(lambda_t^-2 - fx^2 - fy^2)) }
+    no rescale): h_t = F^-1{ F{I_t} exp(-2 pi i z sqrt(lambda_t^-2 - fx^2 - fy^2)) }
     with F the unnormalised DFT (negative exponent), F^-1 its inverse (1/N^2),
     frequencies fx = k / (N d) for the DFT index k folded to [-N/2, N/2), and
-    the evanescent components (negative radicand) set to zero.
+    the evanescent components (negative radicand) set to zero.  The sign is
+    the paper's: its fields carry exp(+i omega t) (setup paragraph), so
+    propagation by +z carries exp(-i k z), as the prefactor of Eq. 6 does.
+    With this sign one z names the same plane for both propagators: at
+    z = z_b (where the Fresnel pixel of Eq. 4 equals the sensor pitch) Eq. 6
+    with its prefactor and output phase is the paraxial limit of this
+    transfer function on the same grid.
 """
 from __future__ import annotations
 
@@ -304,13 +310,15 @@ def depth_dft_adjoint(G: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def as_transfer(N: int, lam: float, pitch: float, z: float) -> np.ndarray:
-    """exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) on the DFT frequency grid, 0 where evanescent."""
+    """exp(-2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) on the DFT frequency grid, 0 where evanescent.
+
+    Propagation by +z under the exp(+i omega t) convention of the paper's fields."""
     f = np.fft.fftfreq(N, d=pitch)
     rad = 1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2
     H = np.zeros((N, N), dtype=np.complex128)
     ok = rad > 0
     cyc = z * np.sqrt(rad[ok])
-    H[ok] = np.exp(2j * np.pi * (cyc - np.floor(cyc)))
+    H[ok] = np.exp(-2j * np.pi * (cyc - np.floor(cyc)))
     return H
 
 

@@ -475,10 +475,11 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
       const double fy = (double)(ky < N / 2 ? ky : ky - N) * inv_nd;
       const double rad = inv_l2 - fx * fx - fy * fy;
       float2 h = make_float2(0.f, 0.f);
-      if (rad > 0.0) {   // propagating: exp(2 pi i (z sqrt(rad) + cyc0)) amp; evanescent: 0
-        // the phase (up to ~1e5 cycles) is reduced to a fraction in FP64; the hardware sine and
-        // cosine take the fraction in cycles (within 1.3e-7 of FP64 over one cycle on gfx950)
-        double cyc = z * sqrt(rad) + cyc0;
+      if (rad > 0.0) {   // propagating: exp(2 pi i (cyc0 - z sqrt(rad))) amp; evanescent: 0
+        // (exp(-i k z) for +z: the paper's fields carry exp(+i omega t), as the prefactor of Eq. 6
+        // does).  The phase (up to ~1e5 cycles) is reduced to a fraction in FP64; the hardware sine
+        // and cosine take the fraction in cycles (within 1.3e-7 of FP64 over one cycle on gfx950)
+        double cyc = cyc0 - z * sqrt(rad);
         cyc -= rint(cyc);
         const float fr = (float)cyc;
         h = make_float2(__builtin_amdgcn_cosf(fr) * (float)amp, __builtin_amdgcn_sinf(fr) * (float)amp);

@@ -286,6 +286,64 @@ def test_eq6_phase_only_scales_magnitude():
     assert np.allclose(np.abs(V1), np.abs(V0) * d * d / (lam1 * z), rtol=1e-10, atol=0)
 
 
+def check_eq6_as_printed():
+    """Eq. 6 exactly as printed, evaluated term by term at the output pixels x = c_u d' (Eq. 4):
+    H(x, y) = (i / (lambda_1 z)) exp(-i k_1 z) d^2 sum_{x', y'} I'(x', y')
+              exp[-i pi ((x - x')^2 + (y - y')^2) / (lambda_1 z)]
+    on the rescaled frames I' (Eq. 5), then the depth sum of Eq. 7; against render(eq6_phase=True).
+    The quadratic is not expanded here, so the DFT sign, the centring, the input chirp, the prefactor
+    i exp(-i k_1 z) d^2 / (lambda_1 z) and the output phase are all checked in their complex values."""
+    frames, lam, d, z, _, _ = _small_case(T=4, N=16, seed=21)
+    T, N, _ = frames.shape
+    lam1 = float(np.max(lam))
+    s = lam / lam1
+    dprime = lam1 * z / (N * d)                        # Eq. 4
+    c = np.arange(N) - N // 2
+    xs = c * d                                         # sensor (calculation-grid) coordinates
+    xo = c * dprime                                    # output coordinates
+    E = np.exp(-1j * np.pi * (xo[:, None] - xs[None, :]) ** 2 / (lam1 * z))   # [output, sensor]
+    pref = 1j / (lam1 * z) * np.exp(-1j * 2 * np.pi * z / lam1) * d * d
+    H = np.empty((T, N, N), dtype=np.complex128)
+    for t in range(T):
+        Ip = O.rescale(frames[t], s[t])                # I'(x', y') at x' = c d
+        H[t] = pref * (E @ Ip @ E.T)                   # rows y, columns x
+    tt = np.arange(T)
+    W = np.exp(-2j * np.pi * np.outer(tt, tt) / T)     # Eq. 7, rectangular gate of the T frames
+    V_printed = np.tensordot(W, H, axes=(1, 0))
+    V = O.render(frames, lam, d, z, eq6_phase=True)
+    assert np.linalg.norm(V - V_printed) <= 1e-10 * np.linalg.norm(V_printed)
+
+
+def test_eq6_as_printed():
+    check_eq6_as_printed()
+
+
+def check_as_matches_eq6_at_zb():
+    """At z = z_b = N d^2 / lambda_1 the Fresnel pixel of Eq. 4 equals the sensor pitch, and the
+    sampled Eq. 6 (prefactor and output phase included) is a circular convolution whose transfer
+    function is exactly exp(-i k z) exp(i pi lambda z f^2) (a Gauss sum): the paraxial limit of the
+    angular-spectrum transfer function.  So, for one wavelength, render(eq6_phase=True) and
+    render_as agree pixel by pixel in complex value, up to the non-paraxial phase
+    2 pi z lambda^3 f^4 / 8 at most (f^2 <= 1 / (2 d^2)).  This pins the sign of the angular
+    spectrum's z to the one of Eq. 6."""
+    rng = np.random.default_rng(31)
+    T, N, d, lam0 = 3, 16, 1e-3, 870e-9
+    frames = rng.integers(0, 65536, size=(T, N, N)).astype(np.uint16)
+    lam = np.full(T, lam0)
+    zb = O.boundary_distance(N, d, lam0)
+    bound = 2 * np.pi * zb * lam0 ** 3 * (1.0 / (2 * d * d)) ** 2 / 8
+    assert bound < 1e-5
+    Vf = O.render(frames, lam, d, zb, eq6_phase=True)
+    Va = O.render_as(frames, lam, d, zb)
+    assert np.linalg.norm(Vf - Va) <= 2 * bound * np.linalg.norm(Va)
+    # the opposite z is a different plane: the agreement is not an accident of the input
+    assert np.linalg.norm(Vf - O.render_as(frames, lam, d, -zb)) > 0.5 * np.linalg.norm(Va)
+
+
+def test_as_matches_eq6_at_zb():
+    check_as_matches_eq6_at_zb()
+
+
 def test_generator_scatterers_focus():
     """Synthetic ground truth: every scatterer of the tiny workload peaks at its pixel and bin."""
     sw = synth.make_config("tiny")
@@ -333,6 +391,33 @@ def test_zernike_closed_forms_and_orthonormality():
     Z = np.stack([O.zernike(j, R, A) for j in range(15)])
     G = np.einsum("jab,kab,ab->jk", Z, Z, W)
     assert np.allclose(G, np.eye(15), atol=1e-10)
+
+
+def check_pupil_grid():
+    """rho = r / (N d / sqrt 2): exactly 1 at the corner pixel (the circumscribed circle) and 0 at the
+    centre; theta = atan2(y, x) with x along columns and y along rows."""
+    N = 16
+    rho, th = O.pupil_grid(N)
+    assert rho[0, 0] == pytest.approx(1.0, abs=1e-15)
+    assert rho[N // 2, N // 2] == 0.0
+    assert rho[N // 2, N - 1] == pytest.approx((N // 2 - 1) * math.sqrt(2) / N, abs=1e-15)
+    assert th[N // 2, N // 2 + 3] == pytest.approx(0.0, abs=1e-15)        # +x: along the row
+    assert th[N // 2 + 3, N // 2] == pytest.approx(np.pi / 2, abs=1e-15)  # +y: down the column
+    # a tilt Z_2 = 2 rho cos(theta) = 2 sqrt(2) c_n / N (Z_1: c_m) of coefficient k pi / sqrt 2 is the
+    # linear phase 2 pi k c / N, which moves the Fresnel DFT (Eq. 6) by exactly -k pixels along v
+    # (u for Z_1): the whole volume is circularly shifted, whatever the other coefficients
+    frames, lam, d, z, phi, zc = _small_case(T=3, N=16, seed=41)
+    V0 = O.render(frames, lam, d, z, phi, zc)
+    for j, axis in ((2, 2), (1, 1)):
+        for k in (1, 3):
+            c = zc.copy()
+            c[j] += k * np.pi / math.sqrt(2)
+            V = O.render(frames, lam, d, z, phi, c)
+            assert np.allclose(V, np.roll(V0, -k, axis=axis), rtol=0, atol=1e-9 * np.abs(V0).max())
+
+
+def test_pupil_grid():
+    check_pupil_grid()
 
 
 # --------------------------------------------------------------------------
@@ -497,14 +582,15 @@ def test_render_extensions_reduce_to_the_paper_form():
 # --------------------------------------------------------------------------
 
 def check_as_plane_wave():
-    """An on-grid plane wave exp(2 pi i (a m + b n) / N) is an eigenfunction: it gains exactly
-    exp(2 pi i z sqrt(1/lambda^2 - (a/(N d))^2 - (b/(N d))^2)), or vanishes if evanescent."""
+    """An on-grid plane wave exp(2 pi i (a m + b n) / N) is an eigenfunction: propagated by +z it
+    gains exactly exp(-2 pi i z sqrt(1/lambda^2 - (a/(N d))^2 - (b/(N d))^2)) (the exp(-i k z) of a wave
+    travelling +z when fields carry exp(+i omega t), as in the paper), or vanishes if evanescent."""
     N, d, lam, z = 32, 10e-6, 850e-9, 0.01
     m = np.arange(N)
     for a, b in ((0, 0), (3, -5), (-16, 7), (11, 11)):
         x = np.exp(2j * np.pi * (a * m[:, None] + b * m[None, :]) / N)
         fx, fy = a / (N * d), b / (N * d)
-        want = np.exp(2j * np.pi * z * np.sqrt(1 / lam ** 2 - fx ** 2 - fy ** 2))
+        want = np.exp(-2j * np.pi * z * np.sqrt(1 / lam ** 2 - fx ** 2 - fy ** 2))
         assert np.allclose(O.as_propagate(x, lam, d, z), want * x, atol=1e-9)
     dd = 0.3e-6                                           # pitch below lambda / 2: the highest frequencies are evanescent
     x = np.exp(2j * np.pi * (16 * m[:, None]) / N) * np.ones((1, N))   # f = 1/(2 dd) > 1/lambda
@@ -526,12 +612,13 @@ def check_as_composition():
 
 
 def check_as_point_focus():
-    """The field of a point source at distance z, sampled on the sensor and band-limited to the
-    grid, propagates back (by -z) to a peak at the source pixel."""
+    """The diverging field exp(-i k r) / r of a point source at distance z (exp(+i omega t)
+    convention), sampled on the sensor and band-limited to the grid, propagates back (by -z) to a
+    peak at the source pixel."""
     N, d, lam, z = 64, 8e-6, 850e-9, 0.004
     c = (np.arange(N) - N // 2) * d
     r = np.sqrt(c[:, None] ** 2 + (c[None, :] - 5 * d) ** 2 + z ** 2)
-    x = np.exp(2j * np.pi * (r / lam)) / r
+    x = np.exp(-2j * np.pi * (r / lam)) / r
     back = np.abs(O.as_propagate(x, lam, d, -z))
     i, j = np.unravel_index(np.argmax(back), back.shape)
     assert (i, j) == (N // 2, N // 2 + 5)
@@ -591,27 +678,47 @@ def _plants():
     yield "AS keeps evanescent", "as_transfer", lambda orig: (lambda N, lam, d, z: _no_cutoff_transfer(N, lam, d, z)), \
         check_as_plane_wave
     yield "AS frequencies unfolded", "as_transfer", lambda orig: (lambda N, lam, d, z: _unfolded_transfer(N, lam, d, z)), \
-        check_as_point_focus
+        check_as_plane_wave
+    yield "eq6 prefactor without i", "eq6_output_factor", lambda orig: (lambda *a: -1j * orig(*a)), \
+        check_eq6_as_printed
+    yield "eq6 output phase conjugated", "eq6_output_factor", lambda orig: (
+        lambda N, lam1, d, z: orig(N, lam1, d, z) * _quad_phase(N, lam1, d, z) ** 2), check_eq6_as_printed
+    yield "eq6 k1 z sign", "eq6_output_factor", lambda orig: (
+        lambda N, lam1, d, z: orig(N, lam1, d, z) * np.exp(4j * np.pi * (z / lam1 % 1.0))), check_eq6_as_printed
+    yield "eq6 output phase conjugated (AS)", "eq6_output_factor", lambda orig: (
+        lambda N, lam1, d, z: orig(N, lam1, d, z) * _quad_phase(N, lam1, d, z) ** 2), check_as_matches_eq6_at_zb
+    yield "AS conjugate kernel (Eq. 6)", "as_transfer", lambda orig: (lambda *a: np.conj(orig(*a))), \
+        check_as_matches_eq6_at_zb
+    yield "pupil radius N/2", "pupil_grid", lambda orig: (lambda N: (lambda r, t: (r * math.sqrt(2), t))(*orig(N))), \
+        check_pupil_grid
+    yield "pupil axes swapped", "pupil_grid", lambda orig: (lambda N: (lambda r, t: (r, np.pi / 2 - t))(*orig(N))), \
+        check_pupil_grid
     yield "gate squared", "render", lambda orig: (
         lambda *a, gate=None, **k: orig(*a, gate=None if gate is None else np.asarray(gate) ** 2, **k)), \
         check_hann_gate
 
 
+def _quad_phase(N, lam1, d, z):
+    """exp(+i pi lambda_1 z (c_u^2 + c_v^2) / (N d)^2): the conjugate of the Eq. 6 output phase."""
+    c = np.arange(N) - N // 2
+    return np.exp(1j * np.pi * lam1 * z * (c[:, None] ** 2 + c[None, :] ** 2) / (N * d) ** 2)
+
+
 def _fresnel_transfer(N, lam, d, z):
     f = np.fft.fftfreq(N, d=d)
-    return np.exp(2j * np.pi * z / lam) * np.exp(-1j * np.pi * lam * z * (f[:, None] ** 2 + f[None, :] ** 2))
+    return np.exp(-2j * np.pi * z / lam) * np.exp(1j * np.pi * lam * z * (f[:, None] ** 2 + f[None, :] ** 2))
 
 
 def _no_cutoff_transfer(N, lam, d, z):
     f = np.fft.fftfreq(N, d=d)
     rad = (1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2).astype(np.complex128)
-    return np.exp(2j * np.pi * z * np.sqrt(rad))
+    return np.exp(-2j * np.pi * z * np.sqrt(rad))
 
 
 def _unfolded_transfer(N, lam, d, z):
     f = np.arange(N) / (N * d)
     rad = 1.0 / lam ** 2 - f[:, None] ** 2 - f[None, :] ** 2
-    return np.where(rad > 0, np.exp(2j * np.pi * z * np.sqrt(np.maximum(rad, 0))), 0)
+    return np.where(rad > 0, np.exp(-2j * np.pi * z * np.sqrt(np.maximum(rad, 0))), 0)
 
 
 def _shifted_positions(N, s):
