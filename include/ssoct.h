@@ -3,7 +3,7 @@
  * coherence tomography by off-axis Fresnel-transform digital holography
  * (Charpentier et al., arXiv 2003.08960).
  *
- * Pipeline of one call to ssoct_render (flowchart of Fig. 3):
+ * Pipeline of one render (ssoct_render, ssoct_plan_render; flowchart of Fig. 3):
  *   1. chromatic rescale of each 16-bit interferogram by linear interpolation,
  *      I'(x, y, t) = I(x lambda_t / lambda_1, y lambda_t / lambda_1, t)
  *      about the frame centre (Eq. 5; makes the Fresnel pixel of Eq. 4
@@ -69,15 +69,18 @@ extern "C" {
 #define SSOCT_SPLIT 4u            /* FP16/BF16 operands split hi + lo (3 products) */
 #define SSOCT_CHIRP_EXACT 8u      /* chirp rate pi d^2 (lambda_t/lambda_1) / (lambda_1 z) instead of lambda_1 only */
 #define SSOCT_EQ6_PHASE 16u       /* apply the Eq. 6 prefactor (i d^2/(lambda_1 z)) e^{-i k_1 z} and output phase */
-#define SSOCT_WRITE_ABS 32u       /* ssoct_render writes |V| (float) instead of V (complex64) */
+#define SSOCT_WRITE_ABS 32u       /* ssoct_plan_render writes |V| (float) instead of V (complex64) */
 #define SSOCT_CUT_POWER 64u       /* ssoct_cuts returns |V|^2 instead of |V| */
 #define SSOCT_BACKWARD 128u       /* workspace also sized for the gradient entry points */
 #define SSOCT_PROFILE 256u        /* record per-stage HIP events (ssoct_profile_read) */
 #define SSOCT_PROFILE_KERNELS 512u /* with SSOCT_PROFILE: an event after every Fresnel-stage launch too
                                       (each adds a few microseconds to the render) */
 #define SSOCT_ANGULAR_SPECTRUM 4096u /* propagate each frame by the angular spectrum at its own wavelength
-                                      (no rescale, sensor pitch, valid for any z) instead of Eq. 6;
-                                      not with SSOCT_CHIRP_EXACT, SSOCT_EQ6_PHASE, aberration or gradients */
+                                      (no rescale, sensor pitch, valid for any z) instead of Eq. 6:
+                                      F^-1{F{I_t} exp(-2 pi i z sqrt(lambda_t^-2 - f^2))}, the sign of
+                                      Eq. 6 (fields carry exp(+i omega t)), so one z names the same plane
+                                      for both propagators; not with SSOCT_CHIRP_EXACT, SSOCT_EQ6_PHASE,
+                                      aberration or gradients */
 #define SSOCT_NONUNIFORM_K 2048u  /* depth transform exp(-2 pi i q kappa_t / T), kappa_t = (k_t - k_0)/dk from lambda:
                                       the uniform depth grid of a sweep not linear in k (dense forms only) */
 #define SSOCT_DEPTH_FFT 1024u     /* FP32 depth transform as a radix FFT along the sweep (T in {16..256},
@@ -95,7 +98,7 @@ int ssoct_version(void);
 /* Text of the last error returned to the calling thread ("" if none). */
 const char* ssoct_last_error(void);
 
-/* Bytes of device workspace ssoct_render (and, with SSOCT_BACKWARD, the
+/* Bytes of device workspace ssoct_plan_render (and, with SSOCT_BACKWARD, the
  * gradient entry points) need for T frames of N x N; 0 for unsupported
  * sizes.  The workspace holds the hologram stack H (T N^2 x 8 bytes), one
  * chunk of row-transformed frames, and with SSOCT_BACKWARD a second stack and
@@ -116,7 +119,35 @@ int ssoct_plan_set_stream(ssoct_plan* plan, hipStream_t stream);
  * destroy those first. */
 int ssoct_plan_destroy(ssoct_plan* plan);
 
-/* Render one sweep: frames [T][N][N] uint16 -> vol [T][N][N] (steps 1-3).
+/* The paper's problem statement as one call (Eq. 5-7): the interferograms of
+ * one sweep, their wavelengths, the pixel pitch and the reconstruction
+ * distance in; the complex volume out (steps 1-3).
+ *   frames  device uint16 [T][N][N]
+ *   T, N    frames per sweep (1 .. 1024) and frame size (power of two, 16 .. 2048)
+ *   lambda  host double [T], metres, > 0 (any order; lambda_1 = max)
+ *   pitch   sensor pixel pitch d, metres, > 0
+ *   z       reconstruction distance, metres, != 0
+ *   vol     device complex64 [T][N][N] (q, u, v), must not overlap frames
+ *   stream  HIP stream the work is enqueued on (0 = null stream)
+ * FP32 throughout (the depth transform as a radix FFT for T in {16, 32, 64,
+ * 128, 256}, else the dense DFT-matrix product on FP32 MFMA), no dispersion
+ * or aberration, rectangular gate.  The plan and its workspace (about
+ * T N^2 8 bytes plus one chunk of at most 128 MiB) are created on the first
+ * call for a (device, stream, T, N) and reused by later calls with the same
+ * four; they are released by ssoct_render_release.  Returns as
+ * ssoct_plan_render (SSOCT_WARN_UNDERSAMPLED when |z| < N d^2 / lambda_1).
+ * Safe to call from several threads (the cache is locked); calls on one stream
+ * share a workspace and run in stream order. */
+int ssoct_render(const uint16_t* frames, int T, int N, const double* lambda, double pitch, double z, void* vol,
+                 hipStream_t stream);
+
+/* Release every plan and workspace ssoct_render has cached (waits for each
+ * device they were made on).  No ssoct_render call may be in flight on
+ * another thread. */
+int ssoct_render_release(void);
+
+/* Render one sweep with an explicit plan: frames [T][N][N] uint16 -> vol
+ * [T][N][N] (steps 1-3), in the plan's precision and depth form.
  *   lambda     host double [T], metres, > 0 (any order; lambda_1 = max)
  *   pitch      sensor pixel pitch d, metres, > 0
  *   z          reconstruction distance, metres, != 0
@@ -125,9 +156,9 @@ int ssoct_plan_destroy(ssoct_plan* plan);
  *   workspace  device, at least ssoct_workspace_size(T, N, flags) bytes
  * Rescale/chirp tables are rebuilt (FP64 on the GPU) only when lambda, pitch,
  * z, disp_phase or zernike change between calls. */
-int ssoct_render(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
-                 const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
-                 void* vol);
+int ssoct_plan_render(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
+                      const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                      void* vol);
 
 /* Three orthogonal cuts of the envelope (step 4) of a complex64 volume:
  *   cut_xy[u][v] = M[q0][u][v]   float [N][N]
@@ -137,7 +168,7 @@ int ssoct_render(ssoct_plan* plan, const uint16_t* frames, const double* lambda,
 int ssoct_cuts(ssoct_plan* plan, const void* vol, int x0, int y0, int q0, float* cut_xy, float* cut_xz,
                float* cut_yz);
 
-/* Vector-Jacobian product of ssoct_render for a real loss L with
+/* Vector-Jacobian product of ssoct_plan_render for a real loss L with
  * dL = Re sum conj(G) dV, G = grad_vol (complex64 [T][N][N], PyTorch's
  * convention G = 2 dL/d conj(V)).  Writes device double grad_out[2 + 15 + T]:
  * [0] = 0, [1] = dL/dz, [2..16] = dL/dc_j, [17..17+T) = dL/dphi_t.
@@ -164,7 +195,7 @@ int ssoct_backward_sharpness(ssoct_plan* plan, const uint16_t* frames, const dou
  * plan.  Not available for the gradient entry points or sliding windows. */
 int ssoct_plan_set_gate(ssoct_plan* plan, const double* gate);
 
-/* With SSOCT_PROFILE every ssoct_render records HIP events on the plan's
+/* With SSOCT_PROFILE every ssoct_plan_render records HIP events on the plan's
  * stream around its stages (and, with SSOCT_PROFILE_KERNELS, after every
  * kernel launch of the Fresnel stage).  This call waits for the last recorded render and fills ms[6] with
  * the mean elapsed milliseconds per render over the renders recorded since
@@ -198,7 +229,7 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
 /* Time candidate launch shapes (and, where allowed, both evaluation orders)
  * on the given inputs (HIP events on the plan's stream; synchronises the
  * stream), keep the fastest in the plan and write it to tuning[4].
- * Arguments as for ssoct_render; vol is overwritten. */
+ * Arguments as for ssoct_plan_render; vol is overwritten. */
 int ssoct_plan_tune(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                     const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                     void* vol, int* tuning);

@@ -119,7 +119,7 @@ class Plan:
         ph_c = native.host_doubles(disp_phase, T)
         zc_c = native.host_doubles(zernike, 15)
         self._sync_stream()
-        self.last_status = native.check(self.lib.ssoct_render(
+        self.last_status = native.check(self.lib.ssoct_plan_render(
             self._h, ctypes.c_void_p(_ptr(frames)), lam_c, float(pitch), float(z), ph_c, zc_c,
             ctypes.c_void_p(_ptr(self.workspace)), self.workspace.numel(), ctypes.c_void_p(_ptr(out))))
         return out
@@ -219,6 +219,29 @@ class Plan:
             data[key] = choice
             _store_cache(cache_path, data)
         return choice
+
+
+def render(frames: torch.Tensor, lam, pitch: float, z: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """ssoct_render: the complex volume [T, N, N] (complex64) of one sweep of uint16 frames [T, N, N]
+    on their device, with the library's cached FP32 default plan, on torch's current stream."""
+    lib = native.load()
+    if frames.dtype != torch.uint16 or frames.dim() != 3 or frames.shape[1] != frames.shape[2] \
+            or not frames.is_contiguous() or not frames.is_cuda:
+        raise ValueError("frames must be a contiguous CUDA uint16 tensor [T, N, N]")
+    T, N = int(frames.shape[0]), int(frames.shape[1])
+    if out is None:
+        out = torch.empty((T, N, N), dtype=torch.complex64, device=frames.device)
+    _check_tensor(out, "out", torch.complex64, (T, N, N), frames.device)
+    with torch.cuda.device(frames.device):
+        stream = torch.cuda.current_stream(frames.device).cuda_stream
+        native.check(lib.ssoct_render(ctypes.c_void_p(_ptr(frames)), T, N, native.host_doubles(lam, T), float(pitch),
+                                      float(z), ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(stream)))
+    return out
+
+
+def render_release():
+    """ssoct_render_release: free the plans and workspaces cached by render()."""
+    native.check(native.load().ssoct_render_release())
 
 
 def _load_cache(path):

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -245,7 +246,6 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
     g[ParamLayout::G_HAS_ABERR] = 1.0;
   }
   std::memcpy(&h[ParamLayout::count(T) + T], &p->zmat[0][0], sizeof(double) * 15 * N_MONO);
-  if (zern_on && !p->apoly) SSOCT_HIP(hipMalloc(&p->apoly, (size_t)N * APOLY_STRIDE * sizeof(float)));
   SSOCT_HIP(hipMemcpyAsync(p->params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p->stream));
   SSOCT_HIP(launch_axis_tables(p->params, T, N, p->rows, p->cols, p->stream));
   if (as) {
@@ -509,6 +509,8 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess) e = hipMalloc(&p->cols, axis);
   if (e == hipSuccess) e = hipMalloc(&p->tw, (ntw > 0 ? ntw : 1) * sizeof(float2));
   if (e == hipSuccess && (flags & SSOCT_EQ6_PHASE)) e = hipMalloc(&p->outfac, (size_t)N * sizeof(float2));
+  // the aberration screen's row polynomials (N x 8 floats): allocated here, so that a render never allocates
+  if (e == hipSuccess) e = hipMalloc(&p->apoly, (size_t)N * APOLY_STRIDE * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&p->params, nparams * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->a_f32, na32 * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&p->a_f16, na16 * sizeof(uint4));
@@ -553,9 +555,9 @@ int ssoct_plan_destroy(ssoct_plan* plan) {
   return SSOCT_OK;
 }
 
-int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
-                 const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
-                 void* vol) {
+int ssoct_plan_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, double pitch, double z,
+                      const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
+                      void* vol) {
   WsLayout L;
   if (int rc = check_render_args(p, frames, workspace, workspace_bytes, vol, &L)) return rc;
   SSOCT_HIP(hipSetDevice(p->device));
@@ -581,6 +583,67 @@ int ssoct_render(ssoct_plan* p, const uint16_t* frames, const double* lambda, do
   if (int rc = render_core(p, p->stream, frames, static_cast<char*>(workspace), L, vol, ev, kev)) return rc;
   if (prof) ++p->rec;
   return status;
+}
+
+// Default plans of the five-argument render: one plan and workspace per
+// (device, stream, T, N), created on first use and kept until
+// ssoct_render_release.  Calls on one stream are ordered on the GPU, so they
+// can share a workspace; the lock orders the table updates of concurrent
+// host threads.
+namespace {
+struct DefaultPlan {
+  int device;
+  hipStream_t stream;
+  int T, N;
+  ssoct_plan* plan;
+  void* ws;
+  size_t bytes;
+};
+std::mutex g_default_mu;
+std::vector<DefaultPlan> g_default;
+}  // namespace
+
+int ssoct_render(const uint16_t* frames, int T, int N, const double* lambda, double pitch, double z, void* vol,
+                 hipStream_t stream) {
+  if (!frames || !lambda || !vol) return fail(SSOCT_EINVAL, "frames, lambda and vol must be non-NULL");
+  if (T < 1 || T > 1024) return fail(SSOCT_EUNSUPPORTED, "T must be in [1, 1024]");
+  if (!pow2_in_range(N)) return fail(SSOCT_EUNSUPPORTED, "N must be a power of two in [16, 2048]");
+  int dev = 0;
+  SSOCT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_default_mu);
+  DefaultPlan* d = nullptr;
+  for (auto& e : g_default)
+    if (e.device == dev && e.stream == stream && e.T == T && e.N == N) d = &e;
+  if (!d) {
+    // FP32 throughout: the depth transform as a radix FFT where T allows it, else the dense product
+    const uint32_t flags = depth_fft_supported(T) ? SSOCT_DEPTH_FFT : SSOCT_PREC_FP32;
+    DefaultPlan e{dev, stream, T, N, nullptr, nullptr, ssoct_workspace_size(T, N, flags)};
+    if (int rc = ssoct_plan_create(&e.plan, T, N, flags, stream)) return rc;
+    const hipError_t he = hipMalloc(&e.ws, e.bytes);
+    if (he != hipSuccess) {
+      plan_free(e.plan);
+      return he == hipErrorOutOfMemory ? fail(SSOCT_ENOMEM, "workspace allocation failed")
+                                       : hip_fail(he, "ssoct_render workspace");
+    }
+    g_default.push_back(e);
+    d = &g_default.back();
+  }
+  return ssoct_plan_render(d->plan, frames, lambda, pitch, z, nullptr, nullptr, d->ws, d->bytes, vol);
+}
+
+int ssoct_render_release(void) {
+  std::lock_guard<std::mutex> lock(g_default_mu);
+  int rc = SSOCT_OK;
+  for (auto& e : g_default) {
+    // the streams the renders ran on may be gone: wait for the whole device
+    hipError_t he = hipSetDevice(e.device);
+    if (he == hipSuccess) he = hipDeviceSynchronize();
+    if (he != hipSuccess && rc == SSOCT_OK) rc = hip_fail(he, "ssoct_render_release");
+    plan_free(e.plan);
+    (void)hipFree(e.ws);
+  }
+  g_default.clear();
+  return rc;
 }
 
 int ssoct_cuts(ssoct_plan* p, const void* vol, int x0, int y0, int q0, float* cut_xy, float* cut_xz, float* cut_yz) {

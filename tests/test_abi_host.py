@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("ssoct_plan_create", "ssoct_render", "ssoct_cuts", "ssoct_backward",
+    for required in ("ssoct_plan_create", "ssoct_render", "ssoct_plan_render", "ssoct_cuts", "ssoct_backward",
                      "ssoct_backward_sharpness", "ssoct_workspace_size"):
         assert required in names
 
@@ -90,7 +90,14 @@ def test_plan_create_rejects_bad_sizes(lib):
 def test_null_plan_is_rejected(lib):
     from paper_2003_08960_amd import native
     lam = (ctypes.c_double * 4)(1e-6, 1e-6, 1e-6, 1e-6)
-    assert lib.ssoct_render(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL
+    assert lib.ssoct_plan_render(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL
+    # the five-argument form checks its pointers and sizes before any HIP call
+    assert lib.ssoct_render(None, 8, 64, lam, 1e-5, 0.1, None, None) == native.EINVAL
+    assert lib.ssoct_render(ctypes.c_void_p(64), 8, 100, lam, 1e-5, 0.1, ctypes.c_void_p(64), None) == \
+        native.EUNSUPPORTED
+    assert lib.ssoct_render(ctypes.c_void_p(64), 0, 64, lam, 1e-5, 0.1, ctypes.c_void_p(64), None) == \
+        native.EUNSUPPORTED
+    assert lib.ssoct_render_release() == native.OK     # nothing cached: nothing to release
     assert lib.ssoct_cuts(None, None, 0, 0, 0, None, None, None) == native.EINVAL
     assert lib.ssoct_backward(None, None, lam, 1e-5, 0.1, None, None, None, None, 0, None) == native.EINVAL
     assert lib.ssoct_backward_sharpness(None, None, lam, 1e-5, 0.1, None, None, None, 0, None) == native.EINVAL

@@ -444,3 +444,37 @@ def test_4step_rejections(gpu_lib):
             Plan(T, 32, precision="fp32_4step")
     with pytest.raises(native.SsoctError):
         Plan(64, 32, precision="fp32_4step", nonuniform_k=True)
+
+
+# ---------------------------------------------------------------- the five-argument render (default plans)
+
+def test_five_argument_render(gpu_lib, tiny):
+    """ssoct_render(frames, T, N, lambda, pitch, z, vol, stream): the problem statement of Eq. 5-7 as
+    one call with a cached FP32 default plan (the FFT depth form where T allows, else the dense FP32
+    product).  Matches the oracle, equals the explicit-plan render of that form bit for bit, reuses
+    its plan across calls, and keeps separate plans per size."""
+    from paper_2003_08960_amd import api
+    from paper_2003_08960_amd.api import Plan
+    sw = tiny
+    T, N = sw.frames.shape[0], sw.frames.shape[1]
+    print(f"\n[gpu] five-argument render T={T} N={N}", flush=True)
+    fr = torch.from_numpy(sw.frames).cuda()
+    V = api.render(fr, sw.lam, sw.pitch, sw.z)
+    V2 = api.render(fr, sw.lam, sw.pitch, sw.z)          # cached plan, same tables
+    torch.cuda.synchronize()
+    ref = O.render(sw.frames, sw.lam, sw.pitch, sw.z)
+    assert rel_l2(V.cpu().numpy(), ref) <= FP32_BAR
+    assert torch.equal(V, V2)
+    assert torch.equal(V, Plan(T, N, precision="fp32_fft").render(fr, sw.lam, sw.pitch, sw.z))
+    # a T the FFT form does not take: the dense FP32 product
+    frames, lam = random_case(20, 64, seed=77)
+    f2 = torch.from_numpy(frames).cuda()
+    W = api.render(f2, lam, 20e-6, 0.05)
+    assert rel_l2(W.cpu().numpy(), O.render(frames, lam, 20e-6, 0.05)) <= FP32_BAR
+    assert torch.equal(W, Plan(20, 64, precision="fp32").render(f2, lam, 20e-6, 0.05))
+    # parameters change between calls: the cached plan rebuilds its tables
+    V3 = api.render(fr, sw.lam, sw.pitch, 0.25)
+    assert rel_l2(V3.cpu().numpy(), O.render(sw.frames, sw.lam, sw.pitch, 0.25)) <= FP32_BAR
+    api.render_release()
+    assert torch.equal(api.render(fr, sw.lam, sw.pitch, sw.z), V)   # a fresh default plan after the release
+    api.render_release()
