@@ -160,6 +160,23 @@ int ssoct_plan_render(ssoct_plan* plan, const uint16_t* frames, const double* la
                       const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                       void* vol);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * render as ssoct_plan_render, with the workspace taken from a device array
+ * of SSOCT_NOALLOC_SCRATCH_BYTES inside the library instead of an argument.
+ * It calls no allocating routine (the plan's tables exist since
+ * ssoct_plan_create).  The plan's frames per chunk are lowered as far as
+ * needed to fit the array (the result does not change); SSOCT_EUNSUPPORTED
+ * when even one frame per chunk does not fit (T N^2 8 bytes plus N^2 8 bytes
+ * beyond the array, e.g. T = 256, N = 1024).  Each GPU the call runs on holds
+ * the array until the process ends, and every call on that GPU shares it:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * on it; calls on one stream are ordered.  Nothing in it needs clearing (a
+ * render writes every workspace byte it reads).  No profiling events. */
+#define SSOCT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int ssoct_plan_render_noalloc(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
+                              const double* disp_phase, const double* zernike, void* vol);
+
 /* Three orthogonal cuts of the envelope (step 4) of a complex64 volume:
  *   cut_xy[u][v] = M[q0][u][v]   float [N][N]
  *   cut_xz[q][v] = M[q][y0][v]   float [T][N]

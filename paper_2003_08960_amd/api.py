@@ -124,6 +124,23 @@ class Plan:
             ctypes.c_void_p(_ptr(self.workspace)), self.workspace.numel(), ctypes.c_void_p(_ptr(out))))
         return out
 
+    def render_noalloc(self, frames: torch.Tensor, lam, pitch: float, z: float, disp_phase=None, zernike=None,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """ssoct_plan_render_noalloc: the same volume as render(), with the workspace in the library's
+        static device array (no allocation inside the call; `out` must be given for a call that may
+        not allocate either)."""
+        T, N = self.T, self.N
+        _check_frames(frames, T, N, self.device)
+        if out is None:
+            out = torch.empty((T, N, N), dtype=torch.float32 if self.write_abs else torch.complex64,
+                              device=self.device)
+        _check_tensor(out, "out", torch.float32 if self.write_abs else torch.complex64, (T, N, N), self.device)
+        self._sync_stream()
+        self.last_status = native.check(self.lib.ssoct_plan_render_noalloc(
+            self._h, ctypes.c_void_p(_ptr(frames)), native.host_doubles(lam, T), float(pitch), float(z),
+            native.host_doubles(disp_phase, T), native.host_doubles(zernike, 15), ctypes.c_void_p(_ptr(out))))
+        return out
+
     def cuts(self, vol: torch.Tensor, x0: int, y0: int, q0: int):
         """(cut_xy [N, N], cut_xz [T, N], cut_yz [T, N]) of the envelope."""
         T, N = self.T, self.N

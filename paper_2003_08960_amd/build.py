@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libssoct.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["tables.hip", "stage_a.hip", "depth.hip", "depth_fft.hip", "depth_4step.hip", "misc.hip"]
+HIP_SOURCES = ["tables.hip", "stage_a.hip", "depth.hip", "depth_fft.hip", "depth_4step.hip", "misc.hip", "noalloc.hip"]
 CPP_SOURCES = ["abi.cpp", "stream.cpp", "slide.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{os.path.join(ROOT, 'include')}"]

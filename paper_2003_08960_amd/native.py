@@ -42,7 +42,7 @@ DEPTH_4STEP = 8192
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",
     "ssoct_plan_set_stream", "ssoct_plan_destroy", "ssoct_render", "ssoct_render_release", "ssoct_plan_render",
-    "ssoct_cuts", "ssoct_backward",
+    "ssoct_plan_render_noalloc", "ssoct_cuts", "ssoct_backward",
     "ssoct_backward_sharpness", "ssoct_plan_set_gate", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
     "ssoct_plan_set_tuning", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
     "ssoct_stream_submit", "ssoct_stream_pop", "ssoct_stream_slot_volume", "ssoct_stream_stats",
@@ -88,6 +88,8 @@ def _declare(lib):
     lib.ssoct_plan_render.restype = c_int
     lib.ssoct_plan_render.argtypes = [c_void_p, c_void_p, _dptr, c_double, c_double, _dptr, _dptr, c_void_p,
                                       c_size_t, c_void_p]
+    lib.ssoct_plan_render_noalloc.restype = c_int
+    lib.ssoct_plan_render_noalloc.argtypes = [c_void_p, c_void_p, _dptr, c_double, c_double, _dptr, _dptr, c_void_p]
     lib.ssoct_cuts.restype = c_int
     lib.ssoct_cuts.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]
     lib.ssoct_backward.restype = c_int
