@@ -55,8 +55,10 @@ def depth_flops(T: int, N: int, form: str) -> float:
     if form.endswith("_4step"):
         # real-form products of the T/16-point and the 16-point DFT matrices, per product:
         # (2 T2) x T2 x 16 x 4 + 32 x 16 x T2 x 4 real flops per pixel, T2 = T/16
+        # (the FP32 form uses the paired real form, rows W_k and W_{n-k} from one row pair: half of it)
         T2 = T // 16
-        return (128.0 * T2 * T2 + 2048.0 * T2) * N * N * depth_products(form)
+        per = (128.0 * T2 * T2 + 2048.0 * T2) * N * N * depth_products(form)
+        return per / 2 if form.startswith("fp32") else per
     # real form of the complex DFT matrix: 4 T^2 real flops per pixel per product
     return 4.0 * T * T * N * N * depth_products(form)
 
@@ -110,24 +112,55 @@ def sampled_pixels(sw, n_random=6, seed=5):
     return pix
 
 
-def cpu_baseline(sw, n_frames=32, n_cols=65536):
-    """The FP64 oracle timed on a bounded sample of the same workload, scaled to one volume."""
+def _oracle_share(frames, lam, t_idx, pitch, z, n_cols, seed):
+    """One worker's share of the oracle on a volume: steps 1-2 (rescale, chirp, Fresnel DFT) of the frames
+    t_idx, and the depth DFT of n_cols pixel columns (random values: its time does not depend on them).
+    Returns (seconds of steps 1-2, seconds of the depth DFT)."""
     from oracle import ssoct_oracle as O
-    T, N, _ = sw.frames.shape
-    s = O.scale_factors(sw.lam)
-    alpha = O.chirp_rates(sw.lam, sw.pitch, sw.z)
+    N = frames.shape[1]
+    T = len(lam)
+    s = O.scale_factors(lam)
+    alpha = O.chirp_rates(lam, pitch, z)
     t0 = time.perf_counter()
-    for t in range(n_frames):
-        J = O.rescale(sw.frames[t], s[t])
+    for i, t in enumerate(t_idx):
+        J = O.rescale(frames[i], s[t])
         O.fresnel_fft(O.chirp(N, alpha[t]) * J)
     t_frames = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    h = rng.standard_normal((T, n_cols)) + 1j * rng.standard_normal((T, n_cols))
-    t0 = time.perf_counter()
-    O.depth_dft(h)
-    t_depth = time.perf_counter() - t0
+    t_depth = 0.0
+    if n_cols > 0:
+        rng = np.random.default_rng(seed)
+        h = rng.standard_normal((T, n_cols)) + 1j * rng.standard_normal((T, n_cols))
+        t0 = time.perf_counter()
+        O.depth_dft(h)
+        t_depth = time.perf_counter() - t0
+    return t_frames, t_depth
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(sw, n_frames=32, n_cols=65536, max_workers=16):
+    """The FP64 oracle as it stands, timed on the host: one thread on a bounded sample scaled to one
+    volume, and the whole volume split over the host's cores (one process per core, at most
+    `max_workers`: frames are independent in steps 1-2, pixel columns in the depth DFT).  Run before
+    the GPU is touched (the workers are spawned child processes)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import resource
+    T, N, _ = sw.frames.shape
+    t_frames, t_depth = _oracle_share(sw.frames[:n_frames], sw.lam, list(range(n_frames)), sw.pitch, sw.z,
+                                      n_cols, 0)
     per_volume = t_frames / n_frames * T + t_depth * (N * N / n_cols)
-    return {
+    out = {
         "value": T * N * N / per_volume / 1e9,
         "unit": "Gvoxel/s",
         "cores": 1,
@@ -135,7 +168,51 @@ def cpu_baseline(sw, n_frames=32, n_cols=65536):
         "sample": (f"oracle steps 1-2 (rescale, chirp, Fresnel DFT) on {n_frames} of {T} frames of {N}x{N} "
                    f"and the depth DFT on {n_cols} of {N * N} pixel columns, numpy FP64 single thread, "
                    f"scaled to one {T}x{N}x{N} volume ({per_volume:.1f} s/volume)"),
+        "cpu_model": _cpu_model(),
+        "peak_rss_mib": resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1024.0,
     }
+    n = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    shares = np.array_split(np.arange(T), n)
+    cols = [len(c) for c in np.array_split(np.arange(N * N), n)]
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"          # one thread per worker process
+    ex = cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn"))
+    res = None
+    try:
+        def run(jobs, limit):
+            futs = [ex.submit(_oracle_share, *j) for j in jobs]
+            done, pending = cf.wait(futs, timeout=limit)
+            if pending:
+                raise TimeoutError(f"{len(pending)} of {len(futs)} oracle workers did not finish in {limit} s")
+            return [f.result() for f in futs]
+        run([(sw.frames[:1], sw.lam, [0], sw.pitch, sw.z, 0, 0)] * n, 120)      # start and warm every worker
+        res = run([(sw.frames[sh[0]:sh[-1] + 1], sw.lam, list(sh), sw.pitch, sw.z, c, i)
+                   for i, (sh, c) in enumerate(zip(shares, cols))], 300)
+    except Exception as e:                                                      # reported, never fatal
+        out["all_cores"] = {"value": None, "error": f"{type(e).__name__}: {e}"}
+    finally:
+        for pid, proc in list(getattr(ex, "_processes", {}).items()):
+            if res is None and proc.is_alive():
+                proc.kill()
+        ex.shutdown(wait=res is not None, cancel_futures=True)
+        if env_threads is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_threads
+    if res is None:
+        return out
+    child_rss = resource.getrusage(resource.RUSAGE_CHILDREN).ru_maxrss / 1024.0   # workers have exited
+    wall = max(a + b for a, b in res)                # the slowest worker's share of one volume
+    out["all_cores"] = {
+        "value": T * N * N / wall / 1e9,
+        "unit": "Gvoxel/s",
+        "cores": n,
+        "sample": (f"the whole {T}x{N}x{N} volume split over {n} worker processes (frames for steps 1-2, "
+                   f"pixel columns for the depth DFT), numpy FP64, one thread each; time of the slowest "
+                   f"share ({wall:.2f} s/volume)"),
+        "peak_rss_mib_largest_worker": child_rss,
+    }
+    return out
 
 
 def roofline(rec, form, T, N):
@@ -427,16 +504,22 @@ def bench_nonuniform(sw, forms=("fp32", "bf16_split"), steps=10, warmup=3, accur
     return out
 
 
-def bench_angular_spectrum(sw, forms=("fp32_fft", "bf16_split"), steps=10, warmup=3, z=0.01):
+def bench_angular_spectrum(sw, forms=("fp32_fft", "bf16_split"), steps=10, warmup=3, z=0.01, accuracy=True):
     """Angular-spectrum propagation of every frame at its own wavelength (z = 1 cm, well below
     z_b = 0.17 m of the 12 um camera, where the Fresnel transform is undersampled), then the depth
-    transform.  Three passes per frame instead of two; parity is covered by the GPU tests."""
+    transform.  Three passes per frame instead of two; the volume is checked against the oracle on
+    sampled pixel columns (the GPU tests cover whole volumes)."""
     import torch
 
     from paper_2003_08960_amd.api import Plan
     T, N, _ = sw.frames.shape
     frames = torch.from_numpy(sw.frames).cuda()
     out = {"workload": f"paper-shaped frames, T={T}, N={N}, z={z} m", "forms": {}}
+    pix = sampled_pixels(sw)
+    ref = None
+    if accuracy:
+        from oracle import ssoct_oracle as O
+        ref = O.render_as_columns(sw.frames, sw.lam, sw.pitch, z, pix)
     for form in forms:
         plan = Plan(T, N, precision=form, angular_spectrum=True, profile=True)
         vol = torch.empty((T, N, N), dtype=torch.complex64, device="cuda")
@@ -450,10 +533,15 @@ def bench_angular_spectrum(sw, forms=("fp32_fft", "bf16_split"), steps=10, warmu
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         st = plan.profile_read()
-        out["forms"][form] = {"ms_per_step": ms, "gvoxel_s": T * N * N / (ms * 1e-3) / 1e9,
-                              "propagation_ms": st[1], "depth_ms": st[2],
-                              "propagation_hbm_gb_s": 42 * T * N * N / (st[1] * 1e-3) / 1e9}
-        log(f"angular spectrum {form}: {ms:.3f} ms/step, propagation {st[1]:.3f} ms, depth {st[2]:.3f} ms")
+        rec = {"ms_per_step": ms, "gvoxel_s": T * N * N / (ms * 1e-3) / 1e9,
+               "propagation_ms": st[1], "depth_ms": st[2],
+               "propagation_hbm_gb_s": 42 * T * N * N / (st[1] * 1e-3) / 1e9}
+        if ref is not None:
+            got = np.stack([vol[:, u, v].cpu().numpy() for u, v in pix], axis=1)
+            rec["rel_l2_sampled"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        out["forms"][form] = rec
+        log(f"angular spectrum {form}: {ms:.3f} ms/step, propagation {st[1]:.3f} ms, depth {st[2]:.3f} ms"
+            + (f", rel-L2 {rec['rel_l2_sampled']:.2e}" if "rel_l2_sampled" in rec else ""))
         del plan, vol
         torch.cuda.empty_cache()
     return out
@@ -528,9 +616,18 @@ def main():
               "(sharding a volume across GPUs is described in the design notes only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2003_08960_amd import synth
+
+    log("generating the paper-shaped sweep (T=256, N=1024)")
+    sw = synth.make_config("paper")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (one thread on a sample; all cores on the volume)")
+        cpu = cpu_baseline(sw)
+
     import torch
 
-    from paper_2003_08960_amd import native, synth
+    from paper_2003_08960_amd import native
     from paper_2003_08960_amd.api import Plan
 
     native.load()
@@ -543,8 +640,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
-    log("generating the paper-shaped sweep (T=256, N=1024)")
-    sw = synth.make_config("paper")
     T, N, _ = sw.frames.shape
     voxels = T * N * N
     frames = torch.from_numpy(sw.frames).to(dev)
@@ -633,6 +728,13 @@ def main():
                                "one rectangular depth gate of all frames, complex64 volume + 3 cuts",
                    "T": T, "N": N, "form": head, "pitch_m": sw.pitch, "z_m": sw.z},
         "roofline": roof,
+        "roofline_path": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
+            "achieved": PATH_BYTES_PER_VOXEL * voxels / (hr["ms_per_step"] * 1e-3) / 1e9,
+            "frac": hr["hbm_frac_path"], "bytes_per_voxel": PATH_BYTES_PER_VOXEL,
+            "note": ("the whole render (tables, Fresnel stage, depth transform, cuts) against the 26 B/voxel "
+                     "the method must move (u16 frames in, H out and back in, complex64 volume out); "
+                     "the 60 % target on this figure is not met")},
         "kernels": kernels,
         "stage_a_hbm_frac": FRESNEL_BYTES_PER_VOXEL * voxels / (hr["stage_ms"]["fresnel"] * 1e-3) / HBM_PEAK,
         "hbm_frac_whole_path": hr["hbm_frac_path"],
@@ -650,12 +752,11 @@ def main():
     if not args.no_nonuniform:
         out["nonuniform_k"] = bench_nonuniform(sw, accuracy=not args.no_accuracy)
     if not args.no_as:
-        out["angular_spectrum"] = bench_angular_spectrum(sw)
+        out["angular_spectrum"] = bench_angular_spectrum(sw, accuracy=not args.no_accuracy)
     if not args.no_backward:
         out["backward"] = bench_backward()
-    if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a bounded sample (CPU)")
-        out["cpu_baseline"] = cpu_baseline(sw)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

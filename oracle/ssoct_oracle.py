@@ -341,6 +341,28 @@ def render_as(frames, lam, pitch, z, disp_phase=None, gate=None, nonuniform_k=Fa
     return depth_nudft(out, wavenumber_positions(lam)) if nonuniform_k else depth_dft(out)
 
 
+def render_as_columns(frames, lam, pitch, z, pixels, disp_phase=None, gate=None) -> np.ndarray:
+    """V[:, u, v] of ``render_as`` for each (u, v) in ``pixels`` (complex128 [T, P]): the forward DFT of
+    each frame by the library FFT, times the transfer function, then the inverse DFT evaluated only at
+    the sampled pixels as direct sums (integer phase indices reduced modulo N), and the depth sum of
+    Eq. 7 term by term."""
+    frames, lam = _check(frames, lam)
+    T, N, _ = frames.shape
+    pix = np.asarray(pixels, dtype=np.int64).reshape(-1, 2)
+    k = np.arange(N)
+    Eu = np.exp(2j * np.pi * (np.mod(np.outer(pix[:, 0], k), N) / N))   # [P, N] over row frequencies
+    Ev = np.exp(2j * np.pi * (np.mod(np.outer(pix[:, 1], k), N) / N))   # [P, N] over column frequencies
+    phi = np.zeros(T) if disp_phase is None else np.asarray(disp_phase, dtype=np.float64)
+    g = np.ones(T) if gate is None else np.asarray(gate, dtype=np.float64)
+    h = np.empty((T, pix.shape[0]), dtype=np.complex128)
+    for t in range(T):
+        A = np.fft.fft2(frames[t].astype(np.float64)) * as_transfer(N, lam[t], pitch, z)
+        h[t] = g[t] * np.exp(1j * phi[t]) * np.sum((Eu @ A) * Ev, axis=1) / (N * N)
+    tt = np.arange(T)
+    W = np.exp(-2j * np.pi * (np.mod(np.outer(tt, tt), T) / T))        # W[q, t]
+    return W @ h
+
+
 # ---------------------------------------------------------------------------
 # Whole chain
 # ---------------------------------------------------------------------------

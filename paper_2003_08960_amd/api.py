@@ -362,7 +362,9 @@ class Stream:
                 "cut_xy": xy, "cut_xz": xz, "cut_yz": yz}
 
     def slot_volume(self, slot: int) -> torch.Tensor:
-        """Device complex volume of a slot (a view, valid until the slot is reused)."""
+        """Device complex volume of a slot (a view, valid until the slot is reused: a read of the view on
+        torch's stream must have completed, e.g. torch.cuda.synchronize(), before the slot is acquired,
+        pushed into or submitted again)."""
         ptr = ctypes.c_void_p()
         native.check(self.lib.ssoct_stream_slot_volume(self._h, int(slot), ctypes.byref(ptr)))
         raw = torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N, 2), "<f4"), device=self.plan.device)
@@ -455,7 +457,9 @@ class Slide:
                 "cut_xy": xy, "cut_xz": xz, "cut_yz": yz}
 
     def volume(self, slot: int) -> torch.Tensor:
-        """Device complex volume of an output slot (a view, valid until the slot is reused)."""
+        """Device complex volume of an output slot (a view, valid until the slot is reused: the next
+        push or advance may start a window in it on the library's stream, so a read of the view, e.g. a
+        clone on torch's stream, must have completed, e.g. torch.cuda.synchronize(), before that call)."""
         ptr = ctypes.c_void_p()
         native.check(self.lib.ssoct_slide_volume(self._h, int(slot), ctypes.byref(ptr)))
         raw = torch.as_tensor(_DeviceArray(ptr.value, (self.T, self.N, self.N, 2), "<f4"), device=self.plan.device)

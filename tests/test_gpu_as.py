@@ -95,6 +95,7 @@ def test_as_sliding_window(gpu_lib):
         assert sl.push(np.ascontiguousarray(frames[seq:seq + n]), seq) == native.OK
         while (r := sl.pop(wait=True)) is not None:
             got[r["start"]] = sl.volume(r["slot"]).clone()
+            torch.cuda.synchronize()      # the copy is done before a later window may reuse the slot
     sl.close()
     assert sorted(got) == list(range(0, frames.shape[0] - T + 1, 4))
     for j in got:

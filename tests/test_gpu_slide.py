@@ -52,6 +52,8 @@ def run_host_fed(plan, frames, lam, hop, disp=None, zern=None, chunk=None):
             if r is None:
                 break
             out[r["start"]] = (sl.volume(r["slot"]).clone(), (r["cut_xy"], r["cut_xz"], r["cut_yz"]))
+            torch.cuda.synchronize()      # the copy is done before a later window may reuse the slot
+            torch.cuda.synchronize()      # the copy is done before a later window may reuse the slot
     assert sl.stats()["dropped_windows"] == 0
     sl.close()
     return out
@@ -112,6 +114,7 @@ def test_device_resident_ring_equals_host_fed(gpu_lib, stream_frames):
             if r is None:
                 break
             got[r["start"]] = sl.volume(r["slot"]).clone()
+            torch.cuda.synchronize()      # the copy is done before a later window may reuse the slot
     sl.close()
     assert sorted(got) == sorted(ref)
     for j in got:
@@ -136,6 +139,7 @@ def test_sequence_gap_restarts_the_windows(gpu_lib, stream_frames):
     got = {}
     while (r := sl.pop(wait=True)) is not None:
         got[r["start"]] = sl.volume(r["slot"]).clone()
+        torch.cuda.synchronize()      # the copy is done before a later window may reuse the slot
     assert sorted(got) == [45]
     assert rel_l2(got[45].cpu().numpy(), oracle_window(frames, lam, 45)) <= 1e-5
     assert sl.stats()["restarts"] == 1

@@ -646,6 +646,20 @@ def test_render_as_parseval_and_depth():
     assert abs(np.sum(np.abs(V) ** 2) / (T * np.sum(frames.astype(np.float64) ** 2)) - 1) < 1e-12
 
 
+def test_render_as_columns_match_render_as():
+    """The sampled-pixel evaluation (inverse DFT as direct sums) against the FFT-based render_as, every
+    pixel of a tiny sweep, with dispersion and a gate."""
+    rng = np.random.default_rng(3)
+    T, N = 5, 16
+    frames = rng.integers(0, 65536, size=(T, N, N)).astype(np.uint16)
+    lam = synth.sweep_wavelengths(T, 870e-9, 800e-9)
+    phi, g = rng.uniform(-2, 2, T), np.hanning(T)
+    V = O.render_as(frames, lam, 10e-6, 0.003, phi, g)
+    pix = [(u, v) for u in range(N) for v in range(N)]
+    Vc = O.render_as_columns(frames, lam, 10e-6, 0.003, pix, phi, g)
+    assert np.allclose(V.reshape(T, -1), Vc, rtol=0, atol=1e-10 * np.abs(V).max())
+
+
 # --------------------------------------------------------------------------
 # Planted mistakes: each plausible error in the oracle must fail a pin
 # --------------------------------------------------------------------------
