@@ -96,7 +96,7 @@ def traffic_record(kernel: str):
 
 def traffic_key(kernel: str, form: str) -> str:
     """Name of a kernel variant in profiles/traffic.json."""
-    if kernel == "k_row_pass":
+    if kernel in ("k_row_pass", "k_rescale_dft_win", "k_row_pass_g", "k_col_pass_v"):
         return kernel
     if kernel == "k_col_pass":
         return f"k_col_pass_{form.split('_')[0]}"      # the column pass differs by H format only
@@ -215,24 +215,44 @@ def cpu_baseline(sw, n_frames=32, n_cols=65536, max_workers=16):
     return out
 
 
+def depth_first(rec, form) -> bool:
+    """The FFT form renders the bench's sweep in the depth-first order when its tuning asks for it
+    (default chirp, no dispersion, no gate: the order is allowed)."""
+    return form == "fp32_fft" and rec["tuning"]["order"] == 1
+
+
 def roofline(rec, form, T, N):
     """Per-kernel achieved rates from the live HIP-event times of one step, and
     the roofline object of the kernel that takes the most time per step."""
     voxels = T * N * N
     st = rec["stage_ms"]
     sp = rec["fresnel_split_ms"]
-    nch = -(-T // rec["tuning"]["frames_per_chunk"])
+    form = form.removesuffix("_frame")
     prec = form.split("_")[0]
-    dname = "k_depth_fft" if form.endswith("_fft") else ("k_depth_4step" if form.endswith("_4step") else "k_depth")
     # The per-launch events of the split pass add a gap after every launch; the
     # split is rescaled to the event-free Fresnel-stage time of the timed steps.
     scale = st["fresnel"] / (sp["row_pass"] + sp["col_pass"]) if sp["row_pass"] > 0 and sp["col_pass"] > 0 else 0.0
-    ks = {
-        # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
-        dname: (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
-        "k_row_pass": (sp["row_pass"] * scale, nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
-        "k_col_pass": (sp["col_pass"] * scale, nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
-    }
+    if depth_first(rec, form):
+        # stage 1: u16 frames in, the T/2 + 1 Hermitian bins of the depth DFT out; stage 2 per chunk of
+        # bins: the bins in, both transforms (q and T - q; one for q = 0 and q = T/2) out, then the column
+        # DFTs of those transforms into the volume
+        nb = T // 2 + 1
+        fh = max(rec["tuning"]["frames_per_chunk"] // 2, 1)
+        nch = -(-nb // fh)
+        ks = {
+            "k_rescale_dft_win": (st["depth"], 1, (2 * T + 8 * nb) * N * N, 0.0),
+            "k_row_pass_g": (sp["row_pass"] * scale, nch, (8 * nb + 8 * T) * N * N, 0.0),
+            "k_col_pass_v": (sp["col_pass"] * scale, nch, 16 * voxels, 0.0),
+        }
+    else:
+        nch = -(-T // rec["tuning"]["frames_per_chunk"])
+        dname = "k_depth_fft" if form.endswith("_fft") else ("k_depth_4step" if form.endswith("_4step") else "k_depth")
+        ks = {
+            # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
+            dname: (st["depth"], 1, DEPTH_BYTES_PER_VOXEL * voxels, depth_flops(T, N, form)),
+            "k_row_pass": (sp["row_pass"] * scale, nch, ROW_BYTES_PER_VOXEL * voxels, 0.0),
+            "k_col_pass": (sp["col_pass"] * scale, nch, COL_BYTES_PER_VOXEL * voxels, 0.0),
+        }
     kernels = {}
     for name, (ms, n, byts, flops) in ks.items():
         if ms is None or ms <= 0:
@@ -595,7 +615,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp32,fp32_fft,fp32_4step,fp16_split,bf16_split,bf16_split_4step,fp16,bf16")
+    ap.add_argument("--forms",
+                    default="fp32,fp32_fft,fp32_fft_frame,fp32_4step,fp16_split,bf16_split,bf16_split_4step,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming form")
@@ -654,9 +675,14 @@ def main():
     forms = {}
     x0, y0, q0 = N // 2, N // 2, T // 4
     for form in [f for f in args.forms.split(",") if f]:
-        plan = Plan(T, N, precision=form, profile=True)
+        # "<precision>_frame": the FFT form held to the frame order (its default is depth first)
+        prec_name = form.removesuffix("_frame")
+        plan = Plan(T, N, precision=prec_name, profile=True)
         vol = torch.empty((T, N, N), dtype=torch.complex64, device=dev)
         tuning = plan.tune(frames, sw.lam, sw.pitch, sw.z, out=vol) if args.tune else plan.get_tuning()
+        if form.endswith("_frame"):
+            tuning = tuning[:3] + [0]
+            plan.set_tuning(tuning)
         for _ in range(args.warmup):
             plan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
             plan.cuts(vol, x0, y0, q0)
@@ -674,7 +700,7 @@ def main():
         del plan
         torch.cuda.empty_cache()
         # untimed pass with an event after every Fresnel-stage launch: per-pass split of that stage
-        kplan = Plan(T, N, precision=form, profile="kernels")
+        kplan = Plan(T, N, precision=prec_name, profile="kernels")
         kplan.set_tuning(tuning)
         for _ in range(3):
             kplan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
@@ -736,7 +762,10 @@ def main():
                      "the method must move (u16 frames in, H out and back in, complex64 volume out); "
                      "the 60 % target on this figure is not met")},
         "kernels": kernels,
-        "stage_a_hbm_frac": FRESNEL_BYTES_PER_VOXEL * voxels / (hr["stage_ms"]["fresnel"] * 1e-3) / HBM_PEAK,
+        # stage A (rescale + chirp + 2-D DFT) as one stage exists in the frame order only
+        "stage_a_hbm_frac": (None if depth_first(hr, head) else
+                             FRESNEL_BYTES_PER_VOXEL * voxels / (hr["stage_ms"]["fresnel"] * 1e-3) / HBM_PEAK),
+        "order": "depth first" if depth_first(hr, head) else "frame",
         "hbm_frac_whole_path": hr["hbm_frac_path"],
         "forms": forms,
         "paper_context_gvoxel_s": PAPER_GVOXEL_S,
@@ -747,7 +776,7 @@ def main():
         stream_form = min(split, key=lambda f: forms[f]["ms_per_step"]) if split else head
         out["streaming"] = bench_stream(sw, stream_form, paced=not args.no_paced)
     if not args.no_slide:
-        out["sliding"] = bench_slide(sw, head if head.startswith("fp32") else "fp32_fft",
+        out["sliding"] = bench_slide(sw, head.removesuffix("_frame") if head.startswith("fp32") else "fp32_fft",
                                      paced=not args.no_paced)
     if not args.no_nonuniform:
         out["nonuniform_k"] = bench_nonuniform(sw, accuracy=not args.no_accuracy)

@@ -235,12 +235,12 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  * persistent workgroups of the dense depth transform (0 = default; the
  * SSOCT_DEPTH_FFT and SSOCT_DEPTH_4STEP forms launch one workgroup per pixel
  * tile and ignore it), tuning[3] evaluation
- * order of the SSOCT_DEPTH_FFT form (0 = default: Fresnel transform of every
- * frame, then the depth transform; 1 = depth transform of the rescaled real
+ * order of the SSOCT_DEPTH_FFT form (0 = Fresnel transform of every frame,
+ * then the depth transform; 1 = default: depth transform of the rescaled real
  * frames first, then one Fresnel transform per bin, which by linearity is the
  * same map when the chirp and the per-frame factor do not depend on the
- * frame: no SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS; otherwise
- * the frame order is used).  tuning[0..2] change speed only, never results;
+ * frame: no SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS, no gate;
+ * otherwise the frame order is used).  tuning[0..2] change speed only, never results;
  * tuning[3] changes the rounding order only. */
 
 /* Time candidate launch shapes (and, where allowed, both evaluation orders)

@@ -218,32 +218,40 @@ __device__ __forceinline__ void src_pos(int i, int N, double s, int& i0, float& 
 
 // The same transform for N >= 64, where a tile of PX = 32 FFT positions lies
 // inside one row and one half of the centred order, so its source columns at
-// frame t are a window of at most PX + 2 samples (s_t <= 1) starting at the
-// first position's column.  The two source rows of that window are staged
-// in LDS for every frame with aligned dword loads, and the interpolation
-// reads LDS: one coalesced load per dword instead of four scattered 2-byte
-// gathers and two 16-byte table reads per sample.
+// frame t form a window.  The two source rows of every frame's window are
+// interpolated along y once while they are staged (16-byte loads of 8
+// samples, FP32 rows in LDS), so that each sample then takes two LDS reads
+// and one interpolation along x; twiddles are staged in LDS.  The window of
+// a 32-position tile at frame t starts at the first position's source
+// column rounded down to 8 samples and spans 40 samples: the last position's
+// right tap lies at most 7 + 31 + 1 samples past the start (s_t <= 1).
+// Chunks starting at or past column N are zero (only the right tap of the
+// last column reads there, with weight 0).
 template <int T2>
-__global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restrict__ frames,
+__global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restrict__ frames,
                                                          const double* __restrict__ params,
                                                          const float2* __restrict__ wt, float2* __restrict__ G,
                                                          int N, int logN) {
   constexpr int PX = 32;
   constexpr int T = 16 * T2;
-  constexpr int WD = PX / 2 + 2;             // dwords per staged row window (36 samples >= PX + 3)
+  constexpr int NT = 16 * PX;                 // threads
+  constexpr int WS = 40;                      // staged samples per frame (five chunks of 8)
+  constexpr int NCH = WS / 8;
+  constexpr int NITEM = T * NCH;              // (frame, chunk) staging items
+  constexpr int NI = (NITEM + NT - 1) / NT;
   constexpr int STRIDE = ParamLayout::PER_FRAME;   // doubles per frame in the parameter block (s_t first)
-  constexpr int NE = (T * 2 * WD + 16 * PX - 1) / (16 * PX);
-  __shared__ float2 lds[T * PX];             // transposition buffer; the staged windows alias it
-  __shared__ double fs[T], fp[T];            // per frame: s_t and the source position of the tile's first column
-  __shared__ int fy0[T], fxa[T];             // per frame: source row y0 and the even start of the window
-  __shared__ float ffy[T];                   // per frame: y weight
-  static_assert(T * 2 * WD * 4 <= T * PX * 8, "staged windows must fit the transposition buffer");
-  uint32_t* foot = reinterpret_cast<uint32_t*>(lds);   // [T][2][WD]
-  const int px = threadIdx.x % PX, r = threadIdx.x / PX;
+  __shared__ float2 lds[T * PX];              // transposition [q2][t1][px]; the staged rows alias it
+  __shared__ float2 tws[T];                   // exp(-2 pi i k / T)
+  __shared__ double fs[T], fp[T];             // per frame: s_t and the source position of the tile's first column
+  __shared__ int frow[T], fxs[T];             // per frame: source row y0 and the window start
+  __shared__ float ffy[T];                    // per frame: y weight
+  static_assert(T * WS * 4 <= T * PX * 8, "staged rows must fit the transposition buffer");
+  float* ya = reinterpret_cast<float*>(lds);  // [T][WS]
+  const int tid = threadIdx.x;
+  const int px = tid % PX, r = tid / PX;
   const size_t P = (size_t)N * N;
-  // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles so that neighbouring strips and rows, which share
-  // source rows, meet in one L2
+  // contiguous runs of tiles per XCD (workgroups are dispatched round-robin
+  // over the XCDs), so that neighbouring rows, which share source rows, meet in one L2
   const int tile = (gridDim.x % SSOCT_XCDS == 0)
                        ? (blockIdx.x % SSOCT_XCDS) * (gridDim.x / SSOCT_XCDS) + blockIdx.x / SSOCT_XCDS
                        : blockIdx.x;
@@ -251,8 +259,7 @@ __global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restr
   const int m = pix0 >> logN, n0 = pix0 & (N - 1);
   const int half = N >> 1;
   const int c0 = ((n0 + half) & (N - 1)) - half;   // centred index of the first column (same half as the tile)
-
-  for (int t = threadIdx.x; t < T; t += 16 * PX) {
+  for (int t = tid; t < T; t += NT) {
     const double st = params[(size_t)STRIDE * t];
     int y0, x0;
     float fy, fx;
@@ -260,34 +267,53 @@ __global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restr
     src_pos(n0, N, st, x0, fx);
     fs[t] = st;
     fp[t] = __dadd_rn(__dmul_rn((double)c0, st), (double)half);
-    fy0[t] = y0;
+    frow[t] = y0;
     ffy[t] = fy;
-    fxa[t] = x0 & ~1;
+    fxs[t] = x0 & ~7;
+    tws[t] = wt[t];
   }
   __syncthreads();
-  // every load of the staging is in flight before the first LDS store
-  uint32_t stage[NE];
+  // every staging load is in flight before the first interpolation
+  uint4 ra[NI], rb[NI];
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * 16 * PX;
-    stage[i] = 0u;
-    if (e < T * 2 * WD) {
-      const int t = e / (2 * WD), rr = (e / WD) & 1, d = e % WD;
-      const int y0 = fy0[t];
-      const int y = rr ? (y0 + 1 < N ? y0 + 1 : N - 1) : y0;
-      const int col = fxa[t] + 2 * d;
-      const uint16_t* row = frames + (size_t)t * P + (size_t)y * N;
-      if (col + 1 < N) stage[i] = *reinterpret_cast<const uint32_t*>(row + col);
-      else if (col < N) stage[i] = row[col];
+  for (int k = 0; k < NI; ++k) {
+    const int i = tid + k * NT;
+    ra[k] = make_uint4(0u, 0u, 0u, 0u);
+    rb[k] = ra[k];
+    if (i < NITEM) {
+      const int t = i / NCH, c = i - (i / NCH) * NCH;
+      const int x = fxs[t] + 8 * c;
+      if (x < N) {   // x and N are multiples of 8: the chunk is whole
+        const int y0 = frow[t];
+        const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
+        const uint16_t* col = frames + (size_t)t * P + x;
+        ra[k] = *reinterpret_cast<const uint4*>(col + (size_t)y0 * N);
+        rb[k] = *reinterpret_cast<const uint4*>(col + (size_t)y1 * N);
+      }
     }
   }
 #pragma unroll
-  for (int i = 0; i < NE; ++i) {
-    const int e = threadIdx.x + i * 16 * PX;
-    if (e < T * 2 * WD) foot[e] = stage[i];
+  for (int k = 0; k < NI; ++k) {
+    const int i = tid + k * NT;
+    if (i < NITEM) {
+      const int t = i / NCH, c = i - (i / NCH) * NCH;
+      const float fy = ffy[t];
+      const uint32_t wa[4] = {ra[k].x, ra[k].y, ra[k].z, ra[k].w};
+      const uint32_t wb[4] = {rb[k].x, rb[k].y, rb[k].z, rb[k].w};
+      float o[8];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float a0 = (float)(wa[h] & 0xffffu), a1 = (float)(wa[h] >> 16);
+        const float b0 = (float)(wb[h] & 0xffffu), b1 = (float)(wb[h] >> 16);
+        o[2 * h] = a0 + fy * (b0 - a0);            // lerp along y (then along x below)
+        o[2 * h + 1] = a1 + fy * (b1 - a1);
+      }
+      float4* dst = reinterpret_cast<float4*>(ya + t * WS + 8 * c);
+      dst[0] = make_float4(o[0], o[1], o[2], o[3]);
+      dst[1] = make_float4(o[4], o[5], o[6], o[7]);
+    }
   }
   __syncthreads();
-
   float2 a[T2];
 #pragma unroll
   for (int t2 = 0; t2 < T2; ++t2) {
@@ -295,21 +321,15 @@ __global__ __launch_bounds__(512) void k_rescale_dft_lds(const uint16_t* __restr
     // N/2 + (c0 + px) s_t = fp[t] + px s_t up to FP64 rounding; column and weight as in the tables
     const double Pd = fma((double)px, fs[t], fp[t]);
     const double p0 = floor(Pd);
-    const int o0 = (int)p0 - fxa[t];
     const float fx = (float)(Pd - p0);
-    const float fy = ffy[t];
-    // right tap: the next sample of the window (zero past the last column, where fx is exactly 0)
-    const uint16_t* w0 = reinterpret_cast<const uint16_t*>(foot + (t * 2) * WD);
-    const uint16_t* w1 = reinterpret_cast<const uint16_t*>(foot + (t * 2 + 1) * WD);
-    const float a00 = w0[o0], a01 = w0[o0 + 1], a10 = w1[o0], a11 = w1[o0 + 1];
-    const float ya = a00 + fy * (a10 - a00);          // lerp along y, then along x
-    const float yb = a01 + fy * (a11 - a01);
-    a[t2] = make_float2(ya + fx * (yb - ya), 0.f);
+    const float* w = ya + t * WS + ((int)p0 - fxs[t]);
+    const float y0 = w[0], y1 = w[1];
+    a[t2] = make_float2(y0 + fx * (y1 - y0), 0.f);
   }
-  __syncthreads();   // window reads done before the transposition buffer is written
+  __syncthreads();   // staged rows read before the transposition buffer is written
   if constexpr (T2 > 1) dft_small<T2, -1>(a);
 #pragma unroll
-  for (int q2 = 0; q2 < T2; ++q2) lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], wt[(q2 * r) % T]);
+  for (int q2 = 0; q2 < T2; ++q2) lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], tws[(q2 * r) & (T - 1)]);
   __syncthreads();
   if (r >= T2) return;
   float2 b[16];
@@ -330,7 +350,7 @@ static hipError_t rescale_dft_t(int N, const uint16_t* frames, const AxisTab* ro
   while ((1 << logN) < N) ++logN;
   const size_t P = (size_t)N * N;
   if (N >= 64) {
-    hipLaunchKernelGGL((k_rescale_dft_lds<T2>), dim3((unsigned)(P / 32)), dim3(512), 0, s, frames, params, wt, G, N,
+    hipLaunchKernelGGL((k_rescale_dft_win<T2>), dim3((unsigned)(P / 32)), dim3(512), 0, s, frames, params, wt, G, N,
                        logN);
   } else {
     constexpr int PX = SSOCT_DFFT_PX;

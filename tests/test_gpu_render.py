@@ -319,9 +319,11 @@ def test_depth_first_zero_dispersion_and_chunking(gpu_lib, tiny):
     T, N = tiny.frames.shape[:2]
     fr = torch.from_numpy(tiny.frames).cuda()
     plan = Plan(T, N, precision="fp32_fft")
+    assert plan.get_tuning()[3] == 1                                        # the default order
+    V0 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()              # depth-first order
+    plan.set_tuning(plan.get_tuning()[:3] + [0])
     Vf = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()              # frame order
     plan.set_tuning(plan.get_tuning()[:3] + [1])
-    V0 = plan.render(fr, tiny.lam, tiny.pitch, tiny.z).clone()              # depth-first order
     ref = O.render(tiny.frames, tiny.lam, tiny.pitch, tiny.z)
     assert rel_l2(V0.cpu().numpy(), ref) <= FP32_BAR
     assert rel_l2(Vf.cpu().numpy(), ref) <= FP32_BAR
