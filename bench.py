@@ -239,10 +239,12 @@ def roofline(rec, form, T, N):
         nb = T // 2 + 1
         fh = max(rec["tuning"]["frames_per_chunk"] // 2, 1)
         nch = -(-nb // fh)
+        # column launches: one per chunk for bins q, one more for the partners T - q (0 < q < T/2)
+        ncol = sum(1 + (min(qa + fh, (T + 1) // 2) > max(qa, 1)) for qa in range(0, nb, fh))
         ks = {
             "k_rescale_dft_win": (st["depth"], 1, (2 * T + 8 * nb) * N * N, 0.0),
             "k_row_pass_g": (sp["row_pass"] * scale, nch, (8 * nb + 8 * T) * N * N, 0.0),
-            "k_col_pass_v": (sp["col_pass"] * scale, nch, 16 * voxels, 0.0),
+            "k_col_pass_v": (sp["col_pass"] * scale, ncol, 16 * voxels, 0.0),
         }
     else:
         nch = -(-T // rec["tuning"]["frames_per_chunk"])
@@ -283,6 +285,13 @@ def roofline(rec, form, T, N):
     return roof, kernels
 
 
+def tuning_record(t):
+    """A plan's launch shapes by name (include/ssoct.h, tuning array; 0 = the default)."""
+    return {"frames_per_chunk": t[0], "col_workgroups": t[1], "depth_workgroups": t[2], "order": t[3],
+            "rows_per_group_depth_first": t[4], "col_tile": t[5], "depth_fft_px": t[6],
+            "radix_plan": "16 x 16 x 4 (N = 1024: fixed by N)"}
+
+
 def pctl(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
@@ -304,7 +313,7 @@ def bench_stream(sw, form, n_vol=16, slots=3, fps=512.0, chunk=16, paced=True):
     tuning = plan.tune(frames_dev, sw.lam, sw.pitch, sw.z, out=ws_vol)
     del ws_vol
     torch.cuda.empty_cache()
-    out = {"form": form, "volumes": n_vol, "slots": slots, "tuning": tuning}
+    out = {"form": form, "volumes": n_vol, "slots": slots, "tuning": tuning_record(tuning)}
 
     st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=slots)
     # device-resident: every slot holds the sweep; each volume is one graph launch
@@ -681,7 +690,7 @@ def main():
         vol = torch.empty((T, N, N), dtype=torch.complex64, device=dev)
         tuning = plan.tune(frames, sw.lam, sw.pitch, sw.z, out=vol) if args.tune else plan.get_tuning()
         if form.endswith("_frame"):
-            tuning = tuning[:3] + [0]
+            tuning = tuning[:3] + [0] + tuning[4:]
             plan.set_tuning(tuning)
         for _ in range(args.warmup):
             plan.render(frames, sw.lam, sw.pitch, sw.z, out=vol)
@@ -715,8 +724,7 @@ def main():
                "fresnel_split_ms": {"row_pass": kst[4], "col_pass": kst[5], "fresnel": kst[1],
                                     "note": "separate untimed pass with an event after every launch"},
                "hbm_frac_path": PATH_BYTES_PER_VOXEL * voxels / (ms * 1e-3) / HBM_PEAK,
-               "tuning": {"frames_per_chunk": tuning[0], "col_workgroups": tuning[1],
-                          "depth_workgroups": tuning[2], "order": tuning[3]}}
+               "tuning": tuning_record(tuning)}
         if ref_cols is not None:
             got = np.stack([vol[:, u, v].cpu().numpy() for u, v in pix], axis=1)
             rec["rel_l2_sampled"] = float(np.linalg.norm(got - ref_cols) / np.linalg.norm(ref_cols))

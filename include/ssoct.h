@@ -225,33 +225,50 @@ int ssoct_plan_set_gate(ssoct_plan* plan, const double* gate);
 int ssoct_profile_read(ssoct_plan* plan, float* ms);
 
 /* ---------------------------------------------------------------- tuning
- * Launch-shape parameters of a plan, int tuning[4]: tuning[0] frames per
- * chunk of the Fresnel stage (1 .. the chunk the workspace was sized for),
- * tuning[1] persistent column-pass workgroups (0 = default: as many as are
- * resident at once on the device wherever the column pass prefetches its
- * next tile, which is the angular-spectrum column pass at every N and the
- * Fresnel column pass up to N = 1024; 512 for the Fresnel column pass at
- * N = 2048), tuning[2]
- * persistent workgroups of the dense depth transform (0 = default; the
- * SSOCT_DEPTH_FFT and SSOCT_DEPTH_4STEP forms launch one workgroup per pixel
- * tile and ignore it), tuning[3] evaluation
- * order of the SSOCT_DEPTH_FFT form (0 = Fresnel transform of every frame,
- * then the depth transform; 1 = default: depth transform of the rescaled real
- * frames first, then one Fresnel transform per bin, which by linearity is the
- * same map when the chirp and the per-frame factor do not depend on the
- * frame: no SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS, no gate;
- * otherwise the frame order is used).  tuning[0..2] change speed only, never results;
- * tuning[3] changes the rounding order only. */
+ * Launch-shape parameters of a plan, int tuning[SSOCT_TUNING_LEN]:
+ *   [0] frames per chunk of the Fresnel stage (1 .. the chunk the workspace
+ *       was sized for; in the depth-first order two transforms per bin, so
+ *       half as many bins per chunk)
+ *   [1] persistent column-pass workgroups (0 = default: as many as are
+ *       resident at once on the device wherever the column pass prefetches
+ *       its next tile, which is the angular-spectrum column pass at every N
+ *       and the Fresnel column pass up to N = 1024; 512 for the Fresnel
+ *       column pass at N = 2048)
+ *   [2] persistent workgroups of the dense depth transform (0 = default; the
+ *       SSOCT_DEPTH_FFT and SSOCT_DEPTH_4STEP forms launch one workgroup per
+ *       pixel tile and ignore it)
+ *   [3] evaluation order of the SSOCT_DEPTH_FFT form (0 = Fresnel transform
+ *       of every frame, then the depth transform; 1 = default: depth
+ *       transform of the rescaled real frames first, then one Fresnel
+ *       transform per bin, which by linearity is the same map when the chirp
+ *       and the per-frame factor do not depend on the frame: no
+ *       SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS, no gate;
+ *       otherwise the frame order is used)
+ *   [4] rows per row group of the depth-first order's row pass (0 = chosen by
+ *       the launch size; 2, 4 or 8)
+ *   [5] column tile width of the Fresnel column passes (0 = default, 16
+ *       adjacent columns up to N = 1024; N >= 512 also takes 1/2 and 1/4 of
+ *       the default; the adjoint keeps the default)
+ *   [6] pixels per workgroup of the FFT-form depth transform (0 = default 32;
+ *       16, 32 or 64)
+ *   [7] reserved, 0
+ * [3] changes the rounding order only; every other entry changes speed only,
+ * never results. */
+#define SSOCT_TUNING_LEN 8
 
-/* Time candidate launch shapes (and, where allowed, both evaluation orders)
- * on the given inputs (HIP events on the plan's stream; synchronises the
- * stream), keep the fastest in the plan and write it to tuning[4].
- * Arguments as for ssoct_plan_render; vol is overwritten. */
+/* Time candidate launch shapes (the evaluation order where allowed, then the
+ * Fresnel stage's frames per chunk, column tile width, column workgroups and,
+ * in the depth-first order, rows per row group; then the depth transform's
+ * pixels per workgroup (FFT form) or workgroups (dense form)) on the given
+ * inputs with HIP events on the plan's stream (synchronises the stream),
+ * keep the fastest of each in the plan and write them to tuning.  Arguments
+ * as for ssoct_plan_render; vol is overwritten. */
 int ssoct_plan_tune(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                     const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                     void* vol, int* tuning);
 
-/* Read or set the launch-shape parameters (e.g. from a tuning cache). */
+/* Read or set the launch-shape parameters (e.g. from a tuning cache);
+ * SSOCT_TUNING_LEN entries. */
 int ssoct_plan_get_tuning(const ssoct_plan* plan, int* tuning);
 int ssoct_plan_set_tuning(ssoct_plan* plan, const int* tuning);
 

@@ -192,19 +192,19 @@ class Plan:
 
     # -- launch shapes ---------------------------------------------------------------------------
     def get_tuning(self):
-        """[frames per chunk, column workgroups, depth workgroups, evaluation order]."""
-        t = (ctypes.c_int * 4)()
+        """[frames per chunk, column workgroups, depth workgroups, evaluation order, rows per row group
+        (depth-first order), column tile width, FFT depth pixels per workgroup, 0] (include/ssoct.h)."""
+        t = (ctypes.c_int * native.TUNING_LEN)()
         native.check(self.lib.ssoct_plan_get_tuning(self._h, t))
         return [int(x) for x in t]
 
     def set_tuning(self, tuning):
-        """Set launch shapes; a 3-entry list keeps the current evaluation order."""
+        """Set launch shapes; a shorter list keeps the plan's current values of the entries it omits."""
         vals = [int(x) for x in tuning]
-        if len(vals) == 3:
-            vals.append(self.get_tuning()[3])
-        if len(vals) != 4:
-            raise ValueError("tuning has 3 or 4 entries")
-        t = (ctypes.c_int * 4)(*vals)
+        if not 1 <= len(vals) <= native.TUNING_LEN:
+            raise ValueError(f"tuning has 1 to {native.TUNING_LEN} entries")
+        vals += self.get_tuning()[len(vals):]
+        t = (ctypes.c_int * native.TUNING_LEN)(*vals)
         native.check(self.lib.ssoct_plan_set_tuning(self._h, t))
 
     def tuning_key(self) -> str:
@@ -224,7 +224,7 @@ class Plan:
                 return list(cached)
         _check_frames(frames, self.T, self.N, self.device)
         out = self.render(frames, lam, pitch, z, disp_phase, zernike, out=out)
-        t = (ctypes.c_int * 4)()
+        t = (ctypes.c_int * native.TUNING_LEN)()
         self._sync_stream()
         native.check(self.lib.ssoct_plan_tune(
             self._h, ctypes.c_void_p(_ptr(frames)), native.host_doubles(lam, self.T), float(pitch), float(z),

@@ -290,9 +290,10 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
   return status;
 }
 
-// Persistent column workgroups: the tuned count, else the default for N
-static int col_grid_of(const ssoct_plan* p) {
-  return p->col_grid > 0 ? p->col_grid : col_default_grid(p->N, p->cu);
+// Persistent column workgroups: the tuned count, else the default for N and
+// the column tile width in use (ct; 0 = the default tile)
+static int col_grid_of(const ssoct_plan* p, int ct = 0) {
+  return p->col_grid > 0 ? p->col_grid : col_default_grid(p->N, p->cu, ct);
 }
 
 // Fresnel stage over all frames, chunk by chunk: row pass (rescale + chirp +
@@ -313,7 +314,8 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   const float* ab = p->have_aberr ? p->apoly : nullptr;
   SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
-  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p), s));
+  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p, p->col_tile), s,
+                            p->col_tile));
   return SSOCT_OK;
 }
 
@@ -322,7 +324,7 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
   const int epi = (p->flags & SSOCT_WRITE_ABS) ? EPI_ABS : EPI_STORE;
   if (p->flags & SSOCT_DEPTH_FFT) {
     SSOCT_HIP(launch_depth_fft(p->T, p->N * p->N, +1, epi, reinterpret_cast<const float2*>(ws + L.H), p->dtw, vol, s,
-                               shift, 0, nullptr, depth_fft_grid(p->cu)));
+                               shift, 0, nullptr, depth_fft_grid(p->cu), p->dfft_px));
     return SSOCT_OK;
   }
   if (p->flags & SSOCT_DEPTH_4STEP) {
@@ -364,14 +366,15 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
   if (ev) SSOCT_HIP(hipEventRecord(ev[2], s));
   for (int qa = 0, c = 0; qa < nb; qa += fh, ++c) {
     const int n = nb - qa < fh ? nb - qa : fh;
-    SSOCT_HIP(launch_row_pass_g(N, n, qa, T, G, p->rows, p->cols, p->tw, ab, p->outfac, inter, fh, s));
+    SSOCT_HIP(launch_row_pass_g(N, n, qa, T, G, p->rows, p->cols, p->tw, ab, p->outfac, inter, fh, p->rpg_g, p->cu, s));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c], s));
-    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, col_grid_of(p), s));
+    const int cg = col_grid_of(p, p->col_tile);
+    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, cg, p->col_tile, s));
     const int ca = qa > 1 ? qa : 1;
     const int cb = qa + n < nconj ? qa + n : nconj;
     if (cb > ca)
       SSOCT_HIP(launch_col_pass_v(N, cb - ca, inter + (size_t)(fh + ca - qa) * P, p->tw, p->outfac,
-                                  V + (size_t)(T - ca) * P, -1, col_grid_of(p), s));
+                                  V + (size_t)(T - ca) * P, -1, cg, p->col_tile, s));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
   }
   if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
@@ -391,7 +394,8 @@ int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, 
       const int Fc = T - t0 < F ? T - t0 : F;
       SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
       SSOCT_HIP(hipEventRecord(kev[2 * c], s));
-      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p), s));
+      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma,
+                                col_grid_of(p, p->col_tile), s, p->col_tile));
       SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
     }
   } else {
@@ -784,6 +788,10 @@ int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
   tuning[1] = p->col_grid;
   tuning[2] = p->depth_grid;
   tuning[3] = p->order;
+  tuning[4] = p->rpg_g;
+  tuning[5] = p->col_tile;
+  tuning[6] = p->dfft_px;
+  tuning[7] = 0;
   return SSOCT_OK;
 }
 
@@ -794,11 +802,23 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   if (tuning[1] < 0 || tuning[1] > 65536 || tuning[2] < 0 || tuning[2] > 4096)
     return fail(SSOCT_EINVAL, "workgroup count out of range");
   if (tuning[3] != 0 && tuning[3] != 1) return fail(SSOCT_EINVAL, "order must be 0 or 1");
+  if (tuning[4] != 0 && tuning[4] != 2 && tuning[4] != 4 && tuning[4] != 8)
+    return fail(SSOCT_EINVAL, "rows per row group must be 0, 2, 4 or 8");
+  int ct[3];
+  col_tiles(p->N, ct);
+  if (tuning[5] != 0 && tuning[5] != ct[0] && (tuning[5] != ct[1] || !ct[1]) && (tuning[5] != ct[2] || !ct[2]))
+    return fail(SSOCT_EINVAL, "column tile width not available for this N");
+  if (tuning[6] != 0 && tuning[6] != 16 && tuning[6] != 32 && tuning[6] != 64)
+    return fail(SSOCT_EINVAL, "FFT depth pixels per workgroup must be 0, 16, 32 or 64");
+  if (tuning[7] != 0) return fail(SSOCT_EINVAL, "tuning[7] is reserved (0)");
   if (p->streaming && tuning[3] != p->order) return fail(SSOCT_EINVAL, "the order is fixed while a stream uses the plan");
   p->F_run = tuning[0];
   p->col_grid = tuning[1];
   p->depth_grid = tuning[2];
   p->order = tuning[3];
+  p->rpg_g = tuning[4];
+  p->col_tile = tuning[5] == ct[0] ? 0 : tuning[5];
+  p->dfft_px = tuning[6];
   return SSOCT_OK;
 }
 
@@ -830,36 +850,23 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
     *stage_b = best_b;
     return SSOCT_OK;
   };
-  // Fresnel stage: frames per chunk x persistent column workgroups
-  int bestF = p->F_run, bestC = p->col_grid, bestD = p->depth_grid;
-  float best = 1e30f, a, b;
-  const int Fs[3] = {p->F, p->F / 2, p->F / 4};
-  const int c0 = col_default_grid(p->N, p->cu);
-  const int Cs[3] = {0, 2 * c0, 4 * c0};
+  // Each search keeps the fastest candidate of its own stage (the Fresnel
+  // stage, or the depth transform) before the next search starts.
   int rc = SSOCT_OK;
-  for (int fi = 0; fi < 3 && rc == SSOCT_OK; ++fi) {
-    if (Fs[fi] < 1 || (fi > 0 && Fs[fi] == Fs[fi - 1])) continue;
-    for (int ci = 0; ci < 3 && rc == SSOCT_OK; ++ci) {
-      p->F_run = Fs[fi];
-      p->col_grid = Cs[ci];
+  float a, b;
+  auto search = [&](int* knob, const int* cand, int n, bool stage_b) {
+    int best_v = *knob;
+    float best = 1e30f;
+    for (int i = 0; i < n && rc == SSOCT_OK; ++i) {
+      *knob = cand[i];
       rc = measure(&a, &b);
-      if (rc == SSOCT_OK && a < best) best = a, bestF = Fs[fi], bestC = Cs[ci];
+      const float t = stage_b ? b : a;
+      if (rc == SSOCT_OK && t < best) best = t, best_v = cand[i];
     }
-  }
-  p->F_run = bestF;
-  p->col_grid = bestC;
-  // depth transform: default persistent grid or twice as many workgroups
-  const int d0 = depth_grid(p->T, p->N * p->N, p->cu, p->general);
-  const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};
-  best = 1e30f;
-  for (int di = 0; di < 2 && rc == SSOCT_OK; ++di) {
-    p->depth_grid = Ds[di];
-    rc = measure(&a, &b);
-    if (rc == SSOCT_OK && b < best) best = b, bestD = Ds[di];
-  }
-  p->depth_grid = bestD;
-  // evaluation order (FFT form without frame-dependent factors): whole render, both orders
-  if (rc == SSOCT_OK && p->df_allowed) {
+    *knob = best_v;
+  };
+  // evaluation order (FFT form without frame-dependent factors) first: the whole render, both orders
+  if (p->df_allowed) {
     float tot[2] = {1e30f, 1e30f};
     for (int o = 0; o < 2 && rc == SSOCT_OK; ++o) {
       p->order = o;
@@ -867,6 +874,41 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
       tot[o] = a + b;
     }
     p->order = tot[1] < tot[0] ? 1 : 0;
+  }
+  const bool df = p->depth_first();   // the Fresnel-stage timings below are of that order's 2-D transforms
+  // Fresnel stage: frames per chunk x column tile width x persistent column workgroups
+  int ct[3];
+  col_tiles(p->N, ct);
+  const int Fs[3] = {p->F, p->F / 2, p->F / 4};
+  int nF = 0, Fc[3];
+  for (int i = 0; i < 3; ++i)
+    if (Fs[i] >= 1 && (nF == 0 || Fs[i] != Fc[nF - 1]) && (!df || Fs[i] >= 2)) Fc[nF++] = Fs[i];
+  if (nF == 0) Fc[nF++] = p->F;
+  search(&p->F_run, Fc, nF, false);
+  if (!(p->flags & SSOCT_ANGULAR_SPECTRUM)) {
+    int tiles[3] = {0, ct[1], ct[2]}, nt = 1;
+    if (ct[1]) ++nt;
+    if (ct[2]) ++nt;
+    search(&p->col_tile, tiles, nt, false);
+  }
+  {
+    const int c0 = (p->flags & SSOCT_ANGULAR_SPECTRUM) ? p->as_col_grid0 : col_default_grid(p->N, p->cu, p->col_tile);
+    const int Cs[3] = {0, 2 * c0, 4 * c0};
+    search(&p->col_grid, Cs, 3, false);
+  }
+  if (df) {
+    const int Rs[4] = {0, 8, 4, 2};
+    search(&p->rpg_g, Rs, 4, false);
+  }
+  // depth transform: pixels per workgroup of the FFT form (frame order), or
+  // the persistent grid of the dense product
+  if ((p->flags & SSOCT_DEPTH_FFT) && !df) {
+    const int Ps[3] = {0, 16, 64};
+    search(&p->dfft_px, Ps, 3, true);
+  } else if (!(p->flags & (SSOCT_DEPTH_FFT | SSOCT_DEPTH_4STEP))) {
+    const int d0 = depth_grid(p->T, p->N * p->N, p->cu, p->general);
+    const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};
+    search(&p->depth_grid, Ds, 2, true);
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc != SSOCT_OK) return rc;

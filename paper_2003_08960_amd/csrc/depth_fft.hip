@@ -373,30 +373,43 @@ hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTa
   }
 }
 
+template <int T2, int DIR, int EPI, int PX>
+static hipError_t depth_fft_px(int P, const float2* H, const float2* wt, void* out, int shift, int grid,
+                               hipStream_t s) {
+  const int ntiles = (P + PX - 1) / PX;
+  const int g = grid > 0 && grid < ntiles ? grid : ntiles;
+  hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3(g), dim3(16 * PX), 0, s, H, wt, out, P, shift);
+  return hipGetLastError();
+}
+
+// px: pixels per workgroup of the forward store/|V| transform (16, 32 or 64,
+// a tuning choice; anything else takes SSOCT_DFFT_PX)
 template <int T2, int DIR, int EPI>
 static hipError_t depth_fft_t(int P, const float2* H, const float2* wt, void* out, int shift, float gs,
-                              double* partials, int grid, hipStream_t s) {
+                              double* partials, int grid, int px, hipStream_t s) {
   constexpr int PX = SSOCT_DFFT_PX;
-  const int ntiles = (P + PX - 1) / PX;
   if constexpr (EPI == EPI_GAMMA) {
+    const int ntiles = (P + PX - 1) / PX;
     hipLaunchKernelGGL((k_depth_fft_gamma<T2, PX>), dim3(ntiles), dim3(16 * PX), 0, s, H, wt,
                        static_cast<float2*>(out), P, gs, partials);
-  } else {
-    const int g = grid > 0 && grid < ntiles ? grid : ntiles;
-    hipLaunchKernelGGL((k_depth_fft<T2, DIR, EPI, PX>), dim3(g), dim3(16 * PX), 0, s, H, wt, out, P, shift);
+    return hipGetLastError();
+  } else if constexpr (DIR > 0) {
+    if (px == 16 && PX != 16) return depth_fft_px<T2, DIR, EPI, 16>(P, H, wt, out, shift, grid, s);
+    if (px == 64 && PX != 64) return depth_fft_px<T2, DIR, EPI, 64>(P, H, wt, out, shift, grid, s);
+    if (px == 32 && PX != 32) return depth_fft_px<T2, DIR, EPI, 32>(P, H, wt, out, shift, grid, s);
   }
-  return hipGetLastError();
+  return depth_fft_px<T2, DIR, EPI, PX>(P, H, wt, out, shift, grid, s);
 }
 
 template <int DIR, int EPI>
 static hipError_t depth_fft_d(int T, int P, const float2* H, const float2* wt, void* out, int shift, float gs,
-                              double* partials, int grid, hipStream_t s) {
+                              double* partials, int grid, int px, hipStream_t s) {
   switch (T) {
-    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
-    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
-    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
-    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
-    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, s);
+    case 16: return depth_fft_t<1, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, px, s);
+    case 32: return depth_fft_t<2, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, px, s);
+    case 64: return depth_fft_t<4, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, px, s);
+    case 128: return depth_fft_t<8, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, px, s);
+    case 256: return depth_fft_t<16, DIR, EPI>(P, H, wt, out, shift, gs, partials, grid, px, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -408,19 +421,19 @@ int depth_fft_blocks(int P) { return (P + SSOCT_DFFT_PX - 1) / SSOCT_DFFT_PX; }
 int depth_fft_grid(int cu_count) { return SSOCT_DFFT_WGCU > 0 ? SSOCT_DFFT_WGCU * cu_count : 0; }
 
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
-                            hipStream_t s, int shift, int gamma_exp, double* partials, int grid) {
+                            hipStream_t s, int shift, int gamma_exp, double* partials, int grid, int px) {
   if (P <= 0) return hipSuccess;
   if (shift < 0 || shift >= T) return hipErrorInvalidValue;
   if (dir > 0) {
-    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, shift, 1.f, nullptr, grid, s);
+    if (epi == EPI_ABS) return depth_fft_d<+1, EPI_ABS>(T, P, H, wt, out, shift, 1.f, nullptr, grid, px, s);
     if (epi == EPI_GAMMA) {
       if (!partials || shift != 0) return hipErrorInvalidValue;
-      return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, 0, s);
+      return depth_fft_d<+1, EPI_GAMMA>(T, P, H, wt, out, 0, ldexpf(1.0f, -gamma_exp), partials, 0, 0, s);
     }
-    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, 1.f, nullptr, grid, s);
+    return depth_fft_d<+1, EPI_STORE>(T, P, H, wt, out, shift, 1.f, nullptr, grid, px, s);
   }
   if (epi != EPI_STORE || shift != 0) return hipErrorInvalidValue;
-  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, 1.f, nullptr, grid, s);
+  return depth_fft_d<-1, EPI_STORE>(T, P, H, wt, out, 0, 1.f, nullptr, grid, 0, s);
 }
 
 // wt[k] = exp(-2 pi i k / T), k = 0..T-1, from FP64 (sincospi) rounded to FP32

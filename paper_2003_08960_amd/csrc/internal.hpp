@@ -95,11 +95,17 @@ hipError_t launch_depth_tables(int T, const double* kappa, float* a_f32, uint4* 
 hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const AxisTab* rows,
                            const AxisTab* cols, const float2* tw, const float* apoly,
                            const float2* outfac, float2* inter, hipStream_t s);
+// ctile: column tile width (0 = default; col_tiles lists the choices; the
+// Eq. 6 output phase takes the default)
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
-                           const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s);
+                           const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s,
+                           int ctile = 0);
 // Default persistent grid of the column passes (forward, adjoint, volume
-// output) on a device with `cu` compute units
-int col_default_grid(int N, int cu);
+// output) on a device with `cu` compute units, for column tile width ct (0 = default)
+int col_default_grid(int N, int cu, int ct = 0);
+// Column tile widths of the Fresnel column passes: out[0] the default, out[1]
+// and out[2] the narrower alternatives (0 where N has none)
+void col_tiles(int N, int* out);
 // Default persistent grid of the angular-spectrum column pass (a host query
 // of the kernel's residency: call it outside stream capture)
 int as_col_default_grid(int N, int cu);
@@ -119,11 +125,12 @@ hipError_t launch_as_stage(int N, int F, int t0, const uint16_t* frames, const f
 // frame f of the chunk at V + f fstride N^2.
 hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTab* rows, const AxisTab* cols,
                               const double* params, const float2* wt, float2* G, hipStream_t s);
+// rpg: rows per row group (8, 4 or 2; anything else picks by the launch size on `cu` CUs)
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
                              const AxisTab* cols0, const float2* tw, const float* apoly, const float2* outfac,
-                             float2* inter, int Fh, hipStream_t s);
+                             float2* inter, int Fh, int rpg, int cu, hipStream_t s);
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                             int fstride, int grid, hipStream_t s);
+                             int fstride, int grid, int ctile, hipStream_t s);
 
 // Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
 // into `inter`, then row DFT^- fused with the recomputed row input and the
@@ -151,13 +158,14 @@ int depth_grid(int T, int P, int cu_count, bool general = false);
 // writes Gamma = 4 |V 2^-gamma_exp|^2 V 2^-gamma_exp and one FP64 partial of
 // sum |V|^4 per workgroup, depth_fft_blocks(P) of them).  wt: exp(-2 pi i k/T).
 // grid: workgroups of the EPI_STORE / EPI_ABS kernels walking the tiles
-// (0 = one per tile; depth_fft_grid(cu) gives the tuned value).
+// (0 = one per tile; depth_fft_grid(cu) gives the tuned value); px: pixels per
+// workgroup of the forward EPI_STORE / EPI_ABS kernels (16, 32 or 64; 0 = default).
 bool depth_fft_supported(int T);
 int depth_fft_blocks(int P);
 int depth_fft_grid(int cu_count);
 hipError_t launch_depth_fft(int T, int P, int dir, int epi, const float2* H, const float2* wt, void* out,
                             hipStream_t s, int shift = 0, int gamma_exp = 0, double* partials = nullptr,
-                            int grid = 0);
+                            int grid = 0, int px = 0);
 hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 
 // Depth transform as a two-factor (16 x T/16) DFT on MFMA, forward only, in

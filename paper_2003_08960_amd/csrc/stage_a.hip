@@ -84,16 +84,28 @@ struct ColCfg {
   static constexpr int C = C1 * G > 1024 ? 1024 / G : C1;
   static constexpr int THREADS = C * G;
 };
-// LDS of the column pass: the exchange buffer of C columns, plus the twiddle
-// table where the two fit in one CU's 160 KB (every N <= 1024)
+// Narrower tiles (C/2 and C/4 adjacent columns, for N >= 512) are tuning
+// alternatives of the Fresnel column passes: fewer threads and less LDS per
+// workgroup, so more workgroups per CU, at the price of shorter row segments.
 template <int N>
-struct ColLds {
-  static constexpr int XB = FFTShape<N>::LDS * ColCfg<N>::C;
+struct ColTiles {
+  static constexpr int C = ColCfg<N>::C;
+  static constexpr bool ALT = N >= 512 && C >= 4;
+  static constexpr int C2 = ALT ? C / 2 : C;
+  static constexpr int C4 = ALT ? C / 4 : C;
+};
+// LDS of the column pass: the exchange buffer of CT columns, plus the twiddle
+// table where the two fit in one CU's 160 KB (every N <= 1024)
+template <int N, int CT>
+struct ColLdsT {
+  static constexpr int XB = FFTShape<N>::LDS * CT;
   static constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
   static constexpr bool TWL = SSOCT_COL_TWL && (XB + TWN) * 8 <= 163840;
   static constexpr bool PF = TWL || SSOCT_COL_PREFETCH;    // next tile prefetched into registers
   static constexpr int BYTES = (XB + (TWL ? TWN : 1)) * 8;
 };
+template <int N>
+using ColLds = ColLdsT<N, ColCfg<N>::C>;
 
 // Source rows y0 and y0 + 1 of Eq. 5 for one output row: thread j of a group
 // holds columns [s N/4 + 4 j, s N/4 + 4 j + 4) for s = 0..3, so every load
@@ -274,7 +286,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
 // into chunk frame Fh + f.  The column pass turns these into V[q] and
 // V[T - q] (Eq. 6 is linear and its chirp does not depend on the frame when
 // lambda_1 is used for every frame and no per-frame phase is applied).
-template <int N, bool ABERR, bool EQ6>
+template <int N, bool ABERR, bool EQ6, int RPG>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g(
     const float2* __restrict__ Gq, int qa, int T, const AxisTab* __restrict__ rows0,
     const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float* __restrict__ apoly,
@@ -282,16 +294,19 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
   using S = FFTShape<N>;
   using R = RowCfg<N>;
   constexpr int G = S::G;
-  __shared__ AxisTab ctab[N];
+  // column factors only (contiguous 8-byte entries: a 16-byte table entry read for its factor
+  // alone would put two lanes on one LDS bank)
+  __shared__ float2 cfac[N];
   __shared__ float2 xbuf[R::GR][RowLds<N>::XS];
-  __shared__ float2 rfac_s[R::ROWS];   // row factors of this workgroup's rows
+  constexpr int ROWS = R::GR * RPG;    // rows per workgroup
+  __shared__ float2 rfac_s[ROWS];      // row factors of this workgroup's rows
   constexpr bool OFS = EQ6 && N <= 1024;  // output factor of Eq. 6 in LDS, as in k_row_pass
   __shared__ float2 ofac_s[OFS ? N : 1];
   const int g = threadIdx.x / G, j = threadIdx.x % G;
   const int f = blockIdx.y;
   const int q = qa + f;
   const bool both = q >= 1 && 2 * q < T;
-  const int m0 = blockIdx.x * R::ROWS + g * R::RPG;
+  const int m0 = blockIdx.x * ROWS + g * RPG;
   float2 nxt[16];
   {
     const float2* src = Gq + ((size_t)q * N + m0) * N;
@@ -301,8 +316,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
   // as in k_row_pass: twiddles in registers, per-row table entries in LDS,
   // and no load outstanding when the loop is entered
   const TwRegs<N> twr = load_tw_regs<N>(tw, j);
-  stage_ctab<N>(ctab, cols0);
-  for (int i = threadIdx.x; i < R::ROWS; i += R::THREADS) rfac_s[i] = rows0[blockIdx.x * R::ROWS + i].fac;
+  for (int i = threadIdx.x; i < N; i += R::THREADS) cfac[i] = cols0[i].fac;
+  for (int i = threadIdx.x; i < ROWS; i += R::THREADS) rfac_s[i] = rows0[blockIdx.x * ROWS + i].fac;
   if constexpr (OFS) {
     for (int i = threadIdx.x; i < N; i += R::THREADS) ofac_s[i] = outfac[i];
   }
@@ -310,26 +325,26 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unchanged
   __syncthreads();  // column table and row factors visible
 #pragma unroll 1
-  for (int i = 0; i < R::RPG; ++i) {
+  for (int i = 0; i < RPG; ++i) {
     const int m = m0 + i;
     float2 gv[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) gv[k] = nxt[k];
     const ARow ar = an;
-    if (i + 1 < R::RPG) {  // prefetch the next row of this group
+    if (i + 1 < RPG) {  // prefetch the next row of this group
       const float2* src = Gq + ((size_t)q * N + m + 1) * N;
 #pragma unroll
       for (int k = 0; k < 16; ++k) nxt[k] = ld_once<true>(src + j + k * G);
       an = load_arow<ABERR>(apoly, m + 1);
     }
-    const float2 rowfac = rfac_s[g * R::RPG + i];
+    const float2 rowfac = rfac_s[g * RPG + i];
 #pragma unroll 1
     for (int h = 0; h < (both ? 2 : 1); ++h) {
       float2 v[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int n = j + k * G;
-        float2 fac = cmul(ctab[n].fac, rowfac);
+        float2 fac = cmul(cfac[n], rowfac);
         if constexpr (ABERR) fac = cmul(fac, aberr_factor<N>(ar, n));
         v[k] = cmul(fac, h == 0 ? gv[k] : cconj(gv[k]));
       }
@@ -546,25 +561,25 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2*
 // walked persistently.  src, dst: frame 0 of this launch; frame f at + f N^2.
 // DIR = +1 writes H in format FMT (and the Eq. 6 output phase when EQ6);
 // DIR = -1 writes complex64.
-template <int N, int DIR, int FMT, bool EQ6>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* __restrict__ src,
-                                                                 const float2* __restrict__ tw,
-                                                                 const float2* __restrict__ outfac,
-                                                                 void* __restrict__ dst, float scale, int ntiles,
-                                                                 int fstride) {
+template <int N, int DIR, int FMT, bool EQ6, int CT = ColCfg<N>::C>
+__global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* __restrict__ src,
+                                                                  const float2* __restrict__ tw,
+                                                                  const float2* __restrict__ outfac,
+                                                                  void* __restrict__ dst, float scale, int ntiles,
+                                                                  int fstride) {
   using S = FFTShape<N>;
   constexpr int G = S::G;
-  constexpr int C = ColCfg<N>::C;
+  constexpr int C = CT;
   constexpr int NCB = N / C;  // column blocks per frame
   // The twiddle table goes to LDS where the exchange buffer leaves room for
   // it (N <= 1024).  That frees the registers the twiddles would hold for a
   // prefetch of the next tile, which then loads while the current one is
   // transformed: one 1024-thread workgroup fills a CU, so without it the
   // CU's memory and ALUs take turns.
-  constexpr bool TWL = ColLds<N>::TWL;
-  constexpr bool PF = ColLds<N>::PF;
-  __shared__ float2 xbuf[ColLds<N>::XB];
-  __shared__ float2 twl[TWL ? ColLds<N>::TWN : 1];
+  constexpr bool TWL = ColLdsT<N, CT>::TWL;
+  constexpr bool PF = ColLdsT<N, CT>::PF;
+  __shared__ float2 xbuf[ColLdsT<N, CT>::XB];
+  __shared__ float2 twl[TWL ? ColLdsT<N, CT>::TWN : 1];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   float2 pf[16];
   auto issue = [&](int tile) {
@@ -576,7 +591,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void k_col_pass(const float2* _
   int tile = blockIdx.x;
   if (PF && tile < ntiles) issue(tile);
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += ColCfg<N>::THREADS) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += (CT * G)) twl[i] = tw[i];
     // the first tile has landed; the loop is entered with no load
     // outstanding, so waiting for a prefetched tile inside it leaves the
     // previous tile's stores in flight
@@ -727,12 +742,22 @@ static int col_grid(int ntiles, int req) {
   return ntiles < g ? ntiles : g;
 }
 
-template <int N>
-static int col_default_grid_n(int cu) {
+template <int N, int CT>
+static int col_default_grid_nt(int cu) {
   // with the tile prefetch: one resident round of workgroups, each walking
   // its tiles; without it, two rounds
-  constexpr int per_cu = 163840 / ColLds<N>::BYTES;
-  return ColLds<N>::PF ? cu * (per_cu > 0 ? per_cu : 1) : 512;
+  constexpr int per_lds = 163840 / ColLdsT<N, CT>::BYTES;
+  constexpr int per_thr = 2048 / (CT * FFTShape<N>::G);   // at most 32 waves per CU
+  constexpr int per_cu = per_lds < per_thr ? per_lds : per_thr;
+  return ColLdsT<N, CT>::PF ? cu * (per_cu > 0 ? per_cu : 1) : 512;
+}
+
+template <int N>
+static int col_default_grid_n(int cu, int ct) {
+  using K = ColTiles<N>;
+  if (ct == K::C2 && K::ALT) return col_default_grid_nt<N, K::C2>(cu);
+  if (ct == K::C4 && K::ALT) return col_default_grid_nt<N, K::C4>(cu);
+  return col_default_grid_nt<N, K::C>(cu);
 }
 
 // Default persistent grid of the transfer-function column pass: one resident
@@ -760,36 +785,67 @@ int as_col_default_grid(int N, int cu) {
   }
 }
 
-int col_default_grid(int N, int cu) {
+int col_default_grid(int N, int cu, int ct) {
   switch (N) {
-    case 16: return col_default_grid_n<16>(cu);
-    case 32: return col_default_grid_n<32>(cu);
-    case 64: return col_default_grid_n<64>(cu);
-    case 128: return col_default_grid_n<128>(cu);
-    case 256: return col_default_grid_n<256>(cu);
-    case 512: return col_default_grid_n<512>(cu);
-    case 1024: return col_default_grid_n<1024>(cu);
-    default: return col_default_grid_n<2048>(cu);
+    case 16: return col_default_grid_n<16>(cu, ct);
+    case 32: return col_default_grid_n<32>(cu, ct);
+    case 64: return col_default_grid_n<64>(cu, ct);
+    case 128: return col_default_grid_n<128>(cu, ct);
+    case 256: return col_default_grid_n<256>(cu, ct);
+    case 512: return col_default_grid_n<512>(cu, ct);
+    case 1024: return col_default_grid_n<1024>(cu, ct);
+    default: return col_default_grid_n<2048>(cu, ct);
   }
 }
 
 template <int N>
-static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                             int fmt, int sigma, int req_grid, hipStream_t s) {
-  using C = ColCfg<N>;
-  const int ntiles = F * (N / C::C);
-  dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
-  const float scale = ldexpf(1.0f, -sigma);
-  char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
-  const bool eq6 = outfac != nullptr;
-#define SSOCT_COL(FMT, E)                                                                                  \
-  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E>), grid, block, 0, s, inter, tw, outfac, (void*)dst, scale, \
-                     ntiles, 1)
-  if (fmt == HF_F32) { if (eq6) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
-  else if (fmt == HF_F16) { if (eq6) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
-  else { if (eq6) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
+static void col_tiles_n(int* out) {
+  using K = ColTiles<N>;
+  out[0] = K::C;
+  out[1] = K::ALT ? K::C2 : 0;
+  out[2] = K::ALT ? K::C4 : 0;
+}
+
+void col_tiles(int N, int* out) {
+  switch (N) {
+    case 16: return col_tiles_n<16>(out);
+    case 32: return col_tiles_n<32>(out);
+    case 64: return col_tiles_n<64>(out);
+    case 128: return col_tiles_n<128>(out);
+    case 256: return col_tiles_n<256>(out);
+    case 512: return col_tiles_n<512>(out);
+    case 1024: return col_tiles_n<1024>(out);
+    default: return col_tiles_n<2048>(out);
+  }
+}
+
+// forward column pass of tile width CT (with the Eq. 6 output phase when outfac is given)
+template <int N, int CT>
+static hipError_t col_pass_nt(int F, const float2* inter, const float2* tw, const float2* outfac, void* dst, int fmt,
+                              float scale, int req_grid, int fstride, hipStream_t s) {
+  const int ntiles = F * (N / CT);
+  dim3 grid(col_grid(ntiles, req_grid)), block(CT * FFTShape<N>::G);
+#define SSOCT_COL(FMT, E)                                                                                        \
+  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E, CT>), grid, block, 0, s, inter, tw, outfac, dst, scale, ntiles, \
+                     fstride)
+  if (fmt == HF_F32) { if (outfac) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
+  else if (fmt == HF_F16) { if (outfac) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
+  else { if (outfac) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
 #undef SSOCT_COL
   return hipGetLastError();
+}
+
+// ctile: column tile width (the default ColCfg<N>::C, or one of the narrower
+// ColTiles alternatives)
+template <int N>
+static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
+                             int fmt, int sigma, int req_grid, int ctile, hipStream_t s) {
+  using K = ColTiles<N>;
+  const float scale = ldexpf(1.0f, -sigma);
+  char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
+  if (K::ALT && ctile == K::C2) return col_pass_nt<N, K::C2>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
+  if (K::ALT && ctile == K::C4) return col_pass_nt<N, K::C4>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
+  return col_pass_nt<N, K::C>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
 }
 
 template <int N>
@@ -830,14 +886,14 @@ static hipError_t row_pass_adj_n(int F, int t0, const uint16_t* frames, const Ax
     default: return hipErrorInvalidValue; \
   }
 
-template <int N>
-static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const AxisTab* rows0, const AxisTab* cols0,
-                               const float2* tw, const float* apoly, const float2* outfac, float2* inter, int Fh,
-                               hipStream_t s) {
+template <int N, int RPG>
+static hipError_t row_pass_g_rpg(int nb, int qa, int T, const float2* G, const AxisTab* rows0, const AxisTab* cols0,
+                                 const float2* tw, const float* apoly, const float2* outfac, float2* inter, int Fh,
+                                 hipStream_t s) {
   using R = RowCfg<N>;
-  dim3 grid(N / R::ROWS, nb), block(R::THREADS);
-#define SSOCT_RG(A, E)                                                                                            \
-  hipLaunchKernelGGL((k_row_pass_g<N, A, E>), grid, block, 0, s, G, qa, T, rows0, cols0, tw, apoly, outfac, inter, \
+  dim3 grid(N / (R::GR * RPG), nb), block(R::THREADS);
+#define SSOCT_RG(A, E)                                                                                                \
+  hipLaunchKernelGGL((k_row_pass_g<N, A, E, RPG>), grid, block, 0, s, G, qa, T, rows0, cols0, tw, apoly, outfac, inter, \
                      Fh)
   if (apoly && outfac) SSOCT_RG(true, true);
   else if (apoly) SSOCT_RG(true, false);
@@ -847,32 +903,52 @@ static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const Axi
   return hipGetLastError();
 }
 
+// Rows per group of the bin-pair row pass: `rpg` if it is one of 8, 4, 2 (and
+// leaves at least one row group per workgroup's share), else the largest of
+// them that still gives two workgroups per CU for the launch's nb bins (a
+// chunk of bins has half the frames of a Fresnel chunk, so its row pass
+// launches half as many workgroups at the rows per group of k_row_pass).
+template <int N>
+static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const AxisTab* rows0, const AxisTab* cols0,
+                               const float2* tw, const float* apoly, const float2* outfac, float2* inter, int Fh,
+                               int rpg, int cu, hipStream_t s) {
+  using R = RowCfg<N>;
+  constexpr int MAXR = N / R::GR;   // rows per group cannot exceed the rows of one workgroup's share
+  if (rpg != 8 && rpg != 4 && rpg != 2) {
+    rpg = 2;
+    for (int c = 8; c > 2; c /= 2)
+      if ((N / (R::GR * c)) * nb >= 2 * cu) {
+        rpg = c;
+        break;
+      }
+  }
+  if (rpg > MAXR) rpg = MAXR;
+  if (rpg >= 8 && MAXR >= 8) return row_pass_g_rpg<N, (MAXR >= 8 ? 8 : 1)>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s);
+  if (rpg >= 4 && MAXR >= 4) return row_pass_g_rpg<N, (MAXR >= 4 ? 4 : 1)>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s);
+  if (rpg >= 2 && MAXR >= 2) return row_pass_g_rpg<N, (MAXR >= 2 ? 2 : 1)>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s);
+  return row_pass_g_rpg<N, 1>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s);
+}
+
 template <int N>
 static hipError_t col_pass_v_n(int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                               int fstride, int req_grid, hipStream_t s) {
-  using C = ColCfg<N>;
-  const int ntiles = F * (N / C::C);
-  dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
-  if (outfac)
-    hipLaunchKernelGGL((k_col_pass<N, +1, HF_F32, true>), grid, block, 0, s, inter, tw, outfac, (void*)V, 1.0f,
-                       ntiles, fstride);
-  else
-    hipLaunchKernelGGL((k_col_pass<N, +1, HF_F32, false>), grid, block, 0, s, inter, tw, outfac, (void*)V, 1.0f,
-                       ntiles, fstride);
-  return hipGetLastError();
+                               int fstride, int req_grid, int ctile, hipStream_t s) {
+  using K = ColTiles<N>;
+  if (K::ALT && ctile == K::C2) return col_pass_nt<N, K::C2>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
+  if (K::ALT && ctile == K::C4) return col_pass_nt<N, K::C4>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
+  return col_pass_nt<N, K::C>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
 }
 
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
                              const AxisTab* cols0, const float2* tw, const float* apoly, const float2* outfac,
-                             float2* inter, int Fh, hipStream_t s) {
-#define CALL(n) row_pass_g_n<n>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s)
+                             float2* inter, int Fh, int rpg, int cu, hipStream_t s) {
+#define CALL(n) row_pass_g_n<n>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, rpg, cu, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
 
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                             int fstride, int grid, hipStream_t s) {
-#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, s)
+                             int fstride, int grid, int ctile, hipStream_t s) {
+#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, ctile, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
@@ -911,8 +987,8 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
 }
 
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                           int fmt, int sigma, int grid, hipStream_t s) {
-#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, grid, s)
+                           int fmt, int sigma, int grid, hipStream_t s, int ctile) {
+#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, grid, ctile, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }

@@ -131,7 +131,7 @@ def test_stream_and_tuning_entry_points_reject_null(lib):
     c = (ctypes.c_uint64 * 4)()
     assert lib.ssoct_stream_stats(None, c) == native.EINVAL
     assert lib.ssoct_stream_destroy(None) == native.OK
-    t = (ctypes.c_int * 4)()
+    t = (ctypes.c_int * native.TUNING_LEN)()
     assert lib.ssoct_plan_get_tuning(None, t) == native.EINVAL
     assert lib.ssoct_plan_set_tuning(None, t) == native.EINVAL
     assert lib.ssoct_plan_tune(None, None, lam, 1e-5, 0.1, None, None, None, 0, None, t) == native.EINVAL

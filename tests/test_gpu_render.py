@@ -480,3 +480,36 @@ def test_five_argument_render(gpu_lib, tiny):
     api.render_release()
     assert torch.equal(api.render(fr, sw.lam, sw.pitch, sw.z), V)   # a fresh default plan after the release
     api.render_release()
+
+
+# ---------------------------------------------------------------- tuning alternatives (tiles, row groups)
+
+def test_tiles_and_row_groups_change_speed_not_results(gpu_lib):
+    """The tuner's tile choices at N = 1024: column tile widths 16 / 8 / 4, rows per row group of the
+    depth-first order 2 / 4 / 8 and FFT depth workgroups of 16 / 32 / 64 pixels give bit-identical
+    volumes in both evaluation orders (and in the split H format); the tuner's pick too."""
+    from paper_2003_08960_amd.api import Plan
+    T, N = 16, 1024
+    frames, lam = random_case(T, N, seed=404)
+    fr = torch.from_numpy(frames).cuda()
+    print(f"\n[gpu] tiles and row groups T={T} N={N}", flush=True)
+    ref = O.render(frames, lam, 12e-6, 0.3)
+    for precision in ("fp32_fft", "bf16_split"):
+        for order in ((0, 1) if precision == "fp32_fft" else (0,)):
+            plan = Plan(T, N, precision=precision)
+            plan.set_tuning(plan.get_tuning()[:3] + [order])
+            V0 = plan.render(fr, lam, 12e-6, 0.3).clone()
+            assert rel_l2(V0.cpu().numpy(), ref) <= (FP32_BAR if precision == "fp32_fft" else SPLIT_BAR)
+            for rpg in (0, 2, 4, 8):
+                for tile in (0, 8, 4):
+                    for px in (0, 16, 64):
+                        plan.set_tuning([T, 0, 0, order, rpg, tile, px])
+                        assert torch.equal(plan.render(fr, lam, 12e-6, 0.3), V0), (precision, order, rpg, tile, px)
+            choice = plan.tune(fr, lam, 12e-6, 0.3)
+            print(precision, order, "tuned", choice)
+            assert len(choice) == native.TUNING_LEN
+            if choice[3] == order:
+                assert torch.equal(plan.render(fr, lam, 12e-6, 0.3), V0)
+            else:
+                assert rel_l2(plan.render(fr, lam, 12e-6, 0.3).cpu().numpy(), ref) <= FP32_BAR
+            plan.close()

@@ -156,7 +156,7 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
     V0 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     cache = str(tmp_path / "tuning.json")
     choice = plan.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache)
-    assert 1 <= choice[0] <= T and len(choice) == 4
+    assert 1 <= choice[0] <= T and len(choice) == native.TUNING_LEN
     V1 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     assert torch.equal(V0, V1)
     for tuning in ([1, 0, 0], [3, 7, 5], [T, 1024, 64]):
@@ -168,6 +168,9 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
         plan.set_tuning([0, 0, 0])
     with pytest.raises(native.SsoctError):
         plan.set_tuning([1, 0, 0, 2])
+    for bad in ([1, 0, 0, 0, 3], [1, 0, 0, 0, 0, 5], [1, 0, 0, 0, 0, 0, 48], [1, 0, 0, 0, 0, 0, 0, 1]):
+        with pytest.raises(native.SsoctError):
+            plan.set_tuning(bad)
 
 
 def test_chunkwise_fresnel_with_ragged_chunks_and_discarded_sweep(gpu_lib, sweeps):
