@@ -240,16 +240,24 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
   constexpr int NITEM = T * NCH;              // (frame, chunk) staging items
   constexpr int NI = (NITEM + NT - 1) / NT;
   constexpr int STRIDE = ParamLayout::PER_FRAME;   // doubles per frame in the parameter block (s_t first)
-  __shared__ float2 lds[T * PX];              // transposition [q2][t1][px]; the staged rows alias it
-  __shared__ float2 tws[T];                   // exp(-2 pi i k / T)
-  __shared__ double fs[T], fp[T];             // per frame: s_t and the source position of the tile's first column
-  __shared__ int frow[T], fxs[T];             // per frame: source row y0 and the window start
-  __shared__ float ffy[T];                    // per frame: y weight
+  // one block in declaration order: the per-frame values first, so that
+  // their addresses fit the 16-bit offset field of the LDS instructions
+  struct Lds {
+    double fs[T];             // per frame: s_t
+    double fp[T];             // per frame: position of the tile's first column, relative to the window start
+    int frow[T];              // per frame: source row y0
+    int fxs[T];               // per frame: window start (first column rounded down to 8 samples)
+    float ffy[T];             // per frame: y weight
+    float2 tws[T];            // exp(-2 pi i k / T)
+    float2 lds[T * PX];       // transposition [q2][t1][px]; the staged rows alias it
+  };
+  __shared__ Lds sm;
   static_assert(T * WS * 4 <= T * PX * 8, "staged rows must fit the transposition buffer");
-  float* ya = reinterpret_cast<float*>(lds);  // [T][WS]
+  float* ya = reinterpret_cast<float*>(sm.lds);  // [T][WS]
   const int tid = threadIdx.x;
   const int px = tid % PX, r = tid / PX;
-  const size_t P = (size_t)N * N;
+  // element offsets fit 32 bits (T N^2 <= 2^30 for the T this form takes)
+  const uint32_t P = (uint32_t)N * (uint32_t)N;
   // contiguous runs of tiles per XCD (workgroups are dispatched round-robin
   // over the XCDs), so that neighbouring rows, which share source rows, meet in one L2
   const int tile = (gridDim.x % SSOCT_XCDS == 0)
@@ -265,31 +273,35 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
     float fy, fx;
     src_pos(m, N, st, y0, fy);
     src_pos(n0, N, st, x0, fx);
-    fs[t] = st;
-    fp[t] = __dadd_rn(__dmul_rn((double)c0, st), (double)half);
-    frow[t] = y0;
-    ffy[t] = fy;
-    fxs[t] = x0 & ~7;
-    tws[t] = wt[t];
+    // the window start xs is an integer within 8 samples of N/2 + c0 s_t: the
+    // difference is exact in FP64, so positions are taken relative to it
+    const int xs = x0 & ~7;
+    sm.fs[t] = st;
+    sm.fp[t] = __dadd_rn(__dmul_rn((double)c0, st), (double)half) - (double)xs;
+    sm.frow[t] = y0;
+    sm.ffy[t] = fy;
+    sm.fxs[t] = xs;
+    sm.tws[t] = wt[t];
   }
   __syncthreads();
-  // every staging load is in flight before the first interpolation
+  // every staging load is in flight before the first interpolation.  A chunk
+  // starting at or past column N (x and N are multiples of 8) only feeds the
+  // right tap of the last column, whose weight is exactly 0: it is read from
+  // the frame's last chunk instead, any finite value giving the same sample.
   uint4 ra[NI], rb[NI];
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
     const int i = tid + k * NT;
-    ra[k] = make_uint4(0u, 0u, 0u, 0u);
-    rb[k] = ra[k];
     if (i < NITEM) {
       const int t = i / NCH, c = i - (i / NCH) * NCH;
-      const int x = fxs[t] + 8 * c;
-      if (x < N) {   // x and N are multiples of 8: the chunk is whole
-        const int y0 = frow[t];
-        const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
-        const uint16_t* col = frames + (size_t)t * P + x;
-        ra[k] = *reinterpret_cast<const uint4*>(col + (size_t)y0 * N);
-        rb[k] = *reinterpret_cast<const uint4*>(col + (size_t)y1 * N);
-      }
+      int x = sm.fxs[t] + 8 * c;
+      x = x < N ? x : N - 8;
+      const int y0 = sm.frow[t];
+      const int y1 = y0 + 1 < N ? y0 + 1 : N - 1;
+      const uint32_t row0 = ((uint32_t)t * (uint32_t)N + (uint32_t)y0) * (uint32_t)N + (uint32_t)x;
+      const uint32_t row1 = row0 + (uint32_t)(y1 - y0) * (uint32_t)N;
+      ra[k] = *reinterpret_cast<const uint4*>(frames + row0);
+      rb[k] = *reinterpret_cast<const uint4*>(frames + row1);
     }
   }
 #pragma unroll
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
     const int i = tid + k * NT;
     if (i < NITEM) {
       const int t = i / NCH, c = i - (i / NCH) * NCH;
-      const float fy = ffy[t];
+      const float fy = sm.ffy[t];
       const uint32_t wa[4] = {ra[k].x, ra[k].y, ra[k].z, ra[k].w};
       const uint32_t wb[4] = {rb[k].x, rb[k].y, rb[k].z, rb[k].w};
       float o[8];
@@ -315,31 +327,35 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
   }
   __syncthreads();
   float2 a[T2];
+  const double dpx = (double)px;
 #pragma unroll
   for (int t2 = 0; t2 < T2; ++t2) {
     const int t = r + 16 * t2;
-    // N/2 + (c0 + px) s_t = fp[t] + px s_t up to FP64 rounding; column and weight as in the tables
-    const double Pd = fma((double)px, fs[t], fp[t]);
+    // N/2 + (c0 + px) s_t - xs = fp[t] + px s_t up to FP64 rounding; column and weight as in the tables
+    const double Pd = fma(dpx, sm.fs[t], sm.fp[t]);
     const double p0 = floor(Pd);
     const float fx = (float)(Pd - p0);
-    const float* w = ya + t * WS + ((int)p0 - fxs[t]);
+    const float* w = ya + t * WS + (int)p0;
     const float y0 = w[0], y1 = w[1];
     a[t2] = make_float2(y0 + fx * (y1 - y0), 0.f);
   }
   __syncthreads();   // staged rows read before the transposition buffer is written
   if constexpr (T2 > 1) dft_small<T2, -1>(a);
+  float2* tr = sm.lds + r * PX + px;
 #pragma unroll
-  for (int q2 = 0; q2 < T2; ++q2) lds[(q2 * 16 + r) * PX + px] = q2 == 0 ? a[q2] : cmul(a[q2], tws[(q2 * r) & (T - 1)]);
+  for (int q2 = 0; q2 < T2; ++q2) tr[q2 * 16 * PX] = q2 == 0 ? a[q2] : cmul(a[q2], sm.tws[(q2 * r) & (T - 1)]);
   __syncthreads();
   if (r >= T2) return;
   float2 b[16];
+  const float2* tb = sm.lds + r * 16 * PX + px;
 #pragma unroll
-  for (int t1 = 0; t1 < 16; ++t1) b[t1] = lds[(r * 16 + t1) * PX + px];
+  for (int t1 = 0; t1 < 16; ++t1) b[t1] = tb[t1 * PX];
   dft16<-1>(b);
+  float2* gout = G + ((uint32_t)r * P + (uint32_t)(pix0 + px));
 #pragma unroll
   for (int q1 = 0; q1 < 16; ++q1) {
     const int q = r + T2 * q1;
-    if (2 * q <= T) st_once<SSOCT_DFFT_NT>(G + (size_t)q * P + pix0 + px, b[q1]);
+    if (2 * q <= T) st_once<SSOCT_DFFT_NT>(gout + (uint32_t)(T2 * q1) * P, b[q1]);
   }
 }
 
