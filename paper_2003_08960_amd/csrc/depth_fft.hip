@@ -225,8 +225,16 @@ __device__ __forceinline__ void src_pos(int i, int N, double s, int& i0, float& 
 // a 32-position tile at frame t starts at the first position's source
 // column rounded down to 8 samples and spans 40 samples: the last position's
 // right tap lies at most 7 + 31 + 1 samples past the start (s_t <= 1).
-// Chunks starting at or past column N are zero (only the right tap of the
-// last column reads there, with weight 0).
+//
+// The frames are real, so the transform is Hermitian in q and only bins
+// 0..T/2 are kept; the same holds inside the split.  Stage A of thread t1 is
+// a real T2-point DFT whose bins T2 - q2 are the conjugates of bins q2, so
+// only rows q2 = 0..T2/2 are twiddled and cross LDS, and stage B runs the
+// 16-point DFT of those T2/2 + 1 rows only.  Row q2 (0 < q2 < T2/2) yields
+// bins q2 + T2 q1 directly for q1 <= 7 and, through
+//   V[T - q] = conj V[q],  T - (q2 + T2 q1) = (T2 - q2) + T2 (15 - q1),
+// bins (T2 - q2) + T2 (15 - q1) for q1 >= 8; row 0 yields bins T2 q1 for
+// q1 <= 8 and row T2/2 bins T2/2 + T2 q1 for q1 <= 7.
 template <int T2>
 __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restrict__ frames,
                                                          const double* __restrict__ params,
@@ -240,6 +248,8 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
   constexpr int NITEM = T * NCH;              // (frame, chunk) staging items
   constexpr int NI = (NITEM + NT - 1) / NT;
   constexpr int STRIDE = ParamLayout::PER_FRAME;   // doubles per frame in the parameter block (s_t first)
+  constexpr int NROW = T2 / 2 + 1;            // rows of stage A that cross LDS
+  constexpr int LDSN = (T * WS / 2 > NROW * 16 * PX) ? T * WS / 2 : NROW * 16 * PX;
   // one block in declaration order: the per-frame values first, so that
   // their addresses fit the 16-bit offset field of the LDS instructions
   struct Lds {
@@ -249,10 +259,9 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
     int fxs[T];               // per frame: window start (first column rounded down to 8 samples)
     float ffy[T];             // per frame: y weight
     float2 tws[T];            // exp(-2 pi i k / T)
-    float2 lds[T * PX];       // transposition [q2][t1][px]; the staged rows alias it
+    float2 lds[LDSN];         // transposition [q2][t1][px], rows q2 = 0..T2/2; the staged rows alias it
   };
   __shared__ Lds sm;
-  static_assert(T * WS * 4 <= T * PX * 8, "staged rows must fit the transposition buffer");
   float* ya = reinterpret_cast<float*>(sm.lds);  // [T][WS]
   const int tid = threadIdx.x;
   const int px = tid % PX, r = tid / PX;
@@ -343,19 +352,28 @@ __global__ __launch_bounds__(512) void k_rescale_dft_win(const uint16_t* __restr
   if constexpr (T2 > 1) dft_small<T2, -1>(a);
   float2* tr = sm.lds + r * PX + px;
 #pragma unroll
-  for (int q2 = 0; q2 < T2; ++q2) tr[q2 * 16 * PX] = q2 == 0 ? a[q2] : cmul(a[q2], sm.tws[(q2 * r) & (T - 1)]);
+  for (int q2 = 0; q2 < NROW; ++q2)
+    tr[q2 * 16 * PX] = q2 == 0 ? make_float2(a[0].x, 0.f) : cmul(a[q2], sm.tws[(q2 * r) & (T - 1)]);
   __syncthreads();
-  if (r >= T2) return;
+  if (r >= NROW) return;
   float2 b[16];
   const float2* tb = sm.lds + r * 16 * PX + px;
 #pragma unroll
   for (int t1 = 0; t1 < 16; ++t1) b[t1] = tb[t1 * PX];
   dft16<-1>(b);
-  float2* gout = G + ((uint32_t)r * P + (uint32_t)(pix0 + px));
+  // row r: bins r + T2 q1 (q1 <= 7, and q1 = 8 on row 0); rows strictly
+  // between 0 and T2/2 also give the conjugate bins (T2 - r) + T2 (15 - q1)
+  const bool mirror = r > 0 && 2 * r < T2;
+  float2* gdir = G + ((uint32_t)r * P + (uint32_t)(pix0 + px));
+  float2* gmir = G + ((uint32_t)(T2 - r) * P + (uint32_t)(pix0 + px));
 #pragma unroll
   for (int q1 = 0; q1 < 16; ++q1) {
-    const int q = r + T2 * q1;
-    if (2 * q <= T) st_once<SSOCT_DFFT_NT>(gout + (uint32_t)(T2 * q1) * P, b[q1]);
+    if (q1 < 8) {
+      st_once<SSOCT_DFFT_NT>(gdir + (uint32_t)(T2 * q1) * P, b[q1]);
+    } else {
+      if (q1 == 8 && r == 0) st_once<SSOCT_DFFT_NT>(gdir + (uint32_t)(T2 * 8) * P, b[8]);
+      if (mirror) st_once<SSOCT_DFFT_NT>(gmir + (uint32_t)(T2 * (15 - q1)) * P, cconj(b[q1]));
+    }
   }
 }
 
