@@ -239,8 +239,8 @@ def roofline(rec, form, T, N):
         nb = T // 2 + 1
         fh = max(rec["tuning"]["frames_per_chunk"] // 2, 1)
         nch = -(-nb // fh)
-        # column launches: one per chunk for bins q, one more for the partners T - q (0 < q < T/2)
-        ncol = sum(1 + (min(qa + fh, (T + 1) // 2) > max(qa, 1)) for qa in range(0, nb, fh))
+        # column launches: one per chunk (bins q and, in the same launch, their partners T - q)
+        ncol = nch
         ks = {
             "k_rescale_dft_win": (st["depth"], 1, (2 * T + 8 * nb) * N * N, 0.0),
             "k_row_pass_g": (sp["row_pass"] * scale, nch, (8 * nb + 8 * T) * N * N, 0.0),

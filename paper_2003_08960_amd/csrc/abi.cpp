@@ -368,13 +368,13 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
     const int n = nb - qa < fh ? nb - qa : fh;
     SSOCT_HIP(launch_row_pass_g(N, n, qa, T, G, p->rows, p->cols, p->tw, ab, p->outfac, inter, fh, p->rpg_g, p->cu, s));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c], s));
+    // one launch: V[q] for the chunk's bins, then V[T - q] for those with a partner
     const int cg = col_grid_of(p, p->col_tile);
-    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, cg, p->col_tile, s));
     const int ca = qa > 1 ? qa : 1;
     const int cb = qa + n < nconj ? qa + n : nconj;
-    if (cb > ca)
-      SSOCT_HIP(launch_col_pass_v(N, cb - ca, inter + (size_t)(fh + ca - qa) * P, p->tw, p->outfac,
-                                  V + (size_t)(T - ca) * P, -1, cg, p->col_tile, s));
+    const int nm = cb > ca ? cb - ca : 0;
+    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, cg, p->col_tile, s, nm,
+                                inter + (size_t)(fh + ca - qa) * P, V + (size_t)(T - ca) * P, -1));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
   }
   if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));

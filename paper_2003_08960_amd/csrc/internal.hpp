@@ -129,8 +129,11 @@ hipError_t launch_rescale_dft(int T, int N, const uint16_t* frames, const AxisTa
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
                              const AxisTab* cols0, const float2* tw, const float* apoly, const float2* outfac,
                              float2* inter, int Fh, int rpg, int cu, hipStream_t s);
+// F2 > 0 adds a second run of F2 transforms in the same launch: from inter2
+// (consecutive frames) to V2 + i fstride2 N^2
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                             int fstride, int grid, int ctile, hipStream_t s);
+                             int fstride, int grid, int ctile, hipStream_t s, int F2 = 0,
+                             const float2* inter2 = nullptr, float2* V2 = nullptr, int fstride2 = 0);
 
 // Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
 // into `inter`, then row DFT^- fused with the recomputed row input and the

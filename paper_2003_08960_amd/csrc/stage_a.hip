@@ -558,7 +558,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2*
 
 // ------------------------------------------------------------------ column pass (both directions)
 // Tiles are (frame f, block of C columns) over the F frames of the launch,
-// walked persistently.  src, dst: frame 0 of this launch; frame f at + f N^2.
+// walked persistently.  Frames f < nA read src + f N^2 and write frame
+// f fstride of dst; frames f >= nA read src2 + (f - nA) N^2 and write frame
+// (f - nA) fstride2 of dst2 (two runs of frames in one launch).
 // DIR = +1 writes H in format FMT (and the Eq. 6 output phase when EQ6);
 // DIR = -1 writes complex64.
 template <int N, int DIR, int FMT, bool EQ6, int CT = ColCfg<N>::C>
@@ -566,7 +568,8 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
                                                                   const float2* __restrict__ tw,
                                                                   const float2* __restrict__ outfac,
                                                                   void* __restrict__ dst, float scale, int ntiles,
-                                                                  int fstride) {
+                                                                  int fstride, const float2* __restrict__ src2,
+                                                                  void* __restrict__ dst2, int nA, int fstride2) {
   using S = FFTShape<N>;
   constexpr int G = S::G;
   constexpr int C = CT;
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
   float2 pf[16];
   auto issue = [&](int tile) {
     const int f = tile / NCB, col = (tile % NCB) * C + c;
-    const float2* s = src + (size_t)f * N * N + col;
+    const float2* s = (f < nA ? src + (size_t)f * N * N : src2 + (size_t)(f - nA) * N * N) + col;
 #pragma unroll
     for (int k = 0; k < 16; ++k) pf[k] = ld_once<SSOCT_COL_NT_LD>(s + (size_t)(j + k * G) * N);
   };
@@ -613,13 +616,14 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
     const int f = tile / NCB, col = (tile % NCB) * C + c;
     if constexpr (TWL) fft_group_tw<N, DIR, C, false>(v, j, xbuf + c, TwMem<N>{twl, j});
     else fft_group<N, DIR, C>(v, j, xbuf + c, tw);
-    const long long fo = (long long)f * fstride * N * N;   // output frame f at dst + f fstride N^2
+    void* d = f < nA ? dst : dst2;
+    const long long fo = (f < nA ? (long long)f * fstride : (long long)(f - nA) * fstride2) * N * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int u = j + out_offset<N>(e);
       float2 val = v[e];
       if constexpr (EQ6) val = cmul(val, outfac[u]);
-      store_h<FMT, (DIR > 0 ? SSOCT_COL_NT : SSOCT_ADJ_NT)>(dst, fo + (long long)u * N + col, val, scale);
+      store_h<FMT, (DIR > 0 ? SSOCT_COL_NT : SSOCT_ADJ_NT)>(d, fo + (long long)u * N + col, val, scale);
     }
   }
 }
@@ -822,12 +826,13 @@ void col_tiles(int N, int* out) {
 // forward column pass of tile width CT (with the Eq. 6 output phase when outfac is given)
 template <int N, int CT>
 static hipError_t col_pass_nt(int F, const float2* inter, const float2* tw, const float2* outfac, void* dst, int fmt,
-                              float scale, int req_grid, int fstride, hipStream_t s) {
-  const int ntiles = F * (N / CT);
+                              float scale, int req_grid, int fstride, hipStream_t s, int F2 = 0,
+                              const float2* inter2 = nullptr, void* dst2 = nullptr, int fstride2 = 0) {
+  const int ntiles = (F + F2) * (N / CT);
   dim3 grid(col_grid(ntiles, req_grid)), block(CT * FFTShape<N>::G);
 #define SSOCT_COL(FMT, E)                                                                                        \
   hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E, CT>), grid, block, 0, s, inter, tw, outfac, dst, scale, ntiles, \
-                     fstride)
+                     fstride, inter2, dst2, F, fstride2)
   if (fmt == HF_F32) { if (outfac) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
   else if (fmt == HF_F16) { if (outfac) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
   else { if (outfac) SSOCT_COL(HF_BF16, true); else SSOCT_COL(HF_BF16, false); }
@@ -856,7 +861,7 @@ static hipError_t col_pass_adj_n(int F, int t0, const float2* B, const float2* t
   dim3 grid(col_grid(ntiles, req_grid)), block(C::THREADS);
   const float2* src = B + (size_t)t0 * N * N;
   hipLaunchKernelGGL((k_col_pass<N, -1, HF_F32, false>), grid, block, 0, s, src, tw, (const float2*)nullptr,
-                     (void*)inter, 1.0f, ntiles, 1);
+                     (void*)inter, 1.0f, ntiles, 1, (const float2*)nullptr, (void*)nullptr, F, 0);
   return hipGetLastError();
 }
 
@@ -931,11 +936,15 @@ static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const Axi
 
 template <int N>
 static hipError_t col_pass_v_n(int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                               int fstride, int req_grid, int ctile, hipStream_t s) {
+                               int fstride, int req_grid, int ctile, hipStream_t s, int F2, const float2* inter2,
+                               float2* V2, int fstride2) {
   using K = ColTiles<N>;
-  if (K::ALT && ctile == K::C2) return col_pass_nt<N, K::C2>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
-  if (K::ALT && ctile == K::C4) return col_pass_nt<N, K::C4>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
-  return col_pass_nt<N, K::C>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s);
+#define SSOCT_COLV(CT) \
+  col_pass_nt<N, CT>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s, F2, inter2, V2, fstride2)
+  if (K::ALT && ctile == K::C2) return SSOCT_COLV(K::C2);
+  if (K::ALT && ctile == K::C4) return SSOCT_COLV(K::C4);
+  return SSOCT_COLV(K::C);
+#undef SSOCT_COLV
 }
 
 hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, const AxisTab* rows0,
@@ -947,8 +956,10 @@ hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, cons
 }
 
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
-                             int fstride, int grid, int ctile, hipStream_t s) {
-#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, ctile, s)
+                             int fstride, int grid, int ctile, hipStream_t s, int F2, const float2* inter2,
+                             float2* V2, int fstride2) {
+  if (F2 > 0 && !(inter2 && V2)) return hipErrorInvalidValue;
+#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, ctile, s, F2, inter2, V2, fstride2)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
