@@ -484,21 +484,25 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
     const double* pf = asp + 3 * (size_t)(t0 + f);
     const double inv_l2 = pf[0], cyc0 = pf[1], amp = pf[2];
     const double fx = (double)(kx < N / 2 ? kx : kx - N) * inv_nd;
+    const double rad0 = inv_l2 - fx * fx;
+    const float famp = (float)amp;
+    // propagating: exp(2 pi i (cyc0 - z sqrt(rad))) amp; evanescent (rad <= 0): 0
+    // (exp(-i k z) for +z: the paper's fields carry exp(+i omega t), as the prefactor of Eq. 6
+    // does).  The phase (up to ~1e5 cycles) is reduced to a fraction in FP64; the hardware sine
+    // and cosine take the fraction in cycles (within 1.3e-7 of FP64 over one cycle on gfx950).
+    // Evaluated without branches (an evanescent element takes a dummy root and is zeroed), so the
+    // sixteen FP64 chains of a thread interleave.
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int ky = j + out_offset<N>(e);
       const double fy = (double)(ky < N / 2 ? ky : ky - N) * inv_nd;
-      const double rad = inv_l2 - fx * fx - fy * fy;
-      float2 h = make_float2(0.f, 0.f);
-      if (rad > 0.0) {   // propagating: exp(2 pi i (cyc0 - z sqrt(rad))) amp; evanescent: 0
-        // (exp(-i k z) for +z: the paper's fields carry exp(+i omega t), as the prefactor of Eq. 6
-        // does).  The phase (up to ~1e5 cycles) is reduced to a fraction in FP64; the hardware sine
-        // and cosine take the fraction in cycles (within 1.3e-7 of FP64 over one cycle on gfx950)
-        double cyc = cyc0 - z * sqrt(rad);
-        cyc -= rint(cyc);
-        const float fr = (float)cyc;
-        h = make_float2(__builtin_amdgcn_cosf(fr) * (float)amp, __builtin_amdgcn_sinf(fr) * (float)amp);
-      }
+      const double rad = rad0 - fy * fy;
+      const bool prop = rad > 0.0;
+      double cyc = cyc0 - z * sqrt(prop ? rad : 1.0);
+      cyc -= rint(cyc);
+      const float fr = (float)cyc;
+      const float2 h = make_float2(prop ? __builtin_amdgcn_cosf(fr) * famp : 0.f,
+                                   prop ? __builtin_amdgcn_sinf(fr) * famp : 0.f);
       v[e] = cmul(v[e], h);
     }
     __syncthreads();   // the forward transform's exchange reads are done
