@@ -103,6 +103,110 @@ def traffic_key(kernel: str, form: str) -> str:
     return f"{kernel}_{form}"
 
 
+# ------------------------------------------------------------------ counter summaries
+def _counter_means(path: str) -> dict:
+    """Mean, dispatch count and maximum of each counter per kernel name (template arguments kept)
+    over the dispatches of a rocprofv3 counter-collection CSV."""
+    import csv
+    acc = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"].replace("void ", "").replace("ssoct::", "").split("(")[0].strip()
+            d = acc.setdefault(name, {})
+            d.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    return {k: {c: (sum(v) / len(v), len(v), max(v)) for c, v in d.items()} for k, d in acc.items()}
+
+
+def _traffic_label(name: str, kind: str):
+    """Label of a profiled kernel in the traffic record, or None.  `kind` is the evaluation order of
+    the bench run the counters come from: the column pass is the same kernel in both orders."""
+    base, _, args = name.partition("<")
+    targs = [a.strip() for a in args.rstrip(">").split(",")] if args else []
+    if kind == "depth_first":
+        return {"k_rescale_dft_win": "k_rescale_dft_win", "k_row_pass_g": "k_row_pass_g",
+                "k_col_pass": "k_col_pass_v"}.get(base)
+    if base == "k_row_pass":
+        return "k_row_pass"
+    if base == "k_col_pass" and len(targs) >= 3 and targs[1] == "1":
+        return "k_col_pass_" + {"0": "fp32", "1": "fp16", "2": "bf16"}[targs[2]]
+    prec = {"0": "fp32", "1": "fp16", "2": "bf16", "3": "fp16_split", "4": "bf16_split"}
+    if base == "k_depth" and targs:
+        return "k_depth_" + prec[targs[0]]
+    if base == "k_depth_4step" and len(targs) >= 2:
+        return "k_depth_4step_" + prec[targs[1]] + "_4step"
+    if base == "k_depth_fft":
+        return "k_depth_fft_fp32_fft"
+    return None
+
+
+def _algorithmic_bytes(label: str, T: int, N: int, F: int) -> float:
+    """Algorithmic HBM bytes of one launch (averaged over the launches of one render)."""
+    P = N * N
+    nb = T // 2 + 1
+    nch_df = -(-nb // max(F // 2, 1))
+    if label == "k_rescale_dft_win":
+        return (2 * T + 8 * nb) * P
+    if label == "k_row_pass_g":
+        return (8 * nb + 8 * T) * P / nch_df
+    if label == "k_col_pass_v":
+        return 16 * T * P / nch_df
+    if label == "k_row_pass":
+        return ROW_BYTES_PER_VOXEL * F * P
+    if label.startswith("k_col_pass_"):
+        return COL_BYTES_PER_VOXEL * F * P
+    return DEPTH_BYTES_PER_VOXEL * T * P
+
+
+def summarize_counters(spec: str, out_path: str, T: int = 256, N: int = 1024, F: int = 16) -> str:
+    """Scale rocprofv3 FETCH_SIZE / WRITE_SIZE readings (KiB per dispatch) to HBM bytes per launch with
+    the copy of known size each run starts with (--copy-calibration), write the traffic record and
+    return a markdown table.  spec: comma-separated KIND:FETCH_CSV:WRITE_CSV with KIND the evaluation
+    order of the run (depth_first or frame)."""
+    kernels = {}
+    factors = []
+    for item in spec.split(","):
+        kind, fpath, wpath = item.split(":")
+        fetch, write = _counter_means(fpath), _counter_means(wpath)
+        # the 1 GiB device-to-device copy: the largest copy dispatch of the run
+        fcopy = max(v["FETCH_SIZE"][2] for k, v in fetch.items() if "copyBuffer" in k)
+        wcopy = max(v["WRITE_SIZE"][2] for k, v in write.items() if "copyBuffer" in k)
+        ff, wf = (1 << 30) / (fcopy * 1024), (1 << 30) / (wcopy * 1024)
+        factors.append((ff, wf))
+        sums = {}   # label -> [fetch KiB sum, write KiB sum, dispatches] over its template variants
+        for name in fetch:
+            label = _traffic_label(name, kind)
+            if label is None or name not in write:
+                continue
+            fr, n, _ = fetch[name]["FETCH_SIZE"]
+            wr, nw, _ = write[name]["WRITE_SIZE"]
+            acc = sums.setdefault(label, [0.0, 0.0, 0, 0])
+            acc[0] += fr * n
+            acc[1] += wr * nw
+            acc[2] += n
+            acc[3] += nw
+        for label, (fs, ws, n, nw) in sums.items():
+            fr, wr = fs / n, ws / nw
+            kernels[label] = {"bytes_per_launch": (fr * ff + wr * wf) * 1024, "fetch_kib_raw": fr,
+                              "write_kib_raw": wr, "dispatches": n, "order": kind,
+                              "algorithmic_bytes_per_launch": _algorithmic_bytes(label, T, N, F)}
+    ff = sum(f for f, _ in factors) / len(factors)
+    wf = sum(w for _, w in factors) / len(factors)
+    rec = {"source_hash": kernel_source_hash(), "fetch_factor": ff, "write_factor": wf,
+           "workload": f"T={T} N={N}, {F} frames per Fresnel launch (depth first: {F // 2} bins per chunk)",
+           "kernels": dict(sorted(kernels.items()))}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"Scale factors from the 1 GiB copy: FETCH x{ff:.3f}, WRITE x{wf:.3f} (true bytes per counted byte).",
+             "", "| label | order | dispatches | FETCH KiB (raw) | WRITE KiB (raw) | HBM bytes per launch (scaled) "
+             "| algorithmic bytes per launch | ratio |", "|---|---|---:|---:|---:|---:|---:|---:|"]
+    for label, k in rec["kernels"].items():
+        lines.append(f"| {label} | {k['order']} | {k['dispatches']} | {k['fetch_kib_raw']:.0f} | "
+                     f"{k['write_kib_raw']:.0f} | {k['bytes_per_launch'] / 2**20:.1f} MiB | "
+                     f"{k['algorithmic_bytes_per_launch'] / 2**20:.1f} MiB | "
+                     f"{k['bytes_per_launch'] / k['algorithmic_bytes_per_launch']:.3f} |")
+    return "\n".join(lines)
+
+
 def sampled_pixels(sw, n_random=6, seed=5):
     N = sw.frames.shape[1]
     rng = np.random.default_rng(seed)
@@ -640,7 +744,13 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one untimed 1 GiB device-to-device copy first: the reference kernel that "
                          "scales rocprofv3 FETCH_SIZE/WRITE_SIZE readings to bytes")
+    ap.add_argument("--summarize-counters", metavar="KIND:FETCH_CSV:WRITE_CSV[,...]",
+                    help="no GPU work: scale rocprofv3 FETCH_SIZE/WRITE_SIZE readings of earlier runs into "
+                         "profiles/traffic.json and print the table")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, os.path.join(ROOT, "profiles", "traffic.json")))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the render of one sweep runs on a single MI355X "
               "(sharding a volume across GPUs is described in the design notes only); use --gpus 1", file=sys.stderr)
