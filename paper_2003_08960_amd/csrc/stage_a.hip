@@ -27,8 +27,25 @@ namespace ssoct {
 #ifndef SSOCT_ROW_WAVESYNC
 #define SSOCT_ROW_WAVESYNC 1     // single-wave row groups exchange with wave-level ordering
 #endif
+#ifndef SSOCT_AS_XCD
+#define SSOCT_AS_XCD 1           // transfer-function column pass: contiguous runs of tiles per XCD
+#endif
+#ifndef SSOCT_AS_GROUP
+#define SSOCT_AS_GROUP 0         // > 0: phase evaluations scheduled in groups of this many
+#endif
+#ifndef SSOCT_AS_PF
+#define SSOCT_AS_PF 1            // transfer-function column pass: next tile loaded while the current one is transformed
+#endif
+#ifndef SSOCT_AS_WPE
+#define SSOCT_AS_WPE 0           // > 0: waves per SIMD the transfer-function column pass is compiled for
+#endif
+#if SSOCT_AS_WPE > 0
+#define SSOCT_AS_OCC __attribute__((amdgpu_waves_per_eu(SSOCT_AS_WPE)))
+#else
+#define SSOCT_AS_OCC
+#endif
 #ifndef SSOCT_AS_THREADS
-#define SSOCT_AS_THREADS 512     // transfer-function column pass: at most this many threads per workgroup
+#define SSOCT_AS_THREADS 256     // transfer-function column pass: at most this many threads per workgroup
 #endif
 #ifndef SSOCT_COL_MIN
 #define SSOCT_COL_MIN 16         // minimum adjacent columns per column workgroup (128 B row segments)
@@ -426,8 +443,10 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_fwd(const uint16_
 }
 
 // The transfer-function column pass keeps 16 FP64 phase evaluations in flight
-// per thread, so its tiles are narrower than the column pass's: at most 512
-// threads, which leaves 256 VGPRs per thread.
+// per thread, so its tiles are narrower than the column pass's: at most 256
+// threads (4 columns at N = 1024), which leaves room for two workgroups per
+// CU (LDS: exchange buffer plus twiddle table, 48 KB at N = 1024) at up to 256
+// VGPRs per thread; 8-column tiles hold one workgroup per CU.
 template <int N>
 struct AsColCfg {
   static constexpr int C = ColCfg<N>::C * FFTShape<N>::G > SSOCT_AS_THREADS ? SSOCT_AS_THREADS / FFTShape<N>::G
@@ -435,8 +454,24 @@ struct AsColCfg {
   static constexpr int THREADS = C * FFTShape<N>::G;
 };
 
+// Square root of a positive normal FP64 value (no zero, subnormal, infinity or
+// NaN, so none of the range scaling of the library root): the hardware
+// reciprocal-root estimate, one Goldschmidt step and two Newton corrections
+// of the root, which end within an ulp.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 template <int N>
-__global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restrict__ buf, int t0,
+__global__ __launch_bounds__(AsColCfg<N>::THREADS) SSOCT_AS_OCC void k_as_col(float2* __restrict__ buf, int t0,
                                                                 const float2* __restrict__ tw,
                                                                 const double* __restrict__ asp, double inv_nd,
                                                                 double z, int ntiles) {
@@ -451,6 +486,7 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
   // that is being written in place.
   constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
   constexpr bool TWL = SSOCT_COL_TWL && (S::LDS * C + TWN) * 8 <= 163840;
+  constexpr bool PF = TWL && SSOCT_AS_PF;
   __shared__ float2 xbuf[S::LDS * C];
   __shared__ float2 twl[TWL ? TWN : 1];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
@@ -460,22 +496,32 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
 #pragma unroll
     for (int k = 0; k < 16; ++k) pf[k] = cs[(size_t)(j + k * G) * N];
   };
+  // tiles tile0, tile0 + tstride, ... below tend: with SSOCT_AS_XCD each XCD
+  // (workgroups are dispatched round-robin over the 8) walks a contiguous run,
+  // so the workgroups of one L2 hold neighbouring column blocks
+  int tile0 = blockIdx.x, tstride = gridDim.x, tend = ntiles;
+  if (SSOCT_AS_XCD && gridDim.x % 8 == 0) {
+    const int per = (ntiles + 7) / 8, x = blockIdx.x % 8;
+    tile0 = x * per + (int)blockIdx.x / 8;
+    tstride = gridDim.x / 8;
+    tend = min(ntiles, (x + 1) * per);
+  }
   if constexpr (TWL) {
-    if ((int)blockIdx.x < ntiles) issue(blockIdx.x);
+    if (PF && tile0 < tend) issue(tile0);
     for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += AsColCfg<N>::THREADS) twl[i] = tw[i];
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop is entered with no load outstanding
     __syncthreads();  // twiddles visible
   }
   const TwMem<N> twm{TWL ? static_cast<const float2*>(twl) : tw, j};
 #pragma unroll 1
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = tile0; tile < tend; tile += tstride) {
     const int f = tile / NCB, kx = (tile % NCB) * C + c;
     float2* col = buf + (size_t)f * N * N + kx;
     float2 v[16];
-    if constexpr (TWL) {
+    if constexpr (PF) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) v[k] = pf[k];
-      if (tile + (int)gridDim.x < ntiles) issue(tile + gridDim.x);
+      if (tile + tstride < tend) issue(tile + tstride);
     } else {
 #pragma unroll
       for (int k = 0; k < 16; ++k) v[k] = col[(size_t)(j + k * G) * N];
@@ -483,8 +529,11 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
     fft_group_tw<N, -1, C, false>(v, j, xbuf + c, twm);
     const double* pf = asp + 3 * (size_t)(t0 + f);
     const double inv_l2 = pf[0], cyc0 = pf[1], amp = pf[2];
-    const double fx = (double)(kx < N / 2 ? kx : kx - N) * inv_nd;
-    const double rad0 = inv_l2 - fx * fx;
+    // squared spatial frequency (kx'^2 + ky'^2) / (N d)^2 from the exact integer kx'^2 + ky'^2
+    // (signed indices, at most N^2 / 2)
+    const int sx = kx < N / 2 ? kx : kx - N;
+    const int kx2 = sx * sx;
+    const double inv_nd2 = inv_nd * inv_nd;
     const float famp = (float)amp;
     // propagating: exp(2 pi i (cyc0 - z sqrt(rad))) amp; evanescent (rad <= 0): 0
     // (exp(-i k z) for +z: the paper's fields carry exp(+i omega t), as the prefactor of Eq. 6
@@ -495,15 +544,18 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) void k_as_col(float2* __restr
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int ky = j + out_offset<N>(e);
-      const double fy = (double)(ky < N / 2 ? ky : ky - N) * inv_nd;
-      const double rad = rad0 - fy * fy;
+      const int sy = ky < N / 2 ? ky : ky - N;
+      const double rad = inv_l2 - (double)(kx2 + sy * sy) * inv_nd2;
       const bool prop = rad > 0.0;
-      double cyc = cyc0 - z * sqrt(prop ? rad : 1.0);
+      double cyc = cyc0 - z * sqrt_pos(prop ? rad : 1.0);
       cyc -= rint(cyc);
       const float fr = (float)cyc;
       const float2 h = make_float2(prop ? __builtin_amdgcn_cosf(fr) * famp : 0.f,
                                    prop ? __builtin_amdgcn_sinf(fr) * famp : 0.f);
       v[e] = cmul(v[e], h);
+#if SSOCT_AS_GROUP > 0
+      if ((e + 1) % SSOCT_AS_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+#endif
     }
     __syncthreads();   // the forward transform's exchange reads are done
     // back to rows: DFT^+ expects input element ky at register (ky - j) / G;
