@@ -262,10 +262,19 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  * pixels per workgroup (FFT form) or workgroups (dense form)) on the given
  * inputs with HIP events on the plan's stream (synchronises the stream),
  * keep the fastest of each in the plan and write them to tuning.  Arguments
- * as for ssoct_plan_render; vol is overwritten. */
+ * as for ssoct_plan_render; vol is overwritten.
+ * The choice is kept in a process-wide cache keyed by the device's
+ * architecture and CU count, T, N, the plan flags (the profiling flags
+ * aside) and whether the depth-first order and the aberration factor apply
+ * to these inputs; a later call with the same key applies the cached shapes
+ * without timing anything (vol is then left untouched). */
 int ssoct_plan_tune(ssoct_plan* plan, const uint16_t* frames, const double* lambda, double pitch, double z,
                     const double* disp_phase, const double* zernike, void* workspace, size_t workspace_bytes,
                     void* vol, int* tuning);
+
+/* Empty the tuning cache of ssoct_plan_tune: the next call times again.
+ * Always SSOCT_OK. */
+int ssoct_tune_cache_clear(void);
 
 /* Read or set the launch-shape parameters (e.g. from a tuning cache);
  * SSOCT_TUNING_LEN entries. */

@@ -207,16 +207,19 @@ class Plan:
         t = (ctypes.c_int * native.TUNING_LEN)(*vals)
         native.check(self.lib.ssoct_plan_set_tuning(self._h, t))
 
-    def tuning_key(self) -> str:
+    def tuning_key(self, disp_phase=None, zernike=None) -> str:
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
-        return f"{arch}|T{self.T}|N{self.N}|flags{self.flags & ~native.PROFILE}"
+        flags = self.flags & ~(native.PROFILE | native.PROFILE_KERNELS)
+        return (f"{arch}|T{self.T}|N{self.N}|flags{flags}|disp{int(disp_phase is not None)}"
+                f"|zern{int(zernike is not None)}")
 
     def tune(self, frames, lam, pitch, z, disp_phase=None, zernike=None, cache_path: str | None = None,
              out: torch.Tensor | None = None):
-        """Pick launch shapes by timing candidates (ssoct_plan_tune); with `cache_path`, reuse or store
-        the choice in a JSON cache keyed by GPU architecture, T, N and plan flags.  `out` is an
+        """Pick launch shapes by timing candidates (ssoct_plan_tune, which also keeps its choice in a
+        process-wide cache); with `cache_path`, reuse or store the choice in a JSON file keyed by GPU
+        architecture, T, N, plan flags and whether dispersion and aberration are given.  `out` is an
         optional volume buffer to render into while timing."""
-        key = self.tuning_key()
+        key = self.tuning_key(disp_phase, zernike)
         if cache_path:
             cached = _load_cache(cache_path).get(key)
             if cached is not None:
@@ -259,6 +262,11 @@ def render(frames: torch.Tensor, lam, pitch: float, z: float, out: torch.Tensor 
 def render_release():
     """ssoct_render_release: free the plans and workspaces cached by render()."""
     native.check(native.load().ssoct_render_release())
+
+
+def tune_cache_clear():
+    """ssoct_tune_cache_clear: forget the launch shapes ssoct_plan_tune chose in this process."""
+    native.check(native.load().ssoct_tune_cache_clear())
 
 
 def _load_cache(path):

@@ -11,6 +11,9 @@
 
 #include "plan.hpp"
 
+#include <array>
+#include <map>
+
 using namespace ssoct;
 
 // Fresnel-stage chunking: the row pass of a chunk of frames writes a buffer
@@ -605,6 +608,22 @@ struct DefaultPlan {
 };
 std::mutex g_default_mu;
 std::vector<DefaultPlan> g_default;
+
+// Launch shapes chosen by ssoct_plan_tune, per device architecture, CU count,
+// T, N, plan flags (profiling aside) and whether the depth-first order and the
+// aberration factor apply: a later tune of the same kind takes them unmeasured.
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, SSOCT_TUNING_LEN>> g_tune_cache;
+
+int tune_key(const ssoct_plan* p, std::string* key) {
+  hipDeviceProp_t prop;
+  SSOCT_HIP(hipGetDeviceProperties(&prop, p->device));
+  const unsigned flags = p->flags & ~(unsigned)(SSOCT_PROFILE | SSOCT_PROFILE_KERNELS);
+  *key = std::string(prop.gcnArchName) + "/" + std::to_string(p->cu) + "/" + std::to_string(p->T) + "/" +
+         std::to_string(p->N) + "/" + std::to_string(flags) + "/" + std::to_string((int)p->df_allowed) + "/" +
+         std::to_string((int)p->have_aberr);
+  return SSOCT_OK;
+}
 }  // namespace
 
 int ssoct_render(const uint16_t* frames, int T, int N, const double* lambda, double pitch, double z, void* vol,
@@ -830,6 +849,17 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
   SSOCT_HIP(hipSetDevice(p->device));
   const int status = update_tables(p, lambda, pitch, z, disp_phase, zernike, false);
   if (status < 0) return status;
+  std::string key;
+  if (int rc = tune_key(p, &key)) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {   // shapes already timed for this device, size and form
+      if (int rc = ssoct_plan_set_tuning(p, it->second.data())) return rc;
+      if (tuning) ssoct_plan_get_tuning(p, tuning);
+      return status;
+    }
+  }
   hipEvent_t ev[4];
   for (auto& e : ev) SSOCT_HIP(hipEventCreate(&e));
   auto measure = [&](float* stage_a, float* stage_b) -> int {
@@ -912,8 +942,20 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc != SSOCT_OK) return rc;
+  {
+    std::array<int, SSOCT_TUNING_LEN> t{};
+    ssoct_plan_get_tuning(p, t.data());
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = t;
+  }
   if (tuning) ssoct_plan_get_tuning(p, tuning);
   return status;
+}
+
+int ssoct_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache.clear();
+  return SSOCT_OK;
 }
 
 }  // extern "C"

@@ -45,7 +45,7 @@ EXPORTS = (
     "ssoct_plan_set_stream", "ssoct_plan_destroy", "ssoct_render", "ssoct_render_release", "ssoct_plan_render",
     "ssoct_plan_render_noalloc", "ssoct_cuts", "ssoct_backward",
     "ssoct_backward_sharpness", "ssoct_plan_set_gate", "ssoct_profile_read", "ssoct_plan_tune", "ssoct_plan_get_tuning",
-    "ssoct_plan_set_tuning", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
+    "ssoct_plan_set_tuning", "ssoct_tune_cache_clear", "ssoct_stream_create", "ssoct_stream_push_frames", "ssoct_stream_acquire",
     "ssoct_stream_submit", "ssoct_stream_pop", "ssoct_stream_slot_volume", "ssoct_stream_stats",
     "ssoct_stream_destroy", "ssoct_slide_create", "ssoct_slide_push", "ssoct_slide_ring", "ssoct_slide_advance",
     "ssoct_slide_pop", "ssoct_slide_volume", "ssoct_slide_stats", "ssoct_slide_destroy",
@@ -111,6 +111,8 @@ def _declare(lib):
     lib.ssoct_plan_get_tuning.argtypes = [c_void_p, _iptr]
     lib.ssoct_plan_set_tuning.restype = c_int
     lib.ssoct_plan_set_tuning.argtypes = [c_void_p, _iptr]
+    lib.ssoct_tune_cache_clear.restype = c_int
+    lib.ssoct_tune_cache_clear.argtypes = []
     lib.ssoct_stream_create.restype = c_int
     lib.ssoct_stream_create.argtypes = [ctypes.POINTER(c_void_p), c_void_p, _dptr, c_double, c_double, _dptr, _dptr,
                                         c_int, c_int, c_int, c_int]

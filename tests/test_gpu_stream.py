@@ -173,6 +173,48 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
             plan.set_tuning(bad)
 
 
+def test_tune_cache_in_the_library(gpu_lib, sweeps):
+    """ssoct_plan_tune keeps its choice per (device, T, N, flags, order allowed, aberration): a second
+    plan of the same kind takes it without timing (its volume buffer is left untouched); after
+    ssoct_tune_cache_clear it times again.  Called through the C ABI with a NaN-filled volume."""
+    import ctypes
+    from paper_2003_08960_amd import api
+    from paper_2003_08960_amd.api import Plan
+    sw = sweeps[1]
+    lib = native.load()
+    fr = torch.from_numpy(sw.frames).cuda()
+    api.tune_cache_clear()
+
+    def tune(plan, vol):
+        t = (ctypes.c_int * native.TUNING_LEN)()
+        plan._sync_stream()
+        native.check(lib.ssoct_plan_tune(
+            plan._h, ctypes.c_void_p(fr.data_ptr()), native.host_doubles(sw.lam, T), sw.pitch, sw.z, None, None,
+            ctypes.c_void_p(plan.workspace.data_ptr()), plan.workspace.numel(), ctypes.c_void_p(vol.data_ptr()), t))
+        torch.cuda.synchronize()
+        return [int(x) for x in t]
+
+    nan = torch.view_as_complex(torch.full((T, N, N, 2), float("nan"), device="cuda"))   # NaN + NaN i
+    p1 = Plan(T, N, precision="fp32_fft")
+    vol = nan.clone()
+    choice = tune(p1, vol)
+    assert not torch.isnan(torch.view_as_real(vol)).any()          # timed: rendered into vol
+    p2 = Plan(T, N, precision="fp32_fft")
+    vol = nan.clone()
+    assert tune(p2, vol) == choice and p2.get_tuning() == choice
+    assert torch.isnan(torch.view_as_real(vol)).all()              # from the cache: nothing rendered
+    p3 = Plan(T, N, precision="bf16_split")                          # another form: its own entry
+    vol = nan.clone()
+    tune(p3, vol)
+    assert not torch.isnan(torch.view_as_real(vol)).any()
+    api.tune_cache_clear()
+    vol = nan.clone()
+    assert len(tune(p2, vol)) == native.TUNING_LEN
+    assert not torch.isnan(torch.view_as_real(vol)).any()          # timed again
+    for p in (p1, p2, p3):
+        p.close()
+
+
 def test_chunkwise_fresnel_with_ragged_chunks_and_discarded_sweep(gpu_lib, sweeps):
     """Frames per chunk 5 (T = 32: six full chunks and a ragged one): the chunk
     graphs of a sweep that is then discarded must not disturb the next sweep
