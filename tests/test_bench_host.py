@@ -77,3 +77,6 @@ def test_depth_first_algorithmic_bytes_sum_to_the_path():
              + nch * bench._algorithmic_bytes("k_col_pass_v", T, N, F))
     nb = T // 2 + 1
     assert total == pytest.approx((2 * T + 8 * nb + 8 * nb + 8 * T + 16 * T) * N * N)
+    # the whole-path figure counts stage 1's traffic and the volume, not the 2-D round trip
+    assert bench.path_bytes_per_voxel(T, True) == pytest.approx(2 + 16 * nb / T + 8)
+    assert bench.path_bytes_per_voxel(T, False) == 26
