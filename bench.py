@@ -41,6 +41,12 @@ def path_bytes_per_voxel(T: int, depth_first_order: bool) -> float:
     """Bytes per voxel the whole render must move: in the frame order 26; in the depth-first order
     the u16 frames in, the T/2 + 1 Hermitian bins of the depth DFT out and back in, the volume out."""
     return 2 + 2 * 8 * (T // 2 + 1) / T + 8 if depth_first_order else PATH_BYTES_PER_VOXEL
+
+
+def path_moved_bytes_per_voxel(T: int, depth_first_order: bool) -> float:
+    """Bytes per voxel the render's kernels move (their algorithmic bytes, which the calibrated
+    counters match): the method's bytes plus the row-to-column round trip of the 2-D transforms."""
+    return path_bytes_per_voxel(T, depth_first_order) + 16
 SPLIT_BAR = 1e-4
 FP32_BAR = 1e-5
 PAPER_GVOXEL_S = 10.0                   # paper's table (TITAN Xp, sliding STFT), context only
@@ -883,11 +889,15 @@ def main():
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
             "achieved": hr["path_bytes_per_voxel"] * voxels / (hr["ms_per_step"] * 1e-3) / 1e9,
             "frac": hr["hbm_frac_path"], "bytes_per_voxel": hr["path_bytes_per_voxel"],
+            "moved_bytes_per_voxel": path_moved_bytes_per_voxel(T, depth_first(hr, head)),
+            "frac_moved": path_moved_bytes_per_voxel(T, depth_first(hr, head)) * voxels
+                          / (hr["ms_per_step"] * 1e-3) / HBM_PEAK,
             "note": ("the whole render (tables, Fresnel stage, depth transform, cuts) against the bytes per "
                      "voxel the method must move in its evaluation order: depth first, u16 frames in, the "
                      "T/2 + 1 Hermitian bins of the depth DFT out and back in, complex64 volume out; frame "
                      "order, u16 frames in, H out and back in, volume out (26 B/voxel).  The row-to-column "
-                     "round trip of the 2-D transform (16 B/voxel more) is not counted")},
+                     "round trip of the 2-D transforms (16 B/voxel more) is not counted in frac; frac_moved "
+                     "counts every byte the kernels move (calibrated counters agree within 0.2 %)")},
         "kernels": kernels,
         # stage A (rescale + chirp + 2-D DFT) as one stage exists in the frame order only
         "stage_a_hbm_frac": (None if depth_first(hr, head) else
