@@ -169,7 +169,7 @@ def _algorithmic_bytes(label: str, T: int, N: int, F: int) -> float:
     return DEPTH_BYTES_PER_VOXEL * T * P
 
 
-def summarize_counters(spec: str, out_path: str, T: int = 256, N: int = 1024, F: int = 16) -> str:
+def summarize_counters(spec: str, out_path: str, T: int = 256, N: int = 1024, F: int = 16, F_df: int = 32) -> str:
     """Scale rocprofv3 FETCH_SIZE / WRITE_SIZE readings (KiB per dispatch) to HBM bytes per launch with
     the copy of known size each run starts with (--copy-calibration), write the traffic record and
     return a markdown table.  spec: comma-separated KIND:FETCH_CSV:WRITE_CSV with KIND the evaluation
@@ -200,11 +200,12 @@ def summarize_counters(spec: str, out_path: str, T: int = 256, N: int = 1024, F:
             fr, wr = fs / n, ws / nw
             kernels[label] = {"bytes_per_launch": (fr * ff + wr * wf) * 1024, "fetch_kib_raw": fr,
                               "write_kib_raw": wr, "dispatches": n, "order": kind,
-                              "algorithmic_bytes_per_launch": _algorithmic_bytes(label, T, N, F)}
+                              "algorithmic_bytes_per_launch":
+                                  _algorithmic_bytes(label, T, N, F_df if kind == "depth_first" else F)}
     ff = sum(f for f, _ in factors) / len(factors)
     wf = sum(w for _, w in factors) / len(factors)
     rec = {"source_hash": kernel_source_hash(), "fetch_factor": ff, "write_factor": wf,
-           "workload": f"T={T} N={N}, {F} frames per Fresnel launch (depth first: {F // 2} bins per chunk)",
+           "workload": f"T={T} N={N}, {F} frames per Fresnel launch (depth first: {F_df // 2} bins per chunk)",
            "kernels": dict(sorted(kernels.items()))}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -353,7 +354,7 @@ def roofline(rec, form, T, N):
         # bins: the bins in, both transforms (q and T - q; one for q = 0 and q = T/2) out, then the column
         # DFTs of those transforms into the volume
         nb = T // 2 + 1
-        fh = max(rec["tuning"]["frames_per_chunk"] // 2, 1)
+        fh = max(frames_per_chunk(rec, T, N, True) // 2, 1)
         nch = -(-nb // fh)
         # column launches: one per chunk (bins q and, in the same launch, their partners T - q)
         ncol = nch
@@ -363,7 +364,7 @@ def roofline(rec, form, T, N):
             "k_col_pass_v": (sp["col_pass"] * scale, ncol, 16 * voxels, 0.0),
         }
     else:
-        nch = -(-T // rec["tuning"]["frames_per_chunk"])
+        nch = -(-T // frames_per_chunk(rec, T, N, False))
         dname = "k_depth_fft" if form.endswith("_fft") else ("k_depth_4step" if form.endswith("_4step") else "k_depth")
         ks = {
             # name: (ms per step, launches per step, algorithmic bytes per step, flops per step)
@@ -399,6 +400,16 @@ def roofline(rec, form, T, N):
     roof["avg_launch_us"] = k["avg_launch_us"]
     roof["launches_per_step"] = k["launches"]
     return roof, kernels
+
+
+def frames_per_chunk(rec, T: int, N: int, depth_first_order: bool) -> int:
+    """Frames per Fresnel chunk a render used: the tuning's value, or for 0 the default of its
+    evaluation order (include/ssoct.h, tuning entry [0])."""
+    f = rec["tuning"]["frames_per_chunk"]
+    if f > 0:
+        return f
+    mib = 256 if depth_first_order else 128
+    return max(1, min(T, (mib << 20) // (8 * N * N)))
 
 
 def tuning_record(t):

@@ -228,7 +228,11 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  * Launch-shape parameters of a plan, int tuning[SSOCT_TUNING_LEN]:
  *   [0] frames per chunk of the Fresnel stage (1 .. the chunk the workspace
  *       was sized for; in the depth-first order two transforms per bin, so
- *       half as many bins per chunk)
+ *       half as many bins per chunk).  0 = default of the evaluation order in
+ *       use: min(T, 128 MiB / (8 N^2)) frames in the frame order (16 at
+ *       N = 1024), min(T, 256 MiB / (8 N^2)) in the depth-first order (32,
+ *       i.e. 16 bins); SSOCT_DEPTH_FFT plans size the workspace for the
+ *       larger, other plans for the first.
  *   [1] persistent column-pass workgroups (0 = default: as many as are
  *       resident at once on the device wherever the column pass prefetches
  *       its next tile, which is the angular-spectrum column pass at every N

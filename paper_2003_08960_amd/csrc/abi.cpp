@@ -19,9 +19,15 @@ using namespace ssoct;
 // Fresnel-stage chunking: the row pass of a chunk of frames writes a buffer
 // of SSOCT_CHUNK_MIB that the column pass reads right after.  (Overlapping
 // the two passes on two streams with a ring of buffers was measured slower:
-// the per-chunk cross-stream waits cost more than the overlap.)
+// the per-chunk cross-stream waits cost more than the overlap.)  The
+// depth-first order of the FFT form runs best with twice that buffer (its
+// 2-D passes per chunk of bins then stay within the 256 MB MALL with half as
+// many launches), so FFT-form plans size the buffer for SSOCT_CHUNK_DF_MIB.
 #ifndef SSOCT_CHUNK_MIB
 #define SSOCT_CHUNK_MIB 128
+#endif
+#ifndef SSOCT_CHUNK_DF_MIB
+#define SSOCT_CHUNK_DF_MIB 256
 #endif
 
 namespace ssoct {
@@ -42,13 +48,19 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool pow2_in_range(int N) { return N >= 16 && N <= 2048 && (N & (N - 1)) == 0; }
 
-int frames_per_chunk(int T, int N) {
-  // one chunk of row-transformed frames (8 bytes per pixel) near SSOCT_CHUNK_MIB
+int frames_per_chunk(int T, int N, int mib) {
+  // one chunk of row-transformed frames (8 bytes per pixel) near `mib` MiB
   const size_t per = (size_t)N * N * 8;
-  size_t f = ((size_t)SSOCT_CHUNK_MIB << 20) / per;
+  size_t f = ((size_t)mib << 20) / per;
   if (f < 1) f = 1;
   if (f > (size_t)T) f = (size_t)T;
   return (int)f;
+}
+
+int chunk_capacity(int T, int N, uint32_t flags) {
+  const int fr = frames_per_chunk(T, N, SSOCT_CHUNK_MIB);
+  const int df = (flags & SSOCT_DEPTH_FFT) ? frames_per_chunk(T, N, SSOCT_CHUNK_DF_MIB) : fr;
+  return fr > df ? fr : df;
 }
 
 // FP64 loss partials of the sharpness epilogue: one per dense depth
@@ -340,11 +352,12 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
 }
 
 int fresnel_chunks(const ssoct_plan* p) {
+  const int F = p->frames_run();
   if (p->depth_first()) {
-    const int fh = p->F_run / 2 > 0 ? p->F_run / 2 : 1;
+    const int fh = F / 2 > 0 ? F / 2 : 1;
     return (p->T / 2 + fh) / fh;   // ceil((T/2 + 1) / fh)
   }
-  return (p->T + p->F_run - 1) / p->F_run;
+  return (p->T + F - 1) / F;
 }
 
 // Depth-first order (frame-independent chirp and row factor): the depth
@@ -362,7 +375,8 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
   const float* ab = p->have_aberr ? p->apoly : nullptr;
   const int nb = T / 2 + 1;                     // bins of G
   const int nconj = (T + 1) / 2;                // bins q < nconj have a partner T - q (q >= 1)
-  const int fh = p->F_run / 2 > 0 ? p->F_run / 2 : 1;   // bins per chunk: 2 fh transforms fit the chunk buffer
+  const int F = p->frames_run();
+  const int fh = F / 2 > 0 ? F / 2 : 1;   // bins per chunk: 2 fh transforms fit the chunk buffer
   if (2 * fh > p->F) return fail(SSOCT_EUNSUPPORTED, "chunk buffer too small for the depth-first order");
   if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
   SSOCT_HIP(launch_rescale_dft(T, N, frames, p->rows, p->cols, p->params, p->dtw, G, s));
@@ -387,7 +401,7 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
 int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, const WsLayout& L, void* vol,
                 hipEvent_t* ev, hipEvent_t* kev) {
   if (p->depth_first()) return render_depth_first(p, s, frames, ws, L, vol, ev, kev);
-  const int T = p->T, N = p->N, F = p->F_run;
+  const int T = p->T, N = p->N, F = p->frames_run();
   if (ev) SSOCT_HIP(hipEventRecord(ev[1], s));
   if (kev) {  // the two passes launched one by one with an event after each
     const int fmt = h_format(depth_prec(p->flags));
@@ -418,7 +432,7 @@ static bool adjoint_by_fft(const ssoct_plan* p) { return depth_fft_supported(p->
 
 static int adjoint_chain(ssoct_plan* p, const uint16_t* frames, const void* G, char* ws, const WsLayout& L,
                          const double* loss_partials, int n_loss, double grad_scale, double* out) {
-  const int T = p->T, N = p->N, F = p->F_run;
+  const int T = p->T, N = p->N, F = p->frames_run_frame();
   if (p->have_aberr && !p->screen_ok) {   // the adjoint row pass reads the screen as N x N factors
     if (!p->screen) SSOCT_HIP(hipMalloc(&p->screen, (size_t)N * N * sizeof(float2)));
     SSOCT_HIP(launch_aberr_screen(p->params, T, N, p->screen, p->stream));
@@ -470,7 +484,7 @@ const char* ssoct_last_error(void) { return g_err.c_str(); }
 
 size_t ssoct_workspace_size(int T, int N, uint32_t flags) {
   if (T < 1 || T > 1024 || !pow2_in_range(N)) return 0;
-  return ws_layout(T, N, flags, frames_per_chunk(T, N)).total;
+  return ws_layout(T, N, flags, chunk_capacity(T, N, flags)).total;
 }
 
 int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream_t stream) {
@@ -499,8 +513,10 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   p->N = N;
   p->flags = flags;
   p->stream = stream;
-  p->F = frames_per_chunk(T, N);
-  p->F_run = p->F;
+  p->F_frame = frames_per_chunk(T, N, SSOCT_CHUNK_MIB);
+  p->F_df = (flags & SSOCT_DEPTH_FFT) ? frames_per_chunk(T, N, SSOCT_CHUNK_DF_MIB) : p->F_frame;
+  p->F = chunk_capacity(T, N, flags);
+  p->F_run = 0;
   p->general = (flags & SSOCT_NONUNIFORM_K) != 0;
   p->dl = depth_layout(T, p->general);
   zernike_monomials(p->zmat);
@@ -727,8 +743,9 @@ int ssoct_backward_sharpness(ssoct_plan* p, const uint16_t* frames, const double
   // Fresnel stage in FP32 whatever the plan's depth precision: the loss and its adjoint run in FP32
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   const float* ab = p->have_aberr ? p->apoly : nullptr;
-  for (int t0 = 0; t0 < T; t0 += p->F_run) {
-    const int Fc = T - t0 < p->F_run ? T - t0 : p->F_run;
+  const int F = p->frames_run_frame();
+  for (int t0 = 0; t0 < T; t0 += F) {
+    const int Fc = T - t0 < F ? T - t0 : F;
     SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, p->stream));
     SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, H, HF_F32, 0, col_grid_of(p), p->stream));
   }
@@ -817,7 +834,7 @@ int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
 int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   if (int rc = check_plan(p)) return rc;
   if (!tuning) return fail(SSOCT_EINVAL, "tuning is NULL");
-  if (tuning[0] < 1 || tuning[0] > p->F) return fail(SSOCT_EINVAL, "frames per chunk out of range");
+  if (tuning[0] < 0 || tuning[0] > p->F) return fail(SSOCT_EINVAL, "frames per chunk out of range");
   if (tuning[1] < 0 || tuning[1] > 65536 || tuning[2] < 0 || tuning[2] > 4096)
     return fail(SSOCT_EINVAL, "workgroup count out of range");
   if (tuning[3] != 0 && tuning[3] != 1) return fail(SSOCT_EINVAL, "order must be 0 or 1");

@@ -55,7 +55,7 @@ extern "C" int ssoct_plan_render_noalloc(ssoct_plan* p, const uint16_t* frames, 
   const int T = p->T, N = p->N;
   // the plan's frames per chunk, reduced until the workspace fits the array
   // (the chunking changes the speed only, never the result)
-  int F = p->F_run;
+  int F = p->frames_run();
   WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, F);
   while (F > 1 && L.total > STATIC_SCRATCH_BYTES) L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, --F);
   if (L.total > STATIC_SCRATCH_BYTES)

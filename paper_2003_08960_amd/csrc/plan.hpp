@@ -15,7 +15,8 @@ struct WsLayout {
   size_t H, inter, B2, mono, loss, total;
 };
 WsLayout ws_layout(int T, int N, uint32_t flags, int F);
-int frames_per_chunk(int T, int N);
+int frames_per_chunk(int T, int N, int mib);
+int chunk_capacity(int T, int N, uint32_t flags);
 
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* where);
@@ -31,11 +32,13 @@ int hip_fail(hipError_t e, const char* where);
 struct ssoct_plan {
   int T = 0, N = 0, device = 0, cu = 0;
   int F = 0;                   // frames per chunk the workspace is sized for
+  int F_frame = 0;             // default frames per chunk of the frame order
+  int F_df = 0;                // default frames per chunk of the depth-first order (two per bin)
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
   ssoct::DepthLayout dl{};
   // launch shapes (ssoct_plan_tune / ssoct_plan_set_tuning)
-  int F_run = 0;               // frames per chunk in use (1 .. F)
+  int F_run = 0;               // frames per chunk set by the tuning (1 .. F; 0 = the order's default)
   int col_grid = 0;            // persistent column workgroups (0 = default)
   int as_col_grid0 = 0;        // default of the angular-spectrum column pass (set at creation)
   int depth_grid = 0;          // persistent depth workgroups (0 = default)
@@ -79,6 +82,10 @@ struct ssoct_plan {
   bool df_allowed = false;     // current tables allow the depth-first order (SSOCT_DEPTH_FFT)
   int order = 1;               // tuning: 1 = depth-first order where allowed (default, measured faster), 0 = frame order
   bool depth_first() const { return df_allowed && order == 1; }
+  // frames per chunk of the evaluation order in use, and of the frame order
+  // (the sliding windows and the adjoint always transform frames)
+  int frames_run() const { return F_run > 0 ? F_run : (depth_first() ? F_df : F_frame); }
+  int frames_run_frame() const { return F_run > 0 ? F_run : F_frame; }
 };
 
 namespace ssoct {

@@ -147,7 +147,8 @@ int advance(ssoct_slide* sl, int n, uint64_t first, const uint16_t* host) {
     const int pos = (int)(seq % (uint64_t)T);
     uint64_t stop = end;
     stop = stop < seq + (uint64_t)(T - pos) ? stop : seq + (uint64_t)(T - pos);   // ring wrap
-    stop = stop < seq + (uint64_t)p->F_run ? stop : seq + (uint64_t)p->F_run;     // chunk buffer
+    const uint64_t fr = (uint64_t)p->frames_run_frame();
+    stop = stop < seq + fr ? stop : seq + fr;     // chunk buffer
     // next window end at or after seq: frame e with e + 1 - T >= run_start and (e + 1 - T - run_start) % hop == 0
     const uint64_t first_end = sl->run_start + (uint64_t)T - 1;
     uint64_t wend = first_end;

@@ -193,7 +193,7 @@ int ssoct_stream_create(ssoct_stream** out, ssoct_plan* p, const double* lambda,
   const int T = p->T, N = p->N;
   const WsLayout L = ws_layout(T, N, p->flags & ~SSOCT_BACKWARD, p->F);
   const size_t ncut = (size_t)N * N + 2 * (size_t)T * N;
-  const int F = p->F_run;
+  const int F = p->frames_run();
   // chunk-wise Fresnel graphs need the frame order; the depth-first order starts with all frames
   const int nch = p->depth_first() ? 0 : (T + F - 1) / F;
   st->F = F;

@@ -47,7 +47,7 @@ def test_summarize_counters_scales_by_the_copy(tmp_path):
     assert k["k_row_pass_g"]["dispatches"] == 2
     assert k["k_row_pass_g"]["bytes_per_launch"] == pytest.approx((60.0 * 2 + 120.0) * 1024)
     assert k["k_col_pass_v"]["bytes_per_launch"] == pytest.approx((50.0 * 2 + 70.0) * 1024)
-    assert k["k_col_pass_v"]["algorithmic_bytes_per_launch"] == pytest.approx(16 * 256 * 1024 ** 2 / 17)
+    assert k["k_col_pass_v"]["algorithmic_bytes_per_launch"] == pytest.approx(16 * 256 * 1024 ** 2 / 9)
     assert "k_col_pass_v" in table
 
 
@@ -69,9 +69,9 @@ def test_traffic_labels(name, kind, label):
 def test_depth_first_algorithmic_bytes_sum_to_the_path():
     """Per-launch figures times launches give the depth-first order's bytes per render:
     stage 1 (2 + 8 (T/2+1)/T), row pass (8 (T/2+1)/T + 8) and column pass (16) B per voxel."""
-    T, N, F = 256, 1024, 16
+    T, N, F = 256, 1024, 32
     nch = -(-(T // 2 + 1) // (F // 2))
-    assert nch == 17
+    assert nch == 9
     total = (bench._algorithmic_bytes("k_rescale_dft_win", T, N, F)
              + nch * bench._algorithmic_bytes("k_row_pass_g", T, N, F)
              + nch * bench._algorithmic_bytes("k_col_pass_v", T, N, F))

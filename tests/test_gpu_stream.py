@@ -164,8 +164,12 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
         assert torch.equal(plan.render(fr, sw.lam, sw.pitch, sw.z), V0)
     plan2 = Plan(T, N)
     assert plan2.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache) == choice   # from the cache
+    plan.set_tuning([0, 0, 0])                                  # 0: the order's default chunk
+    assert torch.equal(plan.render(fr, sw.lam, sw.pitch, sw.z), V0)
     with pytest.raises(native.SsoctError):
-        plan.set_tuning([0, 0, 0])
+        plan.set_tuning([-1, 0, 0])
+    with pytest.raises(native.SsoctError):
+        plan.set_tuning([T + 1, 0, 0])
     with pytest.raises(native.SsoctError):
         plan.set_tuning([1, 0, 0, 2])
     for bad in ([1, 0, 0, 0, 3], [1, 0, 0, 0, 0, 5], [1, 0, 0, 0, 0, 0, 48], [1, 0, 0, 0, 0, 0, 0, 1]):
