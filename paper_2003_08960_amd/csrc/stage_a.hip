@@ -454,6 +454,17 @@ struct AsColCfg {
   static constexpr int THREADS = C * FFTShape<N>::G;
 };
 
+// Register of DFT^+ input element j + G m that the forward transform's output
+// register e holds (element j + out_offset(e)): m = e / L + (e % L) (16 / L)
+template <int N>
+__device__ __forceinline__ constexpr int as_in_slot(int e) {
+  constexpr int L = FFTShape<N>::L > 1 ? FFTShape<N>::L : 1;
+  return e / L + (e % L) * (16 / L);
+}
+static_assert(as_in_slot<1024>(5) * FFTShape<1024>::G == out_offset<1024>(5), "register permutation of N = 1024");
+static_assert(as_in_slot<2048>(7) * FFTShape<2048>::G == out_offset<2048>(7), "register permutation of N = 2048");
+static_assert(as_in_slot<256>(9) * FFTShape<256>::G == out_offset<256>(9), "register permutation of N = 256");
+
 // Square root of a positive normal FP64 value (no zero, subnormal, infinity or
 // NaN, so none of the range scaling of the library root): the hardware
 // reciprocal-root estimate, one Goldschmidt step and two Newton corrections
@@ -557,16 +568,18 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) SSOCT_AS_OCC void k_as_col(fl
       if ((e + 1) % SSOCT_AS_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
 #endif
     }
-    __syncthreads();   // the forward transform's exchange reads are done
-    // back to rows: DFT^+ expects input element ky at register (ky - j) / G;
-    // the forward output sits at j + out_offset(e), so go through LDS once
+    // back to the input order of DFT^+, which wants element j + k G in
+    // register k: the forward output register e holds element
+    // j + out_offset(e) = j + G m(e), m(e) = e / L + (e % L) (16 / L), so
+    // the same thread already holds every element it needs and a register
+    // permutation replaces an exchange (the transform's own first exchange
+    // waits for the forward transform's last reads of xbuf)
+    float2 w[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) xbuf[(size_t)lds_slot(j + out_offset<N>(e)) * C + c] = v[e];
-    __syncthreads();
+    for (int e = 0; e < 16; ++e) w[as_in_slot<N>(e)] = v[e];
+    fft_group_tw<N, +1, C, false>(w, j, xbuf + c, twm);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = xbuf[(size_t)lds_slot(j + k * G) * C + c];
-    __syncthreads();
-    fft_group_tw<N, +1, C, false>(v, j, xbuf + c, twm);
+    for (int e = 0; e < 16; ++e) v[e] = w[e];
 #pragma unroll
     for (int e = 0; e < 16; ++e) col[(size_t)(j + out_offset<N>(e)) * N] = v[e];
     __syncthreads();   // this tile's exchange reads are done before the next tile writes LDS
