@@ -51,6 +51,9 @@ def test_workspace_size(lib):
     stack = T * N * N * 8
     ws = lib.ssoct_workspace_size(T, N, 0)
     assert stack < ws <= stack + (256 << 20)     # H stack + row-transformed chunk buffers
+    # FFT-form plans hold a 256 MiB chunk buffer (the depth-first order's chunk), others 128 MiB
+    assert lib.ssoct_workspace_size(T, N, 0) == stack + (128 << 20)
+    assert lib.ssoct_workspace_size(T, N, native.DEPTH_FFT) == stack + (256 << 20)
     wsb = lib.ssoct_workspace_size(T, N, native.BACKWARD)
     assert wsb >= 2 * stack
     for bad in ((0, 128), (1025, 128), (8, 100), (8, 8), (8, 4096)):
