@@ -34,7 +34,7 @@ namespace ssoct {
 #define SSOCT_AS_GROUP 0         // > 0: phase evaluations scheduled in groups of this many
 #endif
 #ifndef SSOCT_AS_PF
-#define SSOCT_AS_PF 1            // transfer-function column pass: next tile loaded while the current one is transformed
+#define SSOCT_AS_PF 0            // 1: transfer-function column pass loads its next tile while transforming (two workgroups per CU instead of three)
 #endif
 #ifndef SSOCT_AS_WPE
 #define SSOCT_AS_WPE 0           // > 0: waves per SIMD the transfer-function column pass is compiled for
@@ -490,11 +490,13 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) SSOCT_AS_OCC void k_as_col(fl
   constexpr int G = S::G;
   constexpr int C = AsColCfg<N>::C;
   constexpr int NCB = N / C;
-  // As in k_col_pass: where the twiddle table fits in LDS beside the
-  // exchange buffer, it goes there and the freed registers hold the next
-  // tile, loaded while the current one is transformed.  Tiles are disjoint
-  // and each belongs to one workgroup, so the prefetch never reads a column
-  // that is being written in place.
+  // As in k_col_pass, the twiddle table goes to LDS beside the exchange
+  // buffer where it fits.  With SSOCT_AS_PF the freed registers hold the
+  // next tile, loaded while the current one is transformed (tiles are
+  // disjoint and each belongs to one workgroup, so the prefetch never reads
+  // a column that is being written in place); without it the kernel needs
+  // 168 VGPRs and three workgroups share a CU, which covers the loads better
+  // at N = 1024.
   constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
   constexpr bool TWL = SSOCT_COL_TWL && (S::LDS * C + TWN) * 8 <= 163840;
   constexpr bool PF = TWL && SSOCT_AS_PF;
