@@ -923,6 +923,8 @@ def main():
         split = [f for f in ("bf16_split_4step", "bf16_split") if f in forms]
         stream_form = min(split, key=lambda f: forms[f]["ms_per_step"]) if split else head
         out["streaming"] = bench_stream(sw, stream_form, paced=not args.no_paced)
+        # the headline's form through the same engine (depth-first order: whole-volume graphs)
+        out["streaming_fp32_fft"] = bench_stream(sw, "fp32_fft", paced=False)
     if not args.no_slide:
         out["sliding"] = bench_slide(sw, head.removesuffix("_frame") if head.startswith("fp32") else "fp32_fft",
                                      paced=not args.no_paced)

@@ -248,8 +248,8 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  *       and the per-frame factor do not depend on the frame: no
  *       SSOCT_CHIRP_EXACT, no dispersion, no SSOCT_WRITE_ABS, no gate;
  *       otherwise the frame order is used)
- *   [4] rows per row group of the depth-first order's row pass (0 = chosen by
- *       the launch size; 2, 4 or 8)
+ *   [4] rows per row group of the depth-first order's row pass (0 = 4 where
+ *       that gives at least two workgroups per CU, else 2; 2, 4 or 8)
  *   [5] column tile width of the Fresnel column passes (0 = default, 16
  *       adjacent columns up to N = 1024; N >= 512 also takes 1/2 and 1/4 of
  *       the default; the adjoint keeps the default)

@@ -991,12 +991,9 @@ static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const Axi
   using R = RowCfg<N>;
   constexpr int MAXR = N / R::GR;   // rows per group cannot exceed the rows of one workgroup's share
   if (rpg != 8 && rpg != 4 && rpg != 2) {
-    rpg = 2;
-    for (int c = 8; c > 2; c /= 2)
-      if ((N / (R::GR * c)) * nb >= 2 * cu) {
-        rpg = c;
-        break;
-      }
+    // 4 rows per group where that still gives two workgroups per CU, else 2
+    // (8 rows measured slower at every launch size of the paper shape)
+    rpg = (N / (R::GR * 4)) * nb >= 2 * cu ? 4 : 2;
   }
   if (rpg > MAXR) rpg = MAXR;
   if (rpg >= 8 && MAXR >= 8) return row_pass_g_rpg<N, (MAXR >= 8 ? 8 : 1)>(nb, qa, T, G, rows0, cols0, tw, apoly, outfac, inter, Fh, s);
