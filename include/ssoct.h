@@ -254,7 +254,8 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  *       adjacent columns up to N = 1024; N >= 512 also takes 1/2 and 1/4 of
  *       the default; the adjoint keeps the default)
  *   [6] pixels per workgroup of the FFT-form depth transform (0 = default 32;
- *       16, 32 or 64)
+ *       16, 32 or 64) or of the factored MFMA form (SSOCT_DEPTH_4STEP;
+ *       0 = default 32; 16 or 32)
  *   [7] reserved, 0
  * [3] changes the rounding order only; every other entry changes speed only,
  * never results. */
@@ -263,7 +264,7 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
 /* Time candidate launch shapes (the evaluation order where allowed, then the
  * Fresnel stage's frames per chunk, column tile width, column workgroups and,
  * in the depth-first order, rows per row group; then the depth transform's
- * pixels per workgroup (FFT form) or workgroups (dense form)) on the given
+ * pixels per workgroup (FFT and factored forms) or workgroups (dense form)) on the given
  * inputs with HIP events on the plan's stream (synchronises the stream),
  * keep the fastest of each in the plan and write them to tuning.  Arguments
  * as for ssoct_plan_render; vol is overwritten.

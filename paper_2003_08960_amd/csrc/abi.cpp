@@ -343,7 +343,8 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
     return SSOCT_OK;
   }
   if (p->flags & SSOCT_DEPTH_4STEP) {
-    SSOCT_HIP(launch_depth_4step(p->T, p->N * p->N, prec, epi, ws + L.H, p->dtw, p->f4ops, vol, p->sigma, s, shift));
+    SSOCT_HIP(launch_depth_4step(p->T, p->N * p->N, prec, epi, ws + L.H, p->dtw, p->f4ops, vol, p->sigma, s, shift,
+                                 p->dfft_px));
     return SSOCT_OK;
   }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
@@ -845,7 +846,9 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   if (tuning[5] != 0 && tuning[5] != ct[0] && (tuning[5] != ct[1] || !ct[1]) && (tuning[5] != ct[2] || !ct[2]))
     return fail(SSOCT_EINVAL, "column tile width not available for this N");
   if (tuning[6] != 0 && tuning[6] != 16 && tuning[6] != 32 && tuning[6] != 64)
-    return fail(SSOCT_EINVAL, "FFT depth pixels per workgroup must be 0, 16, 32 or 64");
+    return fail(SSOCT_EINVAL, "depth pixels per workgroup must be 0, 16, 32 or 64");
+  if ((p->flags & SSOCT_DEPTH_4STEP) && tuning[6] == 64)
+    return fail(SSOCT_EINVAL, "the factored depth form takes 16 or 32 pixels per workgroup");
   if (tuning[7] != 0) return fail(SSOCT_EINVAL, "tuning[7] is reserved (0)");
   if (p->streaming && tuning[3] != p->order) return fail(SSOCT_EINVAL, "the order is fixed while a stream uses the plan");
   p->F_run = tuning[0];
@@ -952,6 +955,9 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
   if ((p->flags & SSOCT_DEPTH_FFT) && !df) {
     const int Ps[3] = {0, 16, 64};
     search(&p->dfft_px, Ps, 3, true);
+  } else if (p->flags & SSOCT_DEPTH_4STEP) {
+    const int Ps[2] = {0, 16};
+    search(&p->dfft_px, Ps, 2, true);
   } else if (!(p->flags & (SSOCT_DEPTH_FFT | SSOCT_DEPTH_4STEP))) {
     const int d0 = depth_grid(p->T, p->N * p->N, p->cu, p->general);
     const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};

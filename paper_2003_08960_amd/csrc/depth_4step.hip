@@ -33,7 +33,7 @@
 namespace ssoct {
 
 #ifndef SSOCT_F4_PX
-#define SSOCT_F4_PX 32           // pixels per tile: 128-byte (16) or 256-byte (32) rows of each frame
+#define SSOCT_F4_PX 32           // default pixels per tile: 128-byte (16) or 256-byte (32) rows of each frame
 #endif
 #ifndef SSOCT_F4_THREADS
 #define SSOCT_F4_THREADS 512     // workgroup size (waves take 32-column MFMA tiles in turn)
@@ -351,12 +351,11 @@ __device__ __forceinline__ void stage_b_pair(const uint2* in, int j, int l, cons
 // One workgroup per tile of PX pixels and all T frames: the stage-A
 // operands go from HBM to registers, the stage-A products cross LDS once,
 // stage B writes the volume.
-template <int T2, int PREC, int EPI>
+template <int T2, int PREC, int EPI, int PX>
 __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restrict__ H,
                                                             const float2* __restrict__ wt,
                                                             const uint32_t* __restrict__ ops, void* __restrict__ out,
                                                             int P, float mid_scale, float out_scale, int shift) {
-  constexpr int PX = F4_PX;
   using S = F4Shape<T2, PX>;
   __shared__ uint2 buf[S::T * PX];   // [q2][t1][pixel]
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -408,30 +407,37 @@ __global__ __launch_bounds__(F4_THREADS) void k_depth_4step(const uint2* __restr
   }
 }
 
-template <int T2, int PREC, int EPI>
+template <int T2, int PREC, int EPI, int PX>
 static hipError_t go_4step(int P, const void* H, const float2* wt, const uint32_t* ops, void* out, float mid,
                            float os, int shift, hipStream_t s) {
-  hipLaunchKernelGGL((k_depth_4step<T2, PREC, EPI>), dim3(P / F4_PX), dim3(F4_THREADS), 0, s,
+  hipLaunchKernelGGL((k_depth_4step<T2, PREC, EPI, PX>), dim3(P / PX), dim3(F4_THREADS), 0, s,
                      reinterpret_cast<const uint2*>(H), wt, ops, out, P, mid, os, shift);
   return hipGetLastError();
 }
 
-template <int T2, int PREC>
+template <int T2, int PREC, int PX>
 static hipError_t go_4step_epi(int epi, int P, const void* H, const float2* wt, const uint32_t* ops, void* out,
                                float mid, float os, int shift, hipStream_t s) {
-  if (epi == EPI_ABS) return go_4step<T2, PREC, EPI_ABS>(P, H, wt, ops, out, mid, os, shift, s);
-  return go_4step<T2, PREC, EPI_STORE>(P, H, wt, ops, out, mid, os, shift, s);
+  if (epi == EPI_ABS) return go_4step<T2, PREC, EPI_ABS, PX>(P, H, wt, ops, out, mid, os, shift, s);
+  return go_4step<T2, PREC, EPI_STORE, PX>(P, H, wt, ops, out, mid, os, shift, s);
+}
+
+template <int T2, int PREC>
+static hipError_t go_4step_px(int px, int epi, int P, const void* H, const float2* wt, const uint32_t* ops,
+                              void* out, float mid, float os, int shift, hipStream_t s) {
+  if (px == 16) return go_4step_epi<T2, PREC, 16>(epi, P, H, wt, ops, out, mid, os, shift, s);
+  return go_4step_epi<T2, PREC, 32>(epi, P, H, wt, ops, out, mid, os, shift, s);
 }
 
 template <int T2>
-static hipError_t go_4step_prec(int prec, int epi, int P, const void* H, const float2* wt, const uint32_t* ops,
-                                void* out, float mid, float os, int shift, hipStream_t s) {
+static hipError_t go_4step_prec(int prec, int px, int epi, int P, const void* H, const float2* wt,
+                                const uint32_t* ops, void* out, float mid, float os, int shift, hipStream_t s) {
   switch (prec) {
-    case DP_F32: return go_4step_epi<T2, DP_F32>(epi, P, H, wt, ops, out, mid, os, shift, s);
-    case DP_F16: return go_4step_epi<T2, DP_F16>(epi, P, H, wt, ops, out, mid, os, shift, s);
-    case DP_BF16: return go_4step_epi<T2, DP_BF16>(epi, P, H, wt, ops, out, mid, os, shift, s);
-    case DP_F16_SPLIT: return go_4step_epi<T2, DP_F16_SPLIT>(epi, P, H, wt, ops, out, mid, os, shift, s);
-    case DP_BF16_SPLIT: return go_4step_epi<T2, DP_BF16_SPLIT>(epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_F32: return go_4step_px<T2, DP_F32>(px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_F16: return go_4step_px<T2, DP_F16>(px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_BF16: return go_4step_px<T2, DP_BF16>(px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_F16_SPLIT: return go_4step_px<T2, DP_F16_SPLIT>(px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case DP_BF16_SPLIT: return go_4step_px<T2, DP_BF16_SPLIT>(px, epi, P, H, wt, ops, out, mid, os, shift, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -464,20 +470,22 @@ hipError_t launch_4step_operands(int T, int prec, uint32_t* ops, hipStream_t s) 
 }
 
 hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, const uint32_t* ops,
-                              void* out, int sigma, hipStream_t s, int shift) {
+                              void* out, int sigma, hipStream_t s, int shift, int px) {
   if (P <= 0) return hipSuccess;
   if (!ops) return hipErrorInvalidValue;
-  if (P % F4_PX != 0 || (epi != EPI_STORE && epi != EPI_ABS) || shift < 0 || shift >= T) return hipErrorInvalidValue;
+  if (px == 0) px = F4_PX;
+  if ((px != 16 && px != 32) || P % px != 0 || (epi != EPI_STORE && epi != EPI_ABS) || shift < 0 || shift >= T)
+    return hipErrorInvalidValue;
   const int T2 = T / 16;
   // FP16 stage-B operands: the stage-A sums grow by up to T2, scaled back by an exact power of two
   const bool f16 = prec == DP_F16 || prec == DP_F16_SPLIT;
   const float mid = f16 ? 1.0f / (float)T2 : 1.0f;
   const float os = ldexpf(f16 ? (float)T2 : 1.0f, sigma);
   switch (T) {
-    case 32: return go_4step_prec<2>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
-    case 64: return go_4step_prec<4>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
-    case 128: return go_4step_prec<8>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
-    case 256: return go_4step_prec<16>(prec, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 32: return go_4step_prec<2>(prec, px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 64: return go_4step_prec<4>(prec, px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 128: return go_4step_prec<8>(prec, px, epi, P, H, wt, ops, out, mid, os, shift, s);
+    case 256: return go_4step_prec<16>(prec, px, epi, P, H, wt, ops, out, mid, os, shift, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -179,8 +179,9 @@ hipError_t launch_depth_twiddles(int T, float2* wt, hipStream_t s);
 bool depth_4step_supported(int T);
 size_t depth_4step_ops_bytes();
 hipError_t launch_4step_operands(int T, int prec, uint32_t* ops, hipStream_t s);
+// px: pixels per workgroup tile, 16 or 32 (0 = 32)
 hipError_t launch_depth_4step(int T, int P, int prec, int epi, const void* H, const float2* wt, const uint32_t* ops,
-                              void* out, int sigma, hipStream_t s, int shift = 0);
+                              void* out, int sigma, hipStream_t s, int shift = 0, int px = 0);
 
 hipError_t launch_cuts(int T, int N, const float2* vol, int x0, int y0, int q0, int power,
                        float* cut_xy, float* cut_xz, float* cut_yz, hipStream_t s);

@@ -487,7 +487,8 @@ def test_five_argument_render(gpu_lib, tiny):
 def test_tiles_and_row_groups_change_speed_not_results(gpu_lib):
     """The tuner's tile choices at N = 1024: column tile widths 16 / 8 / 4, rows per row group of the
     depth-first order 2 / 4 / 8 and FFT depth workgroups of 16 / 32 / 64 pixels give bit-identical
-    volumes in both evaluation orders (and in the split H format); the tuner's pick too."""
+    volumes in both evaluation orders (and in the split H format); the tuner's pick too; and the
+    factored MFMA form gives the same volume with 16- or 32-pixel tiles."""
     from paper_2003_08960_amd.api import Plan
     T, N = 16, 1024
     frames, lam = random_case(T, N, seed=404)
@@ -513,3 +514,18 @@ def test_tiles_and_row_groups_change_speed_not_results(gpu_lib):
             else:
                 assert rel_l2(plan.render(fr, lam, 12e-6, 0.3).cpu().numpy(), ref) <= FP32_BAR
             plan.close()
+    # the factored MFMA form's pixel tile: 16 or 32 pixels per workgroup, the same products per pixel
+    T4 = 32
+    frames4, lam4 = random_case(T4, N, seed=405)
+    fr4 = torch.from_numpy(frames4).cuda()
+    ref4 = O.render(frames4, lam4, 12e-6, 0.3)
+    for precision in ("fp32_4step", "bf16_split_4step"):
+        plan = Plan(T4, N, precision=precision)
+        V0 = plan.render(fr4, lam4, 12e-6, 0.3).clone()
+        assert rel_l2(V0.cpu().numpy(), ref4) <= (FP32_BAR if precision.startswith("fp32") else SPLIT_BAR)
+        for px in (16, 32):
+            plan.set_tuning([0, 0, 0, 0, 0, 0, px])
+            assert torch.equal(plan.render(fr4, lam4, 12e-6, 0.3), V0), (precision, px)
+        with pytest.raises(native.SsoctError):
+            plan.set_tuning([0, 0, 0, 0, 0, 0, 64])
+        plan.close()
