@@ -415,7 +415,7 @@ def frames_per_chunk(rec, T: int, N: int, depth_first_order: bool) -> int:
 def tuning_record(t):
     """A plan's launch shapes by name (include/ssoct.h, tuning array; 0 = the default)."""
     return {"frames_per_chunk": t[0], "col_workgroups": t[1], "depth_workgroups": t[2], "order": t[3],
-            "rows_per_group_depth_first": t[4], "col_tile": t[5], "depth_px": t[6],
+            "rows_per_group_depth_first": t[4], "col_tile": t[5], "depth_px": t[6], "depth_kc": t[7],
             "radix_plan": "16 x 16 x 4 (N = 1024: fixed by N)"}
 
 

@@ -256,7 +256,10 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  *   [6] pixels per workgroup of the FFT-form depth transform (0 = default 32;
  *       16, 32 or 64) or of the factored MFMA form (SSOCT_DEPTH_4STEP;
  *       0 = default 32; 16 or 32)
- *   [7] reserved, 0
+ *   [7] frames per K chunk of the dense depth product (0 = default, the
+ *       smallest of 32, 64, 128, 256 that covers T; or half of it, at least
+ *       32: the same products in the same order, with half the matrix
+ *       operands held per lane)
  * [3] changes the rounding order only; every other entry changes speed only,
  * never results. */
 #define SSOCT_TUNING_LEN 8
@@ -264,7 +267,8 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
 /* Time candidate launch shapes (the evaluation order where allowed, then the
  * Fresnel stage's frames per chunk, column tile width, column workgroups and,
  * in the depth-first order, rows per row group; then the depth transform's
- * pixels per workgroup (FFT and factored forms) or workgroups (dense form)) on the given
+ * pixels per workgroup (FFT and factored forms) or workgroups and K chunk
+ * (dense form)) on the given
  * inputs with HIP events on the plan's stream (synchronises the stream),
  * keep the fastest of each in the plan and write them to tuning.  Arguments
  * as for ssoct_plan_render; vol is overwritten.

@@ -348,7 +348,7 @@ int render_depth(ssoct_plan* p, hipStream_t s, char* ws, const WsLayout& L, void
     return SSOCT_OK;
   }
   SSOCT_HIP(launch_depth(p->T, p->N * p->N, prec, +1, epi, ws + L.H, amat_for(p, prec), vol, p->sigma, 0, nullptr,
-                         depth_grid_for(p), s, p->dtw, shift, p->general));
+                         depth_grid_for(p), s, p->dtw, shift, p->general, p->depth_kc));
   return SSOCT_OK;
 }
 
@@ -828,7 +828,7 @@ int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
   tuning[4] = p->rpg_g;
   tuning[5] = p->col_tile;
   tuning[6] = p->dfft_px;
-  tuning[7] = 0;
+  tuning[7] = p->depth_kc;
   return SSOCT_OK;
 }
 
@@ -849,7 +849,8 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
     return fail(SSOCT_EINVAL, "depth pixels per workgroup must be 0, 16, 32 or 64");
   if ((p->flags & SSOCT_DEPTH_4STEP) && tuning[6] == 64)
     return fail(SSOCT_EINVAL, "the factored depth form takes 16 or 32 pixels per workgroup");
-  if (tuning[7] != 0) return fail(SSOCT_EINVAL, "tuning[7] is reserved (0)");
+  if (tuning[7] != 0 && (tuning[7] != p->dl.KC / 2 || tuning[7] < 32))
+    return fail(SSOCT_EINVAL, "dense depth K chunk must be 0 or half the default chunk (at least 32 frames)");
   if (p->streaming && tuning[3] != p->order) return fail(SSOCT_EINVAL, "the order is fixed while a stream uses the plan");
   p->F_run = tuning[0];
   p->col_grid = tuning[1];
@@ -858,6 +859,7 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   p->rpg_g = tuning[4];
   p->col_tile = tuning[5] == ct[0] ? 0 : tuning[5];
   p->dfft_px = tuning[6];
+  p->depth_kc = tuning[7];
   return SSOCT_OK;
 }
 
@@ -962,6 +964,10 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
     const int d0 = depth_grid(p->T, p->N * p->N, p->cu, p->general);
     const int Ds[2] = {0, 2 * d0 <= 4096 ? 2 * d0 : d0};
     search(&p->depth_grid, Ds, 2, true);
+    if (p->dl.KC / 2 >= 32) {
+      const int Ks[2] = {0, p->dl.KC / 2};
+      search(&p->depth_kc, Ks, 2, true);
+    }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc != SSOCT_OK) return rc;

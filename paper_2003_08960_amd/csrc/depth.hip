@@ -284,10 +284,16 @@ int depth_grid(int T, int P, int cu_count, bool general) {
 
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat, void* out,
                         int sigma, int gamma_exp, double* partials, int grid, hipStream_t s, const float2* wt,
-                        int shift, bool general) {
+                        int shift, bool general, int kc) {
   if (shift != 0 && !wt) return hipErrorInvalidValue;
   if (general && (dir < 0 || epi == EPI_GAMMA || shift != 0)) return hipErrorInvalidValue;   // forward only
   DepthLayout L = depth_layout(T, general);
+  // a smaller K chunk that divides the layout's keeps T_pad and the matrix layout (the K sum runs
+  // through the same products in the same order, chunk after chunk)
+  if (kc != 0) {
+    if (kc < 32 || kc > L.KC || L.KC % kc != 0) return hipErrorInvalidValue;
+    L.KC = kc;
+  }
   const int gen = general ? 1 : 0;
   const float os = ldexpf(1.0f, sigma);
   const float gs = ldexpf(1.0f, -gamma_exp);

@@ -149,9 +149,10 @@ int row_adj_blocks(int N);
 // (dir = +1) or sum_t conj(W[q][t]) in[t][p] (dir = -1).
 // shift > 0 (forward, EPI_STORE): the stack is a ring whose window starts at
 // slot `shift`; bin q is multiplied by exp(+2 pi i q shift / T) = conj(wt[q shift mod T]).
+// kc: frames per K chunk (0 = the layout's; else a divisor of it, at least 32)
 hipError_t launch_depth(int T, int P, int prec, int dir, int epi, const void* in, const void* amat,
                         void* out, int sigma, int gamma_exp, double* partials, int grid,
-                        hipStream_t s, const float2* wt = nullptr, int shift = 0, bool general = false);
+                        hipStream_t s, const float2* wt = nullptr, int shift = 0, bool general = false, int kc = 0);
 int depth_grid(int T, int P, int cu_count, bool general = false);
 
 // Depth transform as a radix FFT along the sweep (FP32; dir -1: adjoint).

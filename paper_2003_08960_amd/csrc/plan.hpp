@@ -44,6 +44,7 @@ struct ssoct_plan {
   int depth_grid = 0;          // persistent depth workgroups (0 = default)
   int rpg_g = 0;               // rows per row group of the bin-pair row pass (0 = by launch size; 2, 4, 8)
   int col_tile = 0;            // column tile width of the Fresnel column passes (0 = default)
+  int depth_kc = 0;            // frames per K chunk of the dense depth product (0 = default; half of it)
   int dfft_px = 0;             // pixels per workgroup of the forward FFT (16, 32, 64) or factored (16, 32)
                                // depth transform (0 = default 32)
   // device tables

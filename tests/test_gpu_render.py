@@ -484,6 +484,30 @@ def test_five_argument_render(gpu_lib, tiny):
 
 # ---------------------------------------------------------------- tuning alternatives (tiles, row groups)
 
+@pytest.mark.parametrize("T", [64, 256])
+def test_dense_k_chunk_changes_speed_not_results(gpu_lib, T):
+    """Tuning entry 7: the dense depth product with half its default K chunk (32 of 64, 128 of 256
+    frames) runs the same products in the same order, so the volume is bit-identical; other chunks
+    are rejected."""
+    from paper_2003_08960_amd.api import Plan
+    N = 128
+    frames, lam = random_case(T, N, seed=406 + T)
+    fr = torch.from_numpy(frames).cuda()
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    print(f"\n[gpu] dense K chunk T={T} N={N}", flush=True)
+    for precision, bar in (("fp32", FP32_BAR), ("bf16_split", SPLIT_BAR), ("fp16_split", SPLIT_BAR)):
+        plan = Plan(T, N, precision=precision)
+        V0 = plan.render(fr, lam, 20e-6, 0.05).clone()
+        assert rel_l2(V0.cpu().numpy(), ref) <= bar
+        kc = T // 2
+        plan.set_tuning([0, 0, 0, 0, 0, 0, 0, kc])
+        assert torch.equal(plan.render(fr, lam, 20e-6, 0.05), V0), (precision, kc)
+        for bad in (kc // 2, T, 48):
+            with pytest.raises(native.SsoctError):
+                plan.set_tuning([0, 0, 0, 0, 0, 0, 0, bad])
+        plan.close()
+
+
 def test_tiles_and_row_groups_change_speed_not_results(gpu_lib):
     """The tuner's tile choices at N = 1024: column tile widths 16 / 8 / 4, rows per row group of the
     depth-first order 2 / 4 / 8 and FFT depth workgroups of 16 / 32 / 64 pixels give bit-identical
