@@ -412,11 +412,22 @@ def frames_per_chunk(rec, T: int, N: int, depth_first_order: bool) -> int:
     return max(1, min(T, (mib << 20) // (8 * N * N)))
 
 
-def tuning_record(t):
+def radix_plan(N, order):
+    """Radix passes of an N-point column transform in the given radix order (include/ssoct.h, tuning [8])."""
+    r, n = [], N
+    while n % 16 == 0 and n > 1:
+        r.append(16)
+        n //= 16
+    if n > 1:
+        r = [n] + r if order == 1 else r + [n]
+    return " x ".join(str(x) for x in r)
+
+
+def tuning_record(t, N=1024):
     """A plan's launch shapes by name (include/ssoct.h, tuning array; 0 = the default)."""
     return {"frames_per_chunk": t[0], "col_workgroups": t[1], "depth_workgroups": t[2], "order": t[3],
             "rows_per_group_depth_first": t[4], "col_tile": t[5], "depth_px": t[6], "depth_kc": t[7],
-            "radix_plan": "16 x 16 x 4 (N = 1024: fixed by N)"}
+            "col_radix_order": t[8], "col_radix_plan": radix_plan(N, t[8])}
 
 
 def pctl(xs, q):
@@ -440,7 +451,7 @@ def bench_stream(sw, form, n_vol=16, slots=3, fps=512.0, chunk=16, paced=True):
     tuning = plan.tune(frames_dev, sw.lam, sw.pitch, sw.z, out=ws_vol)
     del ws_vol
     torch.cuda.empty_cache()
-    out = {"form": form, "volumes": n_vol, "slots": slots, "tuning": tuning_record(tuning)}
+    out = {"form": form, "volumes": n_vol, "slots": slots, "tuning": tuning_record(tuning, N)}
 
     st = Stream(plan, sw.lam, sw.pitch, sw.z, slots=slots)
     # device-resident: every slot holds the sweep; each volume is one graph launch
@@ -856,7 +867,7 @@ def main():
                "stage_ms": {"tables": stage[0], "fresnel": stage[1], "depth": stage[2]},
                "fresnel_split_ms": {"row_pass": kst[4], "col_pass": kst[5], "fresnel": kst[1],
                                     "note": "separate untimed pass with an event after every launch"},
-               "tuning": tuning_record(tuning)}
+               "tuning": tuning_record(tuning, N)}
         rec["path_bytes_per_voxel"] = path_bytes_per_voxel(T, depth_first(rec, form))
         rec["hbm_frac_path"] = rec["path_bytes_per_voxel"] * voxels / (ms * 1e-3) / HBM_PEAK
         if ref_cols is not None:

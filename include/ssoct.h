@@ -260,12 +260,20 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  *       smallest of 32, 64, 128, 256 that covers T; or half of it, at least
  *       32: the same products in the same order, with half the matrix
  *       operands held per lane)
- * [3] changes the rounding order only; every other entry changes speed only,
- * never results. */
-#define SSOCT_TUNING_LEN 8
+ *   [8] radix order of the forward Fresnel column transforms (0 = default:
+ *       the radix-16 passes first and the radix-2, 4 or 8 pass last, 16 16 4
+ *       at N = 1024; 1 = the small radix first, 4 16 16, which leaves the
+ *       output in natural order in registers at the price of twiddles on
+ *       every radix-16 pass).  Only N that is not a power of 16 (32, 64, 128,
+ *       512, 1024, 2048) has the second order; angular-spectrum plans and the
+ *       adjoint keep the default.
+ * [3] and [8] change the rounding only (the same transforms, within the
+ * same error bars); every other entry changes speed only, never results. */
+#define SSOCT_TUNING_LEN 9
 
 /* Time candidate launch shapes (the evaluation order where allowed, then the
- * Fresnel stage's frames per chunk, column tile width, column workgroups and,
+ * Fresnel stage's frames per chunk, column tile width, radix order of the
+ * column transforms, column workgroups and,
  * in the depth-first order, rows per row group; then the depth transform's
  * pixels per workgroup (FFT and factored forms) or workgroups and K chunk
  * (dense form)) on the given

@@ -193,7 +193,8 @@ class Plan:
     # -- launch shapes ---------------------------------------------------------------------------
     def get_tuning(self):
         """[frames per chunk, column workgroups, depth workgroups, evaluation order, rows per row group
-        (depth-first order), column tile width, FFT depth pixels per workgroup, 0] (include/ssoct.h)."""
+        (depth-first order), column tile width, depth pixels per workgroup (FFT and factored forms),
+        dense K chunk, column radix order] (include/ssoct.h)."""
         t = (ctypes.c_int * native.TUNING_LEN)()
         native.check(self.lib.ssoct_plan_get_tuning(self._h, t))
         return [int(x) for x in t]

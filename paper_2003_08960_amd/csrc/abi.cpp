@@ -136,6 +136,7 @@ static void plan_free(ssoct_plan* p) {
   (void)hipFree(p->rows);
   (void)hipFree(p->cols);
   (void)hipFree(p->tw);
+  (void)hipFree(p->tw1);
   (void)hipFree(p->outfac);
   (void)hipFree(p->apoly);
   (void)hipFree(p->screen);
@@ -307,6 +308,9 @@ int update_tables(ssoct_plan* p, const double* lambda, double pitch, double z, c
 
 // Persistent column workgroups: the tuned count, else the default for N and
 // the column tile width in use (ct; 0 = the default tile)
+// twiddle table of the forward column transforms' radix order
+static const float2* col_tw(const ssoct_plan* p) { return p->col_radix ? p->tw1 : p->tw; }
+
 static int col_grid_of(const ssoct_plan* p, int ct = 0) {
   return p->col_grid > 0 ? p->col_grid : col_default_grid(p->N, p->cu, ct);
 }
@@ -329,8 +333,8 @@ int render_chunk(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws,
   float2* inter = reinterpret_cast<float2*>(ws + L.inter);
   const float* ab = p->have_aberr ? p->apoly : nullptr;
   SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
-  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma, col_grid_of(p, p->col_tile), s,
-                            p->col_tile));
+  SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, col_tw(p), p->outfac, ws + L.H, fmt, p->sigma,
+                            col_grid_of(p, p->col_tile), s, p->col_tile, p->col_radix));
   return SSOCT_OK;
 }
 
@@ -391,8 +395,8 @@ static int render_depth_first(ssoct_plan* p, hipStream_t s, const uint16_t* fram
     const int ca = qa > 1 ? qa : 1;
     const int cb = qa + n < nconj ? qa + n : nconj;
     const int nm = cb > ca ? cb - ca : 0;
-    SSOCT_HIP(launch_col_pass_v(N, n, inter, p->tw, p->outfac, V + (size_t)qa * P, +1, cg, p->col_tile, s, nm,
-                                inter + (size_t)(fh + ca - qa) * P, V + (size_t)(T - ca) * P, -1));
+    SSOCT_HIP(launch_col_pass_v(N, n, inter, col_tw(p), p->outfac, V + (size_t)qa * P, +1, cg, p->col_tile, s, nm,
+                                inter + (size_t)(fh + ca - qa) * P, V + (size_t)(T - ca) * P, -1, p->col_radix));
     if (kev) SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
   }
   if (ev) SSOCT_HIP(hipEventRecord(ev[3], s));
@@ -412,8 +416,8 @@ int render_core(ssoct_plan* p, hipStream_t s, const uint16_t* frames, char* ws, 
       const int Fc = T - t0 < F ? T - t0 : F;
       SSOCT_HIP(launch_row_pass(N, Fc, t0, frames, p->rows, p->cols, p->tw, ab, p->outfac, inter, s));
       SSOCT_HIP(hipEventRecord(kev[2 * c], s));
-      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, p->tw, p->outfac, ws + L.H, fmt, p->sigma,
-                                col_grid_of(p, p->col_tile), s, p->col_tile));
+      SSOCT_HIP(launch_col_pass(N, Fc, t0, inter, col_tw(p), p->outfac, ws + L.H, fmt, p->sigma,
+                                col_grid_of(p, p->col_tile), s, p->col_tile, p->col_radix));
       SSOCT_HIP(hipEventRecord(kev[2 * c + 1], s));
     }
   } else {
@@ -532,6 +536,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess) e = hipMalloc(&p->rows, axis);
   if (e == hipSuccess) e = hipMalloc(&p->cols, axis);
   if (e == hipSuccess) e = hipMalloc(&p->tw, (ntw > 0 ? ntw : 1) * sizeof(float2));
+  if (e == hipSuccess && has_radix_orders(N)) e = hipMalloc(&p->tw1, twiddle_table_size(N, 1) * sizeof(float2));
   if (e == hipSuccess && (flags & SSOCT_EQ6_PHASE)) e = hipMalloc(&p->outfac, (size_t)N * sizeof(float2));
   // the aberration screen's row polynomials (N x 8 floats): allocated here, so that a render never allocates
   if (e == hipSuccess) e = hipMalloc(&p->apoly, (size_t)N * APOLY_STRIDE * sizeof(float));
@@ -551,6 +556,7 @@ int ssoct_plan_create(ssoct_plan** plan, int T, int N, uint32_t flags, hipStream
   if (e == hipSuccess && (flags & SSOCT_ANGULAR_SPECTRUM)) e = hipMalloc(&p->as_params, (size_t)3 * T * sizeof(double));
   if (e == hipSuccess && !p->general) e = launch_depth_tables(T, nullptr, p->a_f32, p->a_f16, p->a_bf16, stream);
   if (e == hipSuccess) e = launch_twiddles(N, p->tw, stream);
+  if (e == hipSuccess && p->tw1) e = launch_twiddles(N, p->tw1, stream, 1);
   if (e == hipSuccess) e = hipMalloc(&p->dtw, (size_t)T * sizeof(float2));
   if (e == hipSuccess) e = launch_depth_twiddles(T, p->dtw, stream);
   if (e == hipSuccess && (flags & SSOCT_DEPTH_4STEP)) e = hipMalloc(&p->f4ops, depth_4step_ops_bytes());
@@ -829,6 +835,7 @@ int ssoct_plan_get_tuning(const ssoct_plan* p, int* tuning) {
   tuning[5] = p->col_tile;
   tuning[6] = p->dfft_px;
   tuning[7] = p->depth_kc;
+  tuning[8] = p->col_radix;
   return SSOCT_OK;
 }
 
@@ -851,6 +858,9 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
     return fail(SSOCT_EINVAL, "the factored depth form takes 16 or 32 pixels per workgroup");
   if (tuning[7] != 0 && (tuning[7] != p->dl.KC / 2 || tuning[7] < 32))
     return fail(SSOCT_EINVAL, "dense depth K chunk must be 0 or half the default chunk (at least 32 frames)");
+  if (tuning[8] != 0 &&
+      (tuning[8] != 1 || !has_radix_orders(p->N) || (p->flags & SSOCT_ANGULAR_SPECTRUM)))
+    return fail(SSOCT_EINVAL, "radix order must be 0, or 1 for a Fresnel plan whose N is not a power of 16");
   if (p->streaming && tuning[3] != p->order) return fail(SSOCT_EINVAL, "the order is fixed while a stream uses the plan");
   p->F_run = tuning[0];
   p->col_grid = tuning[1];
@@ -860,6 +870,7 @@ int ssoct_plan_set_tuning(ssoct_plan* p, const int* tuning) {
   p->col_tile = tuning[5] == ct[0] ? 0 : tuning[5];
   p->dfft_px = tuning[6];
   p->depth_kc = tuning[7];
+  p->col_radix = tuning[8];
   return SSOCT_OK;
 }
 
@@ -942,6 +953,10 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
     if (ct[1]) ++nt;
     if (ct[2]) ++nt;
     search(&p->col_tile, tiles, nt, false);
+    if (has_radix_orders(p->N)) {   // radix order of the column transforms
+      const int Rx[2] = {0, 1};
+      search(&p->col_radix, Rx, 2, false);
+    }
   }
   {
     const int c0 = (p->flags & SSOCT_ANGULAR_SPECTRUM) ? p->as_col_grid0 : col_default_grid(p->N, p->cu, p->col_tile);

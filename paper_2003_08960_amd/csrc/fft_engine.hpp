@@ -13,9 +13,16 @@
 //
 // Register convention shared by every kernel that uses the engine:
 //   input : v[k] = x[j + k G]                      (k = 0..15)
-//   output: v[e] = X[j + out_offset<N>(e)]         (e = 0..15)
+//   output: v[e] = X[j + out_offset<N, PL>(e)]     (e = 0..15)
 // so for every register slot the G threads of a group touch G consecutive
 // elements (coalesced global loads and stores).
+//
+// Radix order PL: 0 runs the radix-16 passes first and the small radix
+// (2, 4 or 8) last (16 16 4 at N = 1024); 1 runs the small radix first
+// (4 16 16), which puts the output in the input's order (out_offset = e G)
+// at the price of twiddles on every radix-16 pass.  Both are Stockham
+// passes of the same DFT; they differ in rounding only.  Sizes that are a
+// power of 16 have one order.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -144,11 +151,11 @@ struct FFTShape {
 // LDS slot of element i (one pad slot every 16 keeps stride-16 writes conflict-free)
 __device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
 
-// output register e of thread j holds element j + out_offset<N>(e)
-template <int N>
+// output register e of thread j holds element j + out_offset<N, PL>(e)
+template <int N, int PL = 0>
 __device__ __forceinline__ constexpr int out_offset(int e) {
   using S = FFTShape<N>;
-  if constexpr (S::L == 1) {
+  if constexpr (S::L == 1 || PL == 1) {
     return e * S::G;
   } else {
     return S::G * (e / S::L) + (e % S::L) * (N / S::L);
@@ -161,17 +168,21 @@ __device__ __forceinline__ constexpr int out_offset(int e) {
 //       s = (j mod Ns) N / (16 Ns), r = 1..15
 //   final radix-L pass (Ns = N/L):   entry i (L-1) + k-1 = exp(+2 pi i b k / N),
 //       b = j + G i, i = 0..16/L-1, k = 1..L-1
+// With the small radix first (PL = 1) every radix-16 pass p = 0..P16-1 has
+// twiddles (Ns = L 16^p), entry r-1 of thread j at off16(p) + 15 j, and
+// there is no radix-L table.
 // The table is built in FP64 on the GPU (tables.hip) from this same layout.
-template <int N>
+template <int N, int PL = 0>
 struct TwPlan {
   using S = FFTShape<N>;
+  static constexpr bool SMALL_FIRST = PL == 1 && S::L > 1;
   static constexpr int G = S::G;
   static constexpr int E16 = 15;
   static constexpr int NB = S::L > 1 ? 16 / S::L : 0;
-  static constexpr int EL = S::L > 1 ? NB * (S::L - 1) : 0;
-  static constexpr int OFF_L = (S::P16 - 1) * G * E16;
+  static constexpr int EL = S::L > 1 && !SMALL_FIRST ? NB * (S::L - 1) : 0;
+  static constexpr int OFF_L = (SMALL_FIRST ? S::P16 : S::P16 - 1) * G * E16;
   static constexpr int SIZE = OFF_L + G * EL;
-  static constexpr int off16(int p) { return (p - 1) * G * E16; }
+  static constexpr int off16(int p) { return (SMALL_FIRST ? p : p - 1) * G * E16; }
 };
 
 template <int DIR>
@@ -198,18 +209,22 @@ __device__ __forceinline__ void exchange_sync() {
 // j at every use; TwRegs holds the same entries in registers, loaded once by
 // a kernel that runs many transforms per thread, so that its loads can be
 // completed before the transform loop starts.
-template <int N>
+template <int N, int PL = 0>
 struct TwMem {
+  static constexpr int PLAN = PL;
   const float2* __restrict__ tw;
   int j;
   __device__ __forceinline__ float2 w16(int p, int r) const {
-    return tw[TwPlan<N>::off16(p) + j * TwPlan<N>::E16 + r - 1];
+    return tw[TwPlan<N, PL>::off16(p) + j * TwPlan<N, PL>::E16 + r - 1];
   }
-  __device__ __forceinline__ float2 wl(int i) const { return tw[TwPlan<N>::OFF_L + j * TwPlan<N>::EL + i]; }
+  __device__ __forceinline__ float2 wl(int i) const {
+    return tw[TwPlan<N, PL>::OFF_L + j * TwPlan<N, PL>::EL + i];
+  }
 };
 
 template <int N>
 struct TwRegs {
+  static constexpr int PLAN = 0;
   using S = FFTShape<N>;
   static constexpr int P = S::P16 > 1 ? S::P16 - 1 : 1;
   static constexpr int E = TwPlan<N>::EL > 0 ? TwPlan<N>::EL : 1;
@@ -242,11 +257,50 @@ __device__ __forceinline__ TwRegs<N> load_tw_regs(const float2* __restrict__ tw,
 // base plus an immediate offset).  With WAVE = false every thread of the
 // workgroup must call this the same number of times (workgroup barriers).
 // `tws` is a twiddle source (TwMem or TwRegs) for this thread.
+//
+// The twiddle source's PLAN picks the radix order; with the small radix
+// first, butterfly b = j + G i (i < 16/L) of the first pass takes elements
+// b + k N/L, which thread j holds in registers i + k 16/L.
 template <int N, int DIR, int LS, bool WAVE, class TW>
 __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds, const TW& tws) {
   constexpr int ls = LS;
   using S = FFTShape<N>;
   constexpr int G = S::G;
+  if constexpr (TwPlan<N, TW::PLAN>::SMALL_FIRST) {
+    constexpr int L = S::L;
+    constexpr int NB = 16 / L;
+    // Ns = 1: output k of butterfly b goes to b L + k
+    exchange_sync<WAVE>();  // previous reads of this region are complete
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      float2 u[L];
+#pragma unroll
+      for (int k = 0; k < L; ++k) u[k] = v[i + k * NB];
+      dft_small<L, DIR>(u);
+#pragma unroll
+      for (int k = 0; k < L; ++k) lds[lds_slot((j + G * i) * L + k) * ls] = u[k];
+    }
+    exchange_sync<WAVE>();
+    int Ns = L;
+#pragma unroll
+    for (int p = 0; p < S::P16; ++p) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_dir<DIR>(tws.w16(p, r)));
+      dft16<DIR>(v);
+      if (p < S::P16 - 1) {
+        const int base = (j / Ns) * Ns * 16 + (j % Ns);
+        exchange_sync<WAVE>();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds[lds_slot(base + k * Ns) * ls] = v[k];
+        exchange_sync<WAVE>();
+        Ns *= 16;
+      }
+    }
+    // the last pass has Ns = G: output k of thread j is element j + k G
+    return;
+  }
   int Ns = 1;
 #pragma unroll
   for (int p = 0; p < S::P16; ++p) {

@@ -83,9 +83,12 @@ constexpr int APOLY_STRIDE = 8;
 hipError_t launch_misc_tables(const double* params, int T, int N, float2* outfac, float* apoly, hipStream_t s);
 // The same screen as N x N complex factors (FP64 phases), for the adjoint row pass
 hipError_t launch_aberr_screen(const double* params, int T, int N, float2* screen, hipStream_t s);
-// FFT engine twiddles (per-thread layout), FP64 -> FP32; size in float2 entries
-hipError_t launch_twiddles(int N, float2* tw, hipStream_t s);
-size_t twiddle_table_size(int N);
+// FFT engine twiddles (per-thread layout of radix order pl: 0 = radix-16
+// passes first, 1 = the small radix first), FP64 -> FP32; size in float2 entries
+hipError_t launch_twiddles(int N, float2* tw, hipStream_t s, int pl = 0);
+size_t twiddle_table_size(int N, int pl = 0);
+// N has a second radix order (N is not a power of 16)
+inline bool has_radix_orders(int N) { return N != 16 && N != 256; }
 // kappa == nullptr: DFT matrix (paired real form); else the general matrix exp(-2 pi i q kappa_t / T)
 hipError_t launch_depth_tables(int T, const double* kappa, float* a_f32, uint4* a_f16, uint4* a_bf16,
                                hipStream_t s);
@@ -96,10 +99,11 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
                            const AxisTab* cols, const float2* tw, const float* apoly,
                            const float2* outfac, float2* inter, hipStream_t s);
 // ctile: column tile width (0 = default; col_tiles lists the choices; the
-// Eq. 6 output phase takes the default)
+// Eq. 6 output phase takes the default); radix: radix order of the column
+// transforms (0 or 1, tw the table of that order)
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw,
                            const float2* outfac, void* H, int fmt, int sigma, int grid, hipStream_t s,
-                           int ctile = 0);
+                           int ctile = 0, int radix = 0);
 // Default persistent grid of the column passes (forward, adjoint, volume
 // output) on a device with `cu` compute units, for column tile width ct (0 = default)
 int col_default_grid(int N, int cu, int ct = 0);
@@ -133,7 +137,8 @@ hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, cons
 // (consecutive frames) to V2 + i fstride2 N^2
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
                              int fstride, int grid, int ctile, hipStream_t s, int F2 = 0,
-                             const float2* inter2 = nullptr, float2* V2 = nullptr, int fstride2 = 0);
+                             const float2* inter2 = nullptr, float2* V2 = nullptr, int fstride2 = 0,
+                             int radix = 0);
 
 // Adjoint Fresnel stage: column DFT^- of B[t0 .. t0+F) ([T][N][N] complex64)
 // into `inter`, then row DFT^- fused with the recomputed row input and the

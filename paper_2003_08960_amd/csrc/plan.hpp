@@ -45,12 +45,14 @@ struct ssoct_plan {
   int rpg_g = 0;               // rows per row group of the bin-pair row pass (0 = by launch size; 2, 4, 8)
   int col_tile = 0;            // column tile width of the Fresnel column passes (0 = default)
   int depth_kc = 0;            // frames per K chunk of the dense depth product (0 = default; half of it)
+  int col_radix = 0;           // radix order of the forward column transforms (0: 16..16 L, 1: L 16..16)
   int dfft_px = 0;             // pixels per workgroup of the forward FFT (16, 32, 64) or factored (16, 32)
                                // depth transform (0 = default 32)
   // device tables
   ssoct::AxisTab* rows = nullptr;
   ssoct::AxisTab* cols = nullptr;
   float2* tw = nullptr;
+  float2* tw1 = nullptr;        // twiddles of the second radix order (N not a power of 16)
   float2* outfac = nullptr;
   float* apoly = nullptr;       // aberration screen, per-row polynomials [N][APOLY_STRIDE]
   float2* screen = nullptr;     // the same screen as N x N factors, built for the gradient entry points

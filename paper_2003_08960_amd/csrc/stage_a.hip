@@ -112,11 +112,11 @@ struct ColTiles {
   static constexpr int C4 = ALT ? C / 4 : C;
 };
 // LDS of the column pass: the exchange buffer of CT columns, plus the twiddle
-// table where the two fit in one CU's 160 KB (every N <= 1024)
-template <int N, int CT>
+// table of radix order PL where the two fit in one CU's 160 KB (every N <= 1024)
+template <int N, int CT, int PL = 0>
 struct ColLdsT {
   static constexpr int XB = FFTShape<N>::LDS * CT;
-  static constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
+  static constexpr int TWN = TwPlan<N, PL>::SIZE > 0 ? TwPlan<N, PL>::SIZE : 1;
   static constexpr bool TWL = SSOCT_COL_TWL && (XB + TWN) * 8 <= 163840;
   static constexpr bool PF = TWL || SSOCT_COL_PREFETCH;    // next tile prefetched into registers
   static constexpr int BYTES = (XB + (TWL ? TWN : 1)) * 8;
@@ -633,8 +633,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_as_row_inv(const float2*
 // f fstride of dst; frames f >= nA read src2 + (f - nA) N^2 and write frame
 // (f - nA) fstride2 of dst2 (two runs of frames in one launch).
 // DIR = +1 writes H in format FMT (and the Eq. 6 output phase when EQ6);
-// DIR = -1 writes complex64.
-template <int N, int DIR, int FMT, bool EQ6, int CT = ColCfg<N>::C>
+// DIR = -1 writes complex64.  PL is the radix order of the transforms.
+template <int N, int DIR, int FMT, bool EQ6, int CT = ColCfg<N>::C, int PL = 0>
 __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* __restrict__ src,
                                                                   const float2* __restrict__ tw,
                                                                   const float2* __restrict__ outfac,
@@ -650,10 +650,11 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
   // prefetch of the next tile, which then loads while the current one is
   // transformed: one 1024-thread workgroup fills a CU, so without it the
   // CU's memory and ALUs take turns.
-  constexpr bool TWL = ColLdsT<N, CT>::TWL;
-  constexpr bool PF = ColLdsT<N, CT>::PF;
-  __shared__ float2 xbuf[ColLdsT<N, CT>::XB];
-  __shared__ float2 twl[TWL ? ColLdsT<N, CT>::TWN : 1];
+  using LT = ColLdsT<N, CT, PL>;
+  constexpr bool TWL = LT::TWL;
+  constexpr bool PF = LT::PF;
+  __shared__ float2 xbuf[LT::XB];
+  __shared__ float2 twl[TWL ? LT::TWN : 1];
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   float2 pf[16];
   auto issue = [&](int tile) {
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
   int tile = blockIdx.x;
   if (PF && tile < ntiles) issue(tile);
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < TwPlan<N>::SIZE; i += (CT * G)) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < TwPlan<N, PL>::SIZE; i += (CT * G)) twl[i] = tw[i];
     // the first tile has landed; the loop is entered with no load
     // outstanding, so waiting for a prefetched tile inside it leaves the
     // previous tile's stores in flight
@@ -685,13 +686,13 @@ __global__ __launch_bounds__(CT * FFTShape<N>::G) void k_col_pass(const float2* 
       for (int k = 0; k < 16; ++k) v[k] = pf[k];
     }
     const int f = tile / NCB, col = (tile % NCB) * C + c;
-    if constexpr (TWL) fft_group_tw<N, DIR, C, false>(v, j, xbuf + c, TwMem<N>{twl, j});
-    else fft_group<N, DIR, C>(v, j, xbuf + c, tw);
+    if constexpr (TWL) fft_group_tw<N, DIR, C, false>(v, j, xbuf + c, TwMem<N, PL>{twl, j});
+    else fft_group_tw<N, DIR, C, false>(v, j, xbuf + c, TwMem<N, PL>{tw, j});
     void* d = f < nA ? dst : dst2;
     const long long fo = (f < nA ? (long long)f * fstride : (long long)(f - nA) * fstride2) * N * N;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int u = j + out_offset<N>(e);
+      const int u = j + out_offset<N, PL>(e);
       float2 val = v[e];
       if constexpr (EQ6) val = cmul(val, outfac[u]);
       store_h<FMT, (DIR > 0 ? SSOCT_COL_NT : SSOCT_ADJ_NT)>(d, fo + (long long)u * N + col, val, scale);
@@ -894,15 +895,16 @@ void col_tiles(int N, int* out) {
   }
 }
 
-// forward column pass of tile width CT (with the Eq. 6 output phase when outfac is given)
-template <int N, int CT>
-static hipError_t col_pass_nt(int F, const float2* inter, const float2* tw, const float2* outfac, void* dst, int fmt,
-                              float scale, int req_grid, int fstride, hipStream_t s, int F2 = 0,
-                              const float2* inter2 = nullptr, void* dst2 = nullptr, int fstride2 = 0) {
+// forward column pass of tile width CT and radix order PL (with the Eq. 6
+// output phase when outfac is given)
+template <int N, int CT, int PL>
+static hipError_t col_pass_ntp(int F, const float2* inter, const float2* tw, const float2* outfac, void* dst, int fmt,
+                               float scale, int req_grid, int fstride, hipStream_t s, int F2,
+                               const float2* inter2, void* dst2, int fstride2) {
   const int ntiles = (F + F2) * (N / CT);
   dim3 grid(col_grid(ntiles, req_grid)), block(CT * FFTShape<N>::G);
-#define SSOCT_COL(FMT, E)                                                                                        \
-  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E, CT>), grid, block, 0, s, inter, tw, outfac, dst, scale, ntiles, \
+#define SSOCT_COL(FMT, E)                                                                                            \
+  hipLaunchKernelGGL((k_col_pass<N, +1, FMT, E, CT, PL>), grid, block, 0, s, inter, tw, outfac, dst, scale, ntiles, \
                      fstride, inter2, dst2, F, fstride2)
   if (fmt == HF_F32) { if (outfac) SSOCT_COL(HF_F32, true); else SSOCT_COL(HF_F32, false); }
   else if (fmt == HF_F16) { if (outfac) SSOCT_COL(HF_F16, true); else SSOCT_COL(HF_F16, false); }
@@ -911,17 +913,35 @@ static hipError_t col_pass_nt(int F, const float2* inter, const float2* tw, cons
   return hipGetLastError();
 }
 
+// the same for a runtime radix order (sizes that are a power of 16 have one)
+template <int N, int CT>
+static hipError_t col_pass_nt(int F, const float2* inter, const float2* tw, const float2* outfac, void* dst, int fmt,
+                              float scale, int req_grid, int fstride, hipStream_t s, int F2 = 0,
+                              const float2* inter2 = nullptr, void* dst2 = nullptr, int fstride2 = 0,
+                              int radix = 0) {
+  if constexpr (FFTShape<N>::L > 1) {
+    if (radix == 1)
+      return col_pass_ntp<N, CT, 1>(F, inter, tw, outfac, dst, fmt, scale, req_grid, fstride, s, F2, inter2, dst2,
+                                    fstride2);
+  }
+  if (radix != 0) return hipErrorInvalidValue;
+  return col_pass_ntp<N, CT, 0>(F, inter, tw, outfac, dst, fmt, scale, req_grid, fstride, s, F2, inter2, dst2,
+                                fstride2);
+}
+
 // ctile: column tile width (the default ColCfg<N>::C, or one of the narrower
 // ColTiles alternatives)
 template <int N>
 static hipError_t col_pass_n(int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                             int fmt, int sigma, int req_grid, int ctile, hipStream_t s) {
+                             int fmt, int sigma, int req_grid, int ctile, int radix, hipStream_t s) {
   using K = ColTiles<N>;
   const float scale = ldexpf(1.0f, -sigma);
   char* dst = reinterpret_cast<char*>(H) + (size_t)t0 * N * N * 8;
-  if (K::ALT && ctile == K::C2) return col_pass_nt<N, K::C2>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
-  if (K::ALT && ctile == K::C4) return col_pass_nt<N, K::C4>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
-  return col_pass_nt<N, K::C>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s);
+#define SSOCT_COLN(CT) col_pass_nt<N, CT>(F, inter, tw, outfac, dst, fmt, scale, req_grid, 1, s, 0, nullptr, nullptr, 0, radix)
+  if (K::ALT && ctile == K::C2) return SSOCT_COLN(K::C2);
+  if (K::ALT && ctile == K::C4) return SSOCT_COLN(K::C4);
+  return SSOCT_COLN(K::C);
+#undef SSOCT_COLN
 }
 
 template <int N>
@@ -1005,10 +1025,10 @@ static hipError_t row_pass_g_n(int nb, int qa, int T, const float2* G, const Axi
 template <int N>
 static hipError_t col_pass_v_n(int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
                                int fstride, int req_grid, int ctile, hipStream_t s, int F2, const float2* inter2,
-                               float2* V2, int fstride2) {
+                               float2* V2, int fstride2, int radix) {
   using K = ColTiles<N>;
 #define SSOCT_COLV(CT) \
-  col_pass_nt<N, CT>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s, F2, inter2, V2, fstride2)
+  col_pass_nt<N, CT>(F, inter, tw, outfac, V, HF_F32, 1.0f, req_grid, fstride, s, F2, inter2, V2, fstride2, radix)
   if (K::ALT && ctile == K::C2) return SSOCT_COLV(K::C2);
   if (K::ALT && ctile == K::C4) return SSOCT_COLV(K::C4);
   return SSOCT_COLV(K::C);
@@ -1025,9 +1045,9 @@ hipError_t launch_row_pass_g(int N, int nb, int qa, int T, const float2* G, cons
 
 hipError_t launch_col_pass_v(int N, int F, const float2* inter, const float2* tw, const float2* outfac, float2* V,
                              int fstride, int grid, int ctile, hipStream_t s, int F2, const float2* inter2,
-                             float2* V2, int fstride2) {
+                             float2* V2, int fstride2, int radix) {
   if (F2 > 0 && !(inter2 && V2)) return hipErrorInvalidValue;
-#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, ctile, s, F2, inter2, V2, fstride2)
+#define CALL(n) col_pass_v_n<n>(F, inter, tw, outfac, V, fstride, grid, ctile, s, F2, inter2, V2, fstride2, radix)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }
@@ -1066,8 +1086,8 @@ hipError_t launch_row_pass(int N, int F, int t0, const uint16_t* frames, const A
 }
 
 hipError_t launch_col_pass(int N, int F, int t0, const float2* inter, const float2* tw, const float2* outfac, void* H,
-                           int fmt, int sigma, int grid, hipStream_t s, int ctile) {
-#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, grid, ctile, s)
+                           int fmt, int sigma, int grid, hipStream_t s, int ctile, int radix) {
+#define CALL(n) col_pass_n<n>(F, t0, inter, tw, outfac, H, fmt, sigma, grid, ctile, radix, s)
   SSOCT_DISPATCH_N(N, CALL)
 #undef CALL
 }

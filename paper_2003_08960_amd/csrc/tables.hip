@@ -66,18 +66,21 @@ __device__ __forceinline__ double mono(int k, double x, double y) {
   return r;
 }
 
-// Per-thread twiddle table of the FFT engine (layout: TwPlan in fft_engine.hpp).
-template <int N>
+// Per-thread twiddle table of the FFT engine (layout: TwPlan in fft_engine.hpp)
+// for radix order PL.
+template <int N, int PL>
 __global__ void k_twiddles(float2* __restrict__ tw) {
-  using P = TwPlan<N>;
+  using P = TwPlan<N, PL>;
   using S = FFTShape<N>;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P::SIZE) return;
   long long num;
   if (idx < P::OFF_L) {
-    const int p = idx / (P::G * P::E16) + 1, rem = idx % (P::G * P::E16);
+    // radix-16 pass p (counted from 0 over all of them) has stride
+    // Ns = 16^p, or L 16^p when the small radix runs first
+    const int p = idx / (P::G * P::E16) + (P::SMALL_FIRST ? 0 : 1), rem = idx % (P::G * P::E16);
     const int j = rem / P::E16, r = rem % P::E16 + 1;
-    const int Ns = 1 << (4 * p);
+    const int Ns = (P::SMALL_FIRST ? S::L : 1) << (4 * p);
     num = (long long)((j % Ns) * (N / (Ns * 16))) * r;
   } else {
     const int rem = idx - P::OFF_L, j = rem / P::EL, e = rem % P::EL;
@@ -90,37 +93,46 @@ __global__ void k_twiddles(float2* __restrict__ tw) {
 }
 
 template <int N>
-static hipError_t twiddles_n(float2* tw, hipStream_t s) {
-  constexpr int n = TwPlan<N>::SIZE;
+static hipError_t twiddles_n(float2* tw, int pl, hipStream_t s) {
+  const int n = pl ? TwPlan<N, 1>::SIZE : TwPlan<N, 0>::SIZE;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_twiddles<N>, dim3((n + 255) / 256), dim3(256), 0, s, tw);
+  if (pl)
+    hipLaunchKernelGGL((k_twiddles<N, 1>), dim3((n + 255) / 256), dim3(256), 0, s, tw);
+  else
+    hipLaunchKernelGGL((k_twiddles<N, 0>), dim3((n + 255) / 256), dim3(256), 0, s, tw);
   return hipGetLastError();
 }
 
-hipError_t launch_twiddles(int N, float2* tw, hipStream_t s) {
+hipError_t launch_twiddles(int N, float2* tw, hipStream_t s, int pl) {
+  if (pl != 0 && pl != 1) return hipErrorInvalidValue;
   switch (N) {
-    case 16: return twiddles_n<16>(tw, s);
-    case 32: return twiddles_n<32>(tw, s);
-    case 64: return twiddles_n<64>(tw, s);
-    case 128: return twiddles_n<128>(tw, s);
-    case 256: return twiddles_n<256>(tw, s);
-    case 512: return twiddles_n<512>(tw, s);
-    case 1024: return twiddles_n<1024>(tw, s);
-    case 2048: return twiddles_n<2048>(tw, s);
+    case 16: return twiddles_n<16>(tw, pl, s);
+    case 32: return twiddles_n<32>(tw, pl, s);
+    case 64: return twiddles_n<64>(tw, pl, s);
+    case 128: return twiddles_n<128>(tw, pl, s);
+    case 256: return twiddles_n<256>(tw, pl, s);
+    case 512: return twiddles_n<512>(tw, pl, s);
+    case 1024: return twiddles_n<1024>(tw, pl, s);
+    case 2048: return twiddles_n<2048>(tw, pl, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-size_t twiddle_table_size(int N) {
+template <int N>
+static size_t tw_size_n(int pl) {
+  return pl ? TwPlan<N, 1>::SIZE : TwPlan<N, 0>::SIZE;
+}
+
+size_t twiddle_table_size(int N, int pl) {
   switch (N) {
-    case 16: return TwPlan<16>::SIZE;
-    case 32: return TwPlan<32>::SIZE;
-    case 64: return TwPlan<64>::SIZE;
-    case 128: return TwPlan<128>::SIZE;
-    case 256: return TwPlan<256>::SIZE;
-    case 512: return TwPlan<512>::SIZE;
-    case 1024: return TwPlan<1024>::SIZE;
-    case 2048: return TwPlan<2048>::SIZE;
+    case 16: return tw_size_n<16>(pl);
+    case 32: return tw_size_n<32>(pl);
+    case 64: return tw_size_n<64>(pl);
+    case 128: return tw_size_n<128>(pl);
+    case 256: return tw_size_n<256>(pl);
+    case 512: return tw_size_n<512>(pl);
+    case 1024: return tw_size_n<1024>(pl);
+    case 2048: return tw_size_n<2048>(pl);
     default: return 0;
   }
 }

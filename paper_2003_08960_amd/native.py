@@ -38,7 +38,7 @@ DEPTH_FFT = 1024
 NONUNIFORM_K = 2048
 ANGULAR_SPECTRUM = 4096
 DEPTH_4STEP = 8192
-TUNING_LEN = 8          # entries of a plan's launch-shape tuning array (SSOCT_TUNING_LEN)
+TUNING_LEN = 9          # entries of a plan's launch-shape tuning array (SSOCT_TUNING_LEN)
 
 EXPORTS = (
     "ssoct_version", "ssoct_last_error", "ssoct_workspace_size", "ssoct_plan_create",

@@ -38,6 +38,7 @@ def make_case(seed):
     lam = synth.sweep_wavelengths(T, 870e-9, 800e-9, bend=bend) if T > 1 else np.array([850e-9])
     pitch = float(rng.choice([8e-6, 12e-6, 20e-6]))
     z = float(rng.choice([0.01, 0.05, 0.3])) if prop == "fresnel" else float(rng.choice([-0.003, 0.002, 0.01]))
+    opts["radix"] = int(rng.random() < 0.5) if prop == "fresnel" and N not in (16, 256) else 0
     frames = synth.random_frames(T, N, seed=seed, lo=0, hi=65535)
     return form, prop, T, N, lam, pitch, z, frames, opts
 
@@ -53,7 +54,7 @@ def test_random_configuration(gpu_lib, seed):
     if o["gate"] is not None:
         plan.set_gate(o["gate"])
     tun = plan.get_tuning()
-    plan.set_tuning([min(o["chunk"], tun[0]), 0, 0, o["order"]])
+    plan.set_tuning([min(o["chunk"], tun[0]), 0, 0, o["order"], 0, 0, 0, 0, o["radix"]])
     V = plan.render(torch.from_numpy(frames).cuda(), lam, pitch, z, o["disp"], o.get("zern")).cpu().numpy()
     if prop == "as":
         ref = O.render_as(frames, lam, pitch, z, o["disp"], o["gate"], o["nonuniform_k"])

@@ -484,6 +484,53 @@ def test_five_argument_render(gpu_lib, tiny):
 
 # ---------------------------------------------------------------- tuning alternatives (tiles, row groups)
 
+@pytest.mark.parametrize("N,T", [(32, 16), (64, 16), (128, 16), (512, 16), (1024, 16), (2048, 2)])
+def test_radix_orders_agree(gpu_lib, N, T):
+    """Tuning entry 8: the column transforms with the small radix first (L 16 .. 16) and in the
+    default order (16 .. 16 L) each meet the oracle bar, in the frame order with complex64 and
+    BF16-split H and in the FFT form's depth-first order; the two orders differ by rounding only."""
+    from paper_2003_08960_amd.api import Plan
+    frames, lam = random_case(T, N, seed=500 + N)
+    fr = torch.from_numpy(frames).cuda()
+    ref = O.render(frames, lam, 20e-6, 0.05)
+    cases = [("fp32", 0), ("bf16_split", 0)] + ([("fp32_fft", 0), ("fp32_fft", 1)] if T >= 16 else [])
+    for precision, order in cases:
+        print(f"\n[gpu] radix orders N={N} T={T} {precision} order {order}", flush=True)
+        bar = SPLIT_BAR if "split" in precision else FP32_BAR
+        plan = Plan(T, N, precision=precision)
+        vols = []
+        for radix in (0, 1):
+            t = plan.get_tuning()
+            t[3], t[8] = order, radix
+            plan.set_tuning(t)
+            assert plan.get_tuning()[8] == radix
+            V = plan.render(fr, lam, 20e-6, 0.05).cpu().numpy()
+            err = rel_l2(V, ref)
+            print(f"radix order {radix}: rel-L2 {err:.3e}")
+            assert err <= bar, (precision, order, radix)
+            vols.append(V)
+        assert rel_l2(vols[1], vols[0]) <= (SPLIT_BAR if "split" in precision else 2e-6)
+        plan.close()
+
+
+def test_radix_order_rejected_where_there_is_one(gpu_lib):
+    """N = 16 and 256 are powers of 16 (one radix order), and the angular-spectrum column pass has
+    one order: tuning entry 8 = 1 is an error there, and any value other than 0 or 1 everywhere."""
+    from paper_2003_08960_amd.api import Plan
+    for N, kw in ((16, {}), (256, {}), (1024, {"angular_spectrum": True})):
+        plan = Plan(4, N, **kw)
+        with pytest.raises(native.SsoctError):
+            plan.set_tuning([0, 0, 0, 0, 0, 0, 0, 0, 1])
+        plan.close()
+    plan = Plan(4, 512)
+    for bad in (2, -1):
+        with pytest.raises(native.SsoctError):
+            plan.set_tuning([0, 0, 0, 0, 0, 0, 0, 0, bad])
+    plan.set_tuning([0, 0, 0, 0, 0, 0, 0, 0, 1])
+    assert plan.get_tuning()[8] == 1
+    plan.close()
+
+
 @pytest.mark.parametrize("T", [64, 256])
 def test_dense_k_chunk_changes_speed_not_results(gpu_lib, T):
     """Tuning entry 7: the dense depth product with half its default K chunk (32 of 64, 128 of 256
