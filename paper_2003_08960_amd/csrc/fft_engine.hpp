@@ -149,7 +149,11 @@ struct FFTShape {
 };
 
 // LDS slot of element i (one pad slot every 16 keeps stride-16 writes conflict-free)
-__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+__device__ __forceinline__ constexpr int lds_slot(int i) { return i + (i >> 4); }
+// slot(a + b) = slot(a) + slot(b) whenever (a mod 16) + (b mod 16) < 16.  Every
+// exchange index below is split that way into a per-thread part and a
+// compile-time part, so that the LDS accesses of a thread share one base
+// address and take immediate offsets (the condition is noted at each use).
 
 // output register e of thread j holds element j + out_offset<N, PL>(e)
 template <int N, int PL = 0>
@@ -278,22 +282,26 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
       for (int k = 0; k < L; ++k) u[k] = v[i + k * NB];
       dft_small<L, DIR>(u);
 #pragma unroll
-      for (int k = 0; k < L; ++k) lds[lds_slot((j + G * i) * L + k) * ls] = u[k];
+      // (j + G i) L + k = L j + (L G i + k): L j mod 16 is a multiple of L, at
+      // most L (G - 1) when L G < 16 (else 16 - L), and L G i mod 16 + k
+      // at most 16 - L G + L - 1 (else L - 1), so the sums stay below 16
+      for (int k = 0; k < L; ++k) lds[(lds_slot(L * j) + lds_slot(L * G * i + k)) * ls] = u[k];
     }
     exchange_sync<WAVE>();
     int Ns = L;
+    const int sj = lds_slot(j);
 #pragma unroll
     for (int p = 0; p < S::P16; ++p) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+      for (int k = 0; k < 16; ++k) v[k] = lds[(sj + lds_slot(k * G)) * ls];   // see read_slots
 #pragma unroll
       for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw_dir<DIR>(tws.w16(p, r)));
       dft16<DIR>(v);
       if (p < S::P16 - 1) {
-        const int base = (j / Ns) * Ns * 16 + (j % Ns);
+        const int sb = lds_slot((j / Ns) * Ns * 16 + (j % Ns));
         exchange_sync<WAVE>();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lds[lds_slot(base + k * Ns) * ls] = v[k];
+        for (int k = 0; k < 16; ++k) lds[(sb + lds_slot(k * Ns)) * ls] = v[k];   // see write_slots
         exchange_sync<WAVE>();
         Ns *= 16;
       }
@@ -301,6 +309,12 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
     // the last pass has Ns = G: output k of thread j is element j + k G
     return;
   }
+  // write_slots: base = (j / Ns) 16 Ns + j mod Ns has base mod 16 = j mod Ns
+  // < Ns when Ns < 16 (Ns divides 16, so k Ns mod 16 <= 16 - Ns), and k Ns
+  // mod 16 = 0 otherwise.  read_slots: j + k G (and the last pass's
+  // j + G (i + k 16/L)) with j < G: G >= 16 gives k G mod 16 = 0, and G < 16
+  // (a divisor of 16) gives j < G and k G mod 16 <= 16 - G.
+  const int sj = lds_slot(j);
   int Ns = 1;
 #pragma unroll
   for (int p = 0; p < S::P16; ++p) {
@@ -311,19 +325,19 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
     dft16<DIR>(v);
     const bool last = (p == S::P16 - 1) && (S::L == 1);
     if (!last) {
-      const int base = (j / Ns) * Ns * 16 + (j % Ns);
+      const int sb = lds_slot((j / Ns) * Ns * 16 + (j % Ns));
       exchange_sync<WAVE>();  // previous reads of this region are complete
 #pragma unroll
-      for (int k = 0; k < 16; ++k) lds[lds_slot(base + k * Ns) * ls] = v[k];
+      for (int k = 0; k < 16; ++k) lds[(sb + lds_slot(k * Ns)) * ls] = v[k];
       exchange_sync<WAVE>();
       Ns *= 16;
       if constexpr (S::L == 1) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+        for (int k = 0; k < 16; ++k) v[k] = lds[(sj + lds_slot(k * G)) * ls];
       } else {
         if (p < S::P16 - 1) {
 #pragma unroll
-          for (int k = 0; k < 16; ++k) v[k] = lds[lds_slot(j + k * G) * ls];
+          for (int k = 0; k < 16; ++k) v[k] = lds[(sj + lds_slot(k * G)) * ls];
         }
       }
     }
@@ -335,7 +349,7 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
 #pragma unroll
-      for (int k = 0; k < L; ++k) v[i * L + k] = lds[lds_slot(j + G * i + k * (N / L)) * ls];
+      for (int k = 0; k < L; ++k) v[i * L + k] = lds[(sj + lds_slot(G * i + k * (N / L))) * ls];
     }
     if constexpr (S::P16 > 0) {
 #pragma unroll

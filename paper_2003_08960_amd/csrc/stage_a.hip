@@ -34,7 +34,7 @@ namespace ssoct {
 #define SSOCT_AS_GROUP 0         // > 0: phase evaluations scheduled in groups of this many
 #endif
 #ifndef SSOCT_AS_PF
-#define SSOCT_AS_PF 0            // 1: transfer-function column pass loads its next tile while transforming (two workgroups per CU instead of three)
+#define SSOCT_AS_PF 1            // 1: transfer-function column pass loads its next tile while transforming
 #endif
 #ifndef SSOCT_AS_WPE
 #define SSOCT_AS_WPE 0           // > 0: waves per SIMD the transfer-function column pass is compiled for
@@ -303,8 +303,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
 // into chunk frame Fh + f.  The column pass turns these into V[q] and
 // V[T - q] (Eq. 6 is linear and its chirp does not depend on the frame when
 // lambda_1 is used for every frame and no per-frame phase is applied).
+// Without the aberration factor the kernel fits two waves per SIMD; the
+// compiler is held to that (with the Eq. 6 output factor it would otherwise
+// take a few registers more and keep one).
 template <int N, bool ABERR, bool EQ6, int RPG>
-__global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass_g(
+__global__ __launch_bounds__(RowCfg<N>::THREADS)
+__attribute__((amdgpu_waves_per_eu(ABERR ? 1 : 2))) void k_row_pass_g(
     const float2* __restrict__ Gq, int qa, int T, const AxisTab* __restrict__ rows0,
     const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float* __restrict__ apoly,
     const float2* __restrict__ outfac, float2* __restrict__ inter, int Fh) {
@@ -494,9 +498,9 @@ __global__ __launch_bounds__(AsColCfg<N>::THREADS) SSOCT_AS_OCC void k_as_col(fl
   // buffer where it fits.  With SSOCT_AS_PF the freed registers hold the
   // next tile, loaded while the current one is transformed (tiles are
   // disjoint and each belongs to one workgroup, so the prefetch never reads
-  // a column that is being written in place); without it the kernel needs
-  // 168 VGPRs and three workgroups share a CU, which covers the loads better
-  // at N = 1024.
+  // a column that is being written in place).  At N = 1024 the kernel then
+  // holds 138 VGPRs, and three workgroups share a CU (the LDS allows three)
+  // as they do without the prefetch at 165 VGPRs.
   constexpr int TWN = TwPlan<N>::SIZE > 0 ? TwPlan<N>::SIZE : 1;
   constexpr bool TWL = SSOCT_COL_TWL && (S::LDS * C + TWN) * 8 <= 163840;
   constexpr bool PF = TWL && SSOCT_AS_PF;
