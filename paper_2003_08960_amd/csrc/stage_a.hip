@@ -71,6 +71,9 @@ namespace ssoct {
 #define SSOCT_ADJ_NT 0           // adjoint column pass: non-temporal stores of the intermediate the
                                  // adjoint row pass reads back (a chunk sized to stay in MALL)
 #endif
+#ifndef SSOCT_ROWG_WPE
+#define SSOCT_ROWG_WPE 2          // waves per SIMD the bin-pair row pass is held to (no aberration, no Eq. 6 factor)
+#endif
 #ifndef SSOCT_ROW_WAVES_PER_EU
 #define SSOCT_ROW_WAVES_PER_EU 0  // > 0: ask the compiler to fit this many row-pass waves per SIMD
 #endif
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) SSOCT_ROW_OCC void k_row_pass(
 // take a few registers more and keep one).
 template <int N, bool ABERR, bool EQ6, int RPG>
 __global__ __launch_bounds__(RowCfg<N>::THREADS)
-__attribute__((amdgpu_waves_per_eu(ABERR ? 1 : 2))) void k_row_pass_g(
+__attribute__((amdgpu_waves_per_eu(ABERR ? 1 : (EQ6 ? 2 : SSOCT_ROWG_WPE)))) void k_row_pass_g(
     const float2* __restrict__ Gq, int qa, int T, const AxisTab* __restrict__ rows0,
     const AxisTab* __restrict__ cols0, const float2* __restrict__ tw, const float* __restrict__ apoly,
     const float2* __restrict__ outfac, float2* __restrict__ inter, int Fh) {
