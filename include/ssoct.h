@@ -278,7 +278,8 @@ int ssoct_profile_read(ssoct_plan* plan, float* ms);
  * pixels per workgroup (FFT and factored forms) or workgroups and K chunk
  * (dense form)) on the given
  * inputs with HIP events on the plan's stream (synchronises the stream),
- * keep the fastest of each in the plan and write them to tuning.  Arguments
+ * keep the fastest of each in the plan (the default, tried first, gives way
+ * only to a value faster by more than 1 %) and write them to tuning.  Arguments
  * as for ssoct_plan_render; vol is overwritten.
  * The choice is kept in a process-wide cache keyed by the device's
  * architecture and CU count, T, N, the plan flags (the profiling flags

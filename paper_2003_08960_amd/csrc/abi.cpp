@@ -914,7 +914,9 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
     return SSOCT_OK;
   };
   // Each search keeps the fastest candidate of its own stage (the Fresnel
-  // stage, or the depth transform) before the next search starts.
+  // stage, or the depth transform) before the next search starts; the first
+  // candidate (the default) gives way only to one faster by more than 1 %,
+  // so that run-to-run noise does not pick an alternative of equal speed.
   int rc = SSOCT_OK;
   float a, b;
   auto search = [&](int* knob, const int* cand, int n, bool stage_b) {
@@ -924,7 +926,7 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
       *knob = cand[i];
       rc = measure(&a, &b);
       const float t = stage_b ? b : a;
-      if (rc == SSOCT_OK && t < best) best = t, best_v = cand[i];
+      if (rc == SSOCT_OK && (i == 0 ? t < best : t < 0.99f * best)) best = t, best_v = cand[i];
     }
     *knob = best_v;
   };
@@ -936,17 +938,19 @@ int ssoct_plan_tune(ssoct_plan* p, const uint16_t* frames, const double* lambda,
       rc = measure(&a, &b);
       tot[o] = a + b;
     }
-    p->order = tot[1] < tot[0] ? 1 : 0;
+    p->order = tot[0] < 0.99f * tot[1] ? 0 : 1;   // the default (depth first) unless the frame order is faster
   }
   const bool df = p->depth_first();   // the Fresnel-stage timings below are of that order's 2-D transforms
   // Fresnel stage: frames per chunk x column tile width x persistent column workgroups
   int ct[3];
   col_tiles(p->N, ct);
+  // frames per chunk: the order's default (0) first, then F, F/2, F/4 where they differ from it
   const int Fs[3] = {p->F, p->F / 2, p->F / 4};
-  int nF = 0, Fc[3];
+  p->F_run = 0;
+  const int Fdef = p->frames_run();
+  int nF = 1, Fc[4] = {0, 0, 0, 0};
   for (int i = 0; i < 3; ++i)
-    if (Fs[i] >= 1 && (nF == 0 || Fs[i] != Fc[nF - 1]) && (!df || Fs[i] >= 2)) Fc[nF++] = Fs[i];
-  if (nF == 0) Fc[nF++] = p->F;
+    if (Fs[i] >= 1 && Fs[i] != Fdef && Fs[i] != Fc[nF - 1] && (!df || Fs[i] >= 2)) Fc[nF++] = Fs[i];
   search(&p->F_run, Fc, nF, false);
   if (!(p->flags & SSOCT_ANGULAR_SPECTRUM)) {
     int tiles[3] = {0, ct[1], ct[2]}, nt = 1;

@@ -156,7 +156,7 @@ def test_tuning_changes_speed_not_results(gpu_lib, sweeps, tmp_path):
     V0 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     cache = str(tmp_path / "tuning.json")
     choice = plan.tune(fr, sw.lam, sw.pitch, sw.z, cache_path=cache)
-    assert 1 <= choice[0] <= T and len(choice) == native.TUNING_LEN
+    assert 0 <= choice[0] <= T and len(choice) == native.TUNING_LEN      # 0: the order's default chunk
     V1 = plan.render(fr, sw.lam, sw.pitch, sw.z).clone()
     assert torch.equal(V0, V1)
     for tuning in ([1, 0, 0], [3, 7, 5], [T, 1024, 64]):
