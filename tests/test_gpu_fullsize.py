@@ -76,18 +76,24 @@ def paper():
     return sw, ref
 
 
-@pytest.mark.parametrize("precision,order,bar", [("fp32_fft", None, 1e-5), ("fp32_fft", 0, 1e-5), ("fp32", None, 1e-5),
-                                                 ("bf16_split", None, 1e-4), ("bf16_split_4step", None, 1e-4)])
-def test_paper_volume_every_voxel(gpu_lib, paper, precision, order, bar):
+@pytest.mark.parametrize("precision,order,radix,bar", [("fp32_fft", None, 0, 1e-5), ("fp32_fft", 0, 0, 1e-5),
+                                                       ("fp32", None, 0, 1e-5), ("bf16_split", None, 0, 1e-4),
+                                                       ("bf16_split_4step", None, 0, 1e-4),
+                                                       ("fp32_fft", None, 1, 1e-5), ("bf16_split_4step", None, 1, 1e-4)])
+def test_paper_volume_every_voxel(gpu_lib, paper, precision, order, radix, bar):
     """The whole 1024 x 1024 x 256 volume against the oracle, element by element, in the launch
     configuration the bench times (default chunking, grids and evaluation order: depth first for the
-    FFT form), the FFT form also in the frame order, and the three cuts."""
+    FFT form), the FFT form also in the frame order, the column transforms also in the second radix
+    order (4 16 16, which the tuner may choose), and the three cuts."""
     from paper_2003_08960_amd.api import Plan
     sw, ref = paper
-    print(f"\n[gpu] paper volume, every voxel, {precision} order {order}", flush=True)
+    print(f"\n[gpu] paper volume, every voxel, {precision} order {order} radix order {radix}", flush=True)
     plan = Plan(T, N, precision=precision)
+    t = plan.get_tuning()
     if order is not None:
-        plan.set_tuning(plan.get_tuning()[:3] + [order])
+        t[3] = order
+    t[8] = radix
+    plan.set_tuning(t)
     V = plan.render(torch.from_numpy(sw.frames).cuda(), sw.lam, sw.pitch, sw.z)
     err, err_ac = rel_l2_blocked(V, ref)
     print(f"{precision}: rel-L2 all voxels {err:.3e}, bins q != 0 {err_ac:.3e}")
