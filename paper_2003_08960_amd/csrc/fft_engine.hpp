@@ -270,10 +270,20 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
   constexpr int ls = LS;
   using S = FFTShape<N>;
   constexpr int G = S::G;
+  // Exchange addresses (see lds_slot).  write_slots: base = (j / Ns) 16 Ns +
+  // j mod Ns has base mod 16 = j mod Ns < Ns when Ns < 16 (Ns divides 16, so
+  // k Ns mod 16 <= 16 - Ns), and k Ns mod 16 = 0 otherwise.  read_slots:
+  // j + k G (and the last pass's j + G (i + k 16/L)) with j < G: G >= 16
+  // gives k G mod 16 = 0, and G < 16 (a divisor of 16) gives j < G and
+  // k G mod 16 <= 16 - G.
+  const int sj = lds_slot(j);
   if constexpr (TwPlan<N, TW::PLAN>::SMALL_FIRST) {
     constexpr int L = S::L;
     constexpr int NB = 16 / L;
-    // Ns = 1: output k of butterfly b goes to b L + k
+    // Ns = 1: output k of butterfly b goes to b L + k.  Its address
+    // (j + G i) L + k = L j + (L G i + k): L j mod 16 is a multiple of L, at
+    // most L (G - 1) when L G < 16 (else 16 - L), and L G i mod 16 + k at
+    // most 16 - L G + L - 1 (else L - 1), so the sums stay below 16.
     exchange_sync<WAVE>();  // previous reads of this region are complete
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -282,14 +292,10 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
       for (int k = 0; k < L; ++k) u[k] = v[i + k * NB];
       dft_small<L, DIR>(u);
 #pragma unroll
-      // (j + G i) L + k = L j + (L G i + k): L j mod 16 is a multiple of L, at
-      // most L (G - 1) when L G < 16 (else 16 - L), and L G i mod 16 + k
-      // at most 16 - L G + L - 1 (else L - 1), so the sums stay below 16
       for (int k = 0; k < L; ++k) lds[(lds_slot(L * j) + lds_slot(L * G * i + k)) * ls] = u[k];
     }
     exchange_sync<WAVE>();
     int Ns = L;
-    const int sj = lds_slot(j);
 #pragma unroll
     for (int p = 0; p < S::P16; ++p) {
 #pragma unroll
@@ -309,12 +315,6 @@ __device__ __forceinline__ void fft_group_tw(float2 (&v)[16], int j, float2* lds
     // the last pass has Ns = G: output k of thread j is element j + k G
     return;
   }
-  // write_slots: base = (j / Ns) 16 Ns + j mod Ns has base mod 16 = j mod Ns
-  // < Ns when Ns < 16 (Ns divides 16, so k Ns mod 16 <= 16 - Ns), and k Ns
-  // mod 16 = 0 otherwise.  read_slots: j + k G (and the last pass's
-  // j + G (i + k 16/L)) with j < G: G >= 16 gives k G mod 16 = 0, and G < 16
-  // (a divisor of 16) gives j < G and k G mod 16 <= 16 - G.
-  const int sj = lds_slot(j);
   int Ns = 1;
 #pragma unroll
   for (int p = 0; p < S::P16; ++p) {
