@@ -38,6 +38,25 @@ def test_noalloc_matches_the_workspace_render(gpu_lib):
         plan.close()
 
 
+def test_noalloc_with_the_second_radix_order(gpu_lib):
+    """The allocation-free render follows the plan's launch shapes: with the column transforms in the
+    second radix order (4 16 16 at N = 1024 is 8 16 at N = 128) it equals the ordinary render of the
+    same plan bit for bit."""
+    from paper_2003_08960_amd.api import Plan
+    T, N = 32, 128
+    print(f"\n[gpu] noalloc radix order 1: T={T} N={N} fp32_fft", flush=True)
+    fr, lam = _case(T, N, seed=310)
+    plan = Plan(T, N, precision="fp32_fft")
+    t = plan.get_tuning()
+    t[8] = 1
+    plan.set_tuning(t)
+    ref = plan.render(fr, lam, 12e-6, 0.3)
+    got = plan.render_noalloc(fr, lam, 12e-6, 0.3, out=torch.empty_like(ref))
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    plan.close()
+
+
 def test_noalloc_rejects_a_workspace_beyond_the_array(gpu_lib):
     from paper_2003_08960_amd.api import Plan
     T, N = 256, 1024        # H alone is 2 GiB
